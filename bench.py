@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Forward-render benchmark on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Workload: 1,000,000 Gaussians drawn from 64 anisotropic clusters, SH degree 3,
+one 1920x1080 pinhole camera, 16x16 tiles.  One step renders that frame once
+with each transmittance model (exponential, linear, quadratic sublinear,
+quadratic superlinear): the whole path (projection, depth sort, binning, tile
+sort, gather, composite) runs for every render.  The scene is uploaded to HBM
+before the timed region.
+
+Prints one JSON line: aggregate Mpix/s over all renders, per-model Mpix/s,
+splats blended per second (sum of per-pixel overdraw / time), mean overdraw,
+p50/p99 render latency, per-stage GPU times (hipEvents recorded by the
+library on the render stream), the roofline of the dominant kernel, and the
+CPU oracle timed on a bounded pixel sample of the same frame.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+MODELS = ("exponential", "linear", "sublinear", "superlinear")
+METRIC = "Mpix/s + splats blended/s per transmittance model; p50/p99 render latency"
+
+# FP32 VALU work of one composited (pixel, splat) pair, counting an FMA as 2
+# flops and the exp2 as 1: offset 2, exponent 8, exp2 1, accumulate 6, plus
+# the operator (exponential 3, linear 1, quadratic 5).
+FLOPS_PER_PAIR = {0: 20, 1: 18, 2: 22, 3: 22}
+# 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz, non-packed FP32
+FP32_VALU_PEAK_TFLOPS = 78.6432
+HBM_PEAK_GBS = 8000.0
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(scene, cam, n_pixels, seed=123):
+    """Time the CPU oracle on a random pixel sample of the frame, per model,
+    and extrapolate to the full frame (setup + per-pixel time x pixels)."""
+    from oracle import render as orender
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(cam.width * cam.height, n_pixels, replace=False)
+    pix = np.stack([flat % cam.width, flat // cam.width], 1)
+    one = pix[:1]
+    frame_s = []
+    t_all = time.perf_counter()
+    for m in range(4):
+        t0 = time.perf_counter()
+        orender.render(scene, cam, m, pixels=one)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        orender.render(scene, cam, m, pixels=pix)
+        t_s = time.perf_counter() - t0
+        per_px = max(t_s - t_setup, 0.0) / n_pixels
+        frame_s.append(t_setup + per_px * cam.width * cam.height)
+    spent = time.perf_counter() - t_all
+    mpix = 4 * cam.width * cam.height / sum(frame_s) / 1e6
+    return {"value": mpix, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{n_pixels} random pixels of the 1920x1080 frame per model "
+                       f"(4 models) plus one 1-pixel call per model for the setup "
+                       f"(projection, key replay, pruning lists); full-frame time = "
+                       f"setup + sample time x W*H/{n_pixels}; {spent:.1f} s of CPU"),
+            "frame_seconds": {MODELS[m]: frame_s[m] for m in range(4)}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[1])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--lds-batch", type=int, default=256)
+    ap.add_argument("--cpu-pixels", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(views and requests shard across GPUs with no exchange in the forward "
+              "pass, so the multi-GPU figure is the single-GPU one times N)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2603_02887_amd import nxs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    scene, cams = synth.scene_scale()
+    cam = cams[0]
+    W, H = cam.width, cam.height
+    dev = torch.device("cuda", 0)
+    g = nxs.scene_to_device(scene, dev)
+    R = nxs.Renderer(0)
+    outs = {m: R.render(g, [cam], model=m, tile=(tw, th), lds_batch=args.lds_batch)
+            for m in range(4)}
+    torch.cuda.synchronize()
+    od_sum = {m: int(outs[m][0]["overdraw"].sum().item()) for m in range(4)}
+    n_inst, _ = R.counts()
+
+    def step(record):
+        for m in range(4):
+            t0 = time.perf_counter()
+            R.render(g, [cam], model=m, tile=(tw, th), lds_batch=args.lds_batch,
+                     outputs=outs[m])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if record is not None:
+                record["lat"][m].append(t1 - t0)
+                record["stages"][m].append(R.stage_times())
+
+    for _ in range(args.warmup):
+        step(None)
+    R.set_timing(True)
+    rec = {"lat": {m: [] for m in range(4)}, "stages": {m: [] for m in range(4)}}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    R.set_timing(False)
+
+    per_model = {}
+    stage_mean = {}
+    for m in range(4):
+        lat = rec["lat"][m]
+        st = {k: float(np.mean([s[k] for s in rec["stages"][m]])) for k in R.STAGES}
+        stage_mean[m] = st
+        t_m = sum(lat)
+        per_model[MODELS[m]] = {
+            "mpix_per_s": W * H * len(lat) / t_m / 1e6,
+            "splats_blended_per_s": od_sum[m] * len(lat) / t_m,
+            "avg_overdraw": od_sum[m] / (W * H),
+            "p50_ms": percentile(lat, 50) * 1e3,
+            "p99_ms": percentile(lat, 99) * 1e3,
+            "stages_ms": st,
+            "gpu_ms": sum(st.values()),
+        }
+    # dominant kernel: the composite of the exponential model (largest stage)
+    all_stage = {(m, k): stage_mean[m][k] for m in range(4) for k in R.STAGES}
+    (dm, dk), dms = max(all_stage.items(), key=lambda kv: kv[1])
+    if dk == "composite":
+        flops = od_sum[dm] * FLOPS_PER_PAIR[dm]
+        achieved = flops / (dms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": f"composite<{MODELS[dm]}>",
+                    "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
+                    "traffic": None,
+                    "work_per_launch": {"composited_pairs": od_sum[dm],
+                                        "flops_per_pair": FLOPS_PER_PAIR[dm]},
+                    "avg_launch_ms": dms}
+    else:
+        roofline = {"bound": "hbm", "kernel": dk, "avg_launch_ms": dms, "achieved": None,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}
+
+    renders = 4 * args.steps
+    value = W * H * renders / total / 1e6
+    exp_ms = per_model["exponential"]["p50_ms"]
+    for name in MODELS[1:]:
+        per_model[name]["speedup_vs_exponential"] = exp_ms / per_model[name]["p50_ms"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, cam, args.cpu_pixels)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "Mpix/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": ("scene-scale forward: 1,000,000 Gaussians from 64 "
+                                "anisotropic clusters, SH degree 3, one 1920x1080 camera; "
+                                "one step = one render per transmittance model"),
+                   "gaussians": scene.n, "width": W, "height": H,
+                   "tile": f"{tw}x{th}", "lds_batch": args.lds_batch,
+                   "instances": n_inst, "models": list(MODELS)},
+        "per_model": per_model,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    R.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * nxs.h -- C ABI of the non-exponential Gaussian splatting renderer for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library renders images of 3D Gaussians by compositing them front to
+ * back with a pluggable transmittance operator: the generalized image
+ * formation of Sec. 4 of "Generalized non-exponential Gaussian splatting"
+ * (eq. generalized_gaussian with the discrete extinction of eq. nexp_p and
+ * the operators of Table 1).  Each call runs, on the caller's HIP stream:
+ * EWA projection, depth sort, tile binning, a stable tile sort, a gather of
+ * each tile's splats into contiguous order, and a per-tile composite.
+ *
+ * Conventions common to every entry point
+ *   - Array pointers are DEVICE pointers of the context's device, unless the
+ *     argument says "host".  Structs passed by pointer are HOST memory, read
+ *     during the call only.
+ *   - The caller owns every input and output buffer.  Inputs must stay
+ *     unmodified and alive until the stream has passed the call's work.
+ *     Outputs are fully overwritten; they need no clearing.
+ *   - The context owns its workspace (device memory grown on demand with
+ *     hipMalloc and kept until nxs_destroy) and a small pinned host buffer.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     nxs_render_forward synchronises that stream once, after projection,
+ *     to read the number of tile instances and size the workspace; it
+ *     returns once the remaining work is enqueued.
+ *   - No exception crosses the ABI.  Every call returns an nxs_status; for
+ *     a non-OK status nxs_last_error() gives a message.  Arguments are
+ *     checked before any launch, so NXS_EINVAL leaves outputs untouched.
+ *   - A context is used by one host thread at a time.  Calls on the same
+ *     context are serialised by the caller; they may use different streams.
+ */
+#ifndef NXS_H
+#define NXS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NXS_OK = 0,
+  NXS_EINVAL = -1,       /* bad argument; nothing was launched */
+  NXS_ENOMEM = -2,       /* workspace allocation failed */
+  NXS_EHIP = -3,         /* a HIP runtime call failed; see nxs_last_error */
+  NXS_ECAPACITY = -4,    /* instance count exceeds the 32-bit index range */
+  NXS_EUNSUPPORTED = -5  /* feature not available in this build */
+} nxs_status;
+
+/* Transmittance models (Table 1 and Sec. 5 of the paper).
+ *   EXPONENTIAL       T = exp(-tau):  p_i = a_i prod_{j<i} (1 - a_j)  (classic 3DGS)
+ *   LINEAR            T = [1 - tau]_+:  p_i = a_i
+ *   QUAD_SUBLINEAR    T = [1 - tau - c tau^2 / 2]_+ with c = -0.5: p_i = a_i (1 + c tau_i)
+ *   QUAD_SUPERLINEAR  the same with c = +0.5
+ * For every model the splat whose p would take sum p to >= 1 gets the remainder
+ * 1 - sum_{j<k} p_j, the transmittance becomes exactly 0 and compositing stops
+ * (eq. nexp_p). */
+typedef enum {
+  NXS_EXPONENTIAL = 0,
+  NXS_LINEAR = 1,
+  NXS_QUAD_SUBLINEAR = 2,
+  NXS_QUAD_SUPERLINEAR = 3
+} nxs_model;
+
+/* Gaussians (Sec. 3: centre, covariance, opacity aleph, directional emission).
+ *   means      [n,3]  world-space centres
+ *   scales     [n,3]  per-axis standard deviations (> 0)
+ *   quats      [n,4]  rotation as (w, x, y, z), normalised by the library;
+ *                     an all-zero quaternion culls that Gaussian
+ *   opacities  [n]    aleph in [0, 1] (values above 1 make the tile
+ *                     bounds non-conservative)
+ *   sh         [n, (sh_degree+1)^2, 3]  real SH coefficients per channel,
+ *                     index l*l + l + m; colour = max(0, sum c_lm Y_lm(d) + 1/2)
+ *                     with d the unit vector camera centre -> mean
+ * All float32, C-contiguous. */
+typedef struct {
+  int32_t n;
+  int32_t sh_degree; /* 0..3 */
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacities;
+  const float* sh;
+} nxs_gaussians;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).
+ * p_cam = R p_world + t with R row-major; pixel (x, y) is sampled at its
+ * centre (x + 1/2, y + 1/2); u = fx x/z + cx, v = fy y/z + cy.
+ * Gaussians with camera-space z <= znear are culled. */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float znear;
+  int32_t width, height;
+} nxs_camera;
+
+/* Render options.  Zero-initialised fields take the defaults noted. */
+typedef struct {
+  int32_t model;          /* nxs_model */
+  float background[3];    /* L_b of eq. generalized_gaussian (default 0) */
+  float alpha_min;        /* splats with alpha < alpha_min are skipped;
+                             0 -> 1e-3 */
+  float t_eps;            /* exponential only: stop after the first splat that
+                             leaves T < t_eps; 0 -> 1e-4, < 0 -> never */
+  int32_t tile_w, tile_h; /* 8x8, 16x16 or 32x8; 0 -> 16x16 */
+  int32_t lds_batch;      /* splats staged in LDS per batch: 0, 128, 256, 512
+                             (0 -> 256) */
+} nxs_render_opts;
+
+/* Per-view outputs (device pointers), row-major:
+ *   rgb       [H, W, 3] float32   pixel value L0
+ *   trans     [H, W]    float32   final transmittance T_{N+1}
+ *   overdraw  [H, W]    int32     composited splats (terminating one included);
+ *                                 may be NULL */
+typedef struct {
+  float* rgb;
+  float* trans;
+  int32_t* overdraw;
+} nxs_image;
+
+typedef struct nxs_context nxs_context;
+
+/* Creates a context on HIP device `device`.  *ctx receives the handle. */
+nxs_status nxs_create(nxs_context** ctx, int device);
+
+/* Frees the workspace (waiting for the device first) and the context. */
+nxs_status nxs_destroy(nxs_context* ctx);
+
+/* Renders n_views >= 1 views of the same Gaussians.
+ *   cams [n_views] host array; out [n_views] host array of device outputs.
+ * Views may differ in size; all share opts.  n = 0 renders background. */
+nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
+                              const nxs_camera* cams, int32_t n_views,
+                              const nxs_render_opts* opts, const nxs_image* out,
+                              void* stream);
+
+/* Message for the last non-OK status returned on this context ("" if none).
+ * The pointer stays valid until the next call on the context. */
+const char* nxs_last_error(const nxs_context* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Inspection of the last nxs_render_forward on a context (for testing).
+ * Each call synchronises the stream of that render and copies into HOST
+ * buffers the caller provides.
+ * ------------------------------------------------------------------------- */
+
+/* Per-stage GPU timing.  With timing enabled, each render records hipEvents
+ * on its stream between its stages; nxs_inspect_stage_times then returns the
+ * milliseconds of the last render's stages, in this order:
+ *   0 projection, 1 depth sort, 2 instance emission, 3 tile sort,
+ *   4 tile ranges + gather, 5 composite.
+ * ms_host has n >= NXS_N_STAGES entries.  Waits for the last render. */
+#define NXS_N_STAGES 6
+nxs_status nxs_set_timing(nxs_context* ctx, int32_t enable);
+nxs_status nxs_inspect_stage_times(nxs_context* ctx, float* ms_host, int32_t n);
+
+/* Number of tile instances M and of global tiles of the last render. */
+nxs_status nxs_inspect_counts(nxs_context* ctx, int64_t* n_instances,
+                              int64_t* n_tiles);
+
+/* The sorted instance list: for instance j, keys_host[j] =
+ * (global_tile << 32) | float32 bits of the Gaussian's camera-space depth,
+ * ids_host[j] = Gaussian index; sorted by key, then index.  Global tile =
+ * first tile of the view + ty * tiles_x + tx.  `capacity` is the length of
+ * both host arrays; NXS_EINVAL if it is below the instance count. */
+nxs_status nxs_inspect_instances(nxs_context* ctx, uint64_t* keys_host,
+                                 int32_t* ids_host, int64_t capacity);
+
+/* Per global tile [start, end) into the sorted list: ranges_host[2*t], [2*t+1]. */
+nxs_status nxs_inspect_ranges(nxs_context* ctx, int32_t* ranges_host,
+                              int64_t capacity);
+
+/* Per Gaussian of view `view`: float32 depth bits (0 if culled) and the
+ * covered tile rectangle (tx0, tx1, ty0, ty1) inclusive, or all -1 if culled.
+ * depth_bits_host [n], rect_host [n*4]. */
+nxs_status nxs_inspect_projection(nxs_context* ctx, int32_t view,
+                                  uint32_t* depth_bits_host, int32_t* rect_host,
+                                  int64_t capacity);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NXS_H */

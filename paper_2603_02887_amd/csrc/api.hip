@@ -1,0 +1,417 @@
+// Host side of the C ABI declared in include/nxs.h: argument checks,
+// workspace management and the launch sequence of one forward render.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nxs.h"
+#include "nxs_internal.h"
+
+using namespace nxs;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct nxs_context {
+  int device = 0;
+  std::string err;
+  // workspace
+  DevBuf views, counters;
+  DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, ntiles, rect, uv, geoA, geoB;
+  DevBuf scan_local, block_sums, counts;
+  DevBuf inst_tile, inst_tile_alt, inst_val, inst_val_alt;
+  DevBuf rec0, rec1, rec2, ranges;
+  Counters* host_counters = nullptr;  // pinned
+  ViewDev* host_views = nullptr;      // pinned
+  int host_views_cap = 0;
+  hipEvent_t done = nullptr;           // recorded at the end of each render
+  bool has_done = false;
+  // optional per-stage timing (hipEvents on the render's stream)
+  bool timing = false;
+  hipEvent_t ev[8] = {};
+  bool ev_valid = false;
+  // state of the last render, for inspection
+  int64_t last_m = 0, last_tiles = 0, last_slots = 0;
+  int32_t last_n = 0, last_views = 0;
+  uint32_t* last_inst_tile = nullptr;
+  uint32_t* last_inst_val = nullptr;
+};
+
+namespace {
+
+nxs_status fail(nxs_context* ctx, nxs_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ctx, NXS_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+nxs_status ensure(nxs_context* ctx, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return NXS_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);  // hipFree waits for outstanding work on the device
+    b.p = nullptr;
+    b.cap = 0;
+    if (e != hipSuccess) return fail(ctx, NXS_EHIP, "hipFree: %s", hipGetErrorString(e));
+  }
+  size_t want = bytes + bytes / 4;
+  want = (want + 255) & ~(size_t)255;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(ctx, NXS_ENOMEM, "hipMalloc(%zu bytes) failed", want);
+  }
+  b.cap = want;
+  return NXS_OK;
+}
+
+int bit_length(uint64_t x) {
+  int b = 0;
+  while (x) {
+    ++b;
+    x >>= 1;
+  }
+  return b;
+}
+
+template <typename T>
+T* P(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+}  // namespace
+
+extern "C" {
+
+nxs_status nxs_create(nxs_context** out, int device) {
+  if (!out) return NXS_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return NXS_EINVAL;
+  nxs_context* ctx = new (std::nothrow) nxs_context();
+  if (!ctx) return NXS_ENOMEM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->host_counters, sizeof(Counters), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess) {
+    if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+    delete ctx;
+    return NXS_EHIP;
+  }
+  *out = ctx;
+  return NXS_OK;
+}
+
+nxs_status nxs_destroy(nxs_context* ctx) {
+  if (!ctx) return NXS_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* all[] = {&ctx->views,      &ctx->counters,      &ctx->depth_key, &ctx->dsort_a, &ctx->dsort_b,
+                   &ctx->slot_a,     &ctx->slot_b,        &ctx->ntiles,    &ctx->rect,
+                   &ctx->uv,         &ctx->geoA,          &ctx->geoB,      &ctx->scan_local,
+                   &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
+                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->rec0,      &ctx->rec1,
+                   &ctx->rec2,       &ctx->ranges};
+  for (DevBuf* b : all)
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+  if (ctx->host_views) (void)hipHostFree(ctx->host_views);
+  if (ctx->done) (void)hipEventDestroy(ctx->done);
+  for (int k = 0; k < 8; ++k)
+    if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
+  delete ctx;
+  return NXS_OK;
+}
+
+const char* nxs_last_error(const nxs_context* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
+                              const nxs_camera* cams, int32_t n_views,
+                              const nxs_render_opts* opts, const nxs_image* out,
+                              void* stream) {
+  if (!ctx) return NXS_EINVAL;
+  ctx->err.clear();
+  if (!g || !cams || !opts || !out) return fail(ctx, NXS_EINVAL, "null argument");
+  if (n_views < 1) return fail(ctx, NXS_EINVAL, "n_views must be >= 1");
+  if (g->n < 0) return fail(ctx, NXS_EINVAL, "n must be >= 0");
+  if (g->sh_degree < 0 || g->sh_degree > 3)
+    return fail(ctx, NXS_EINVAL, "sh_degree must be 0..3");
+  if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh))
+    return fail(ctx, NXS_EINVAL, "null Gaussian array");
+  if (opts->model < 0 || opts->model > 3) return fail(ctx, NXS_EINVAL, "unknown model %d", opts->model);
+  int tw = opts->tile_w ? opts->tile_w : 16, th = opts->tile_h ? opts->tile_h : 16;
+  if (!((tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 8)))
+    return fail(ctx, NXS_EINVAL, "tile size %dx%d not supported (8x8, 16x16, 32x8)", tw, th);
+  int batch = opts->lds_batch ? opts->lds_batch : 256;
+  if (batch != 128 && batch != 256 && batch != 512)
+    return fail(ctx, NXS_EINVAL, "lds_batch must be 0, 128, 256 or 512");
+  float alpha_min = opts->alpha_min > 0.0f ? opts->alpha_min : 1e-3f;
+  if (!(alpha_min < 1.0f)) return fail(ctx, NXS_EINVAL, "alpha_min must be in (0, 1)");
+  float t_eps = opts->t_eps == 0.0f ? 1e-4f : opts->t_eps;
+  int64_t total_tiles = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const nxs_camera& c = cams[v];
+    if (c.width <= 0 || c.height <= 0 || c.width > 32768 || c.height > 32768)
+      return fail(ctx, NXS_EINVAL, "view %d: bad size %dx%d", v, c.width, c.height);
+    if (!out[v].rgb || !out[v].trans) return fail(ctx, NXS_EINVAL, "view %d: null output", v);
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f)) return fail(ctx, NXS_EINVAL, "view %d: bad focal", v);
+    total_tiles += (int64_t)((c.width + tw - 1) / tw) * ((c.height + th - 1) / th);
+  }
+  if (total_tiles >= (int64_t)1 << 31) return fail(ctx, NXS_EINVAL, "too many tiles");
+  const int64_t n = g->n;
+  const int64_t S = n * n_views;
+  if (S >= ((int64_t)1 << 32) - 1) return fail(ctx, NXS_EINVAL, "n * n_views too large");
+
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  // the workspace is shared by all calls on this context: order after the last one
+  if (ctx->has_done) HIP_TRY(hipStreamWaitEvent(s, ctx->done, 0));
+
+  // ---- view table -----------------------------------------------------------
+  if (ctx->host_views_cap < n_views) {
+    if (ctx->host_views) (void)hipHostFree(ctx->host_views);
+    ctx->host_views = nullptr;
+    ctx->host_views_cap = 0;
+    HIP_TRY(hipHostMalloc((void**)&ctx->host_views, sizeof(ViewDev) * n_views,
+                          hipHostMallocDefault));
+    ctx->host_views_cap = n_views;
+  }
+  // (the previous call's copy out of host_views finished before it returned:
+  // it synchronised its stream after the projection)
+  int64_t off = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const nxs_camera& c = cams[v];
+    ViewDev& d = ctx->host_views[v];
+    std::memset(&d, 0, sizeof(d));
+    std::memcpy(d.R, c.R, sizeof(d.R));
+    std::memcpy(d.t, c.t, sizeof(d.t));
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy; d.znear = c.znear;
+    for (int k = 0; k < 3; ++k)
+      d.campos[k] = (float)-((double)c.R[k] * c.t[0] + (double)c.R[3 + k] * c.t[1] +
+                             (double)c.R[6 + k] * c.t[2]);
+    d.width = c.width; d.height = c.height;
+    d.tiles_x = (c.width + tw - 1) / tw;
+    d.tiles_y = (c.height + th - 1) / th;
+    d.tile_off = (int32_t)off;
+    off += (int64_t)d.tiles_x * d.tiles_y;
+    d.rgb = out[v].rgb; d.trans = out[v].trans; d.od = out[v].overdraw;
+  }
+  nxs_status st;
+  if ((st = ensure(ctx, ctx->views, sizeof(ViewDev) * n_views))) return st;
+  if ((st = ensure(ctx, ctx->counters, sizeof(Counters)))) return st;
+  HIP_TRY(hipMemcpyAsync(ctx->views.p, ctx->host_views, sizeof(ViewDev) * n_views,
+                         hipMemcpyHostToDevice, s));
+  const ViewDev* dviews = P<ViewDev>(ctx->views);
+
+  // ---- per-slot buffers and projection ----------------------------------------
+  if ((st = ensure(ctx, ctx->depth_key, 4 * S)) || (st = ensure(ctx, ctx->dsort_a, 4 * S)) ||
+      (st = ensure(ctx, ctx->dsort_b, 4 * S)) ||
+      (st = ensure(ctx, ctx->slot_a, 4 * S)) || (st = ensure(ctx, ctx->slot_b, 4 * S)) ||
+      (st = ensure(ctx, ctx->ntiles, 4 * S)) || (st = ensure(ctx, ctx->rect, 8 * S)) ||
+      (st = ensure(ctx, ctx->uv, 16 * S)) || (st = ensure(ctx, ctx->geoA, 16 * S)) ||
+      (st = ensure(ctx, ctx->geoB, 16 * S)) || (st = ensure(ctx, ctx->scan_local, 4 * S)) ||
+      (st = ensure(ctx, ctx->block_sums, 4 * scan_blocks_size(S))))
+    return st;
+  ProjDev proj{P<uint32_t>(ctx->depth_key), P<uint32_t>(ctx->ntiles), P<uint2>(ctx->rect),
+               P<double2>(ctx->uv), P<float4>(ctx->geoA), P<float4>(ctx->geoB)};
+  GaussDev gd{g->means, g->scales, g->quats, g->opacities, g->sh, g->n, g->sh_degree};
+  Counters* dcount = P<Counters>(ctx->counters);
+  const float kappa2 = (float)(2.0 * std::log(1.0 / (double)alpha_min));
+  auto mark = [&](int k) -> hipError_t {
+    return ctx->timing ? hipEventRecord(ctx->ev[k], s) : hipSuccess;
+  };
+  ctx->ev_valid = false;
+  HIP_TRY(mark(0));
+  launch_init_counters(dcount, s);
+  launch_project(gd, dviews, n_views, kappa2, alpha_min, tw, th, proj, dcount, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(mark(1));
+  HIP_TRY(hipMemcpyAsync(ctx->host_counters, dcount, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const uint64_t M = ctx->host_counters->total;
+  if (M >= 0xFFFFFFFFull)
+    return fail(ctx, NXS_ECAPACITY, "%llu tile instances exceed the 32-bit range",
+                (unsigned long long)M);
+
+  // ---- instance buffers ---------------------------------------------------------
+  const int64_t sort_n = std::max<int64_t>(S, (int64_t)M);
+  if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_size(sort_n))) ||
+      (st = ensure(ctx, ctx->inst_tile, 4 * M)) || (st = ensure(ctx, ctx->inst_tile_alt, 4 * M)) ||
+      (st = ensure(ctx, ctx->inst_val, 4 * M)) || (st = ensure(ctx, ctx->inst_val_alt, 4 * M)) ||
+      (st = ensure(ctx, ctx->rec0, 16 * M)) || (st = ensure(ctx, ctx->rec1, 16 * M)) ||
+      (st = ensure(ctx, ctx->rec2, 4 * M)) || (st = ensure(ctx, ctx->ranges, 8 * total_tiles)))
+    return st;
+
+  uint32_t* inst_tile = P<uint32_t>(ctx->inst_tile);
+  uint32_t* inst_val = P<uint32_t>(ctx->inst_val);
+  HIP_TRY(mark(2));
+  launch_fill_u32(P<uint32_t>(ctx->ranges), 2 * total_tiles, 0u, s);
+  if (M > 0) {
+    // 1. depth sort of the slots on the bits that vary among visible ones
+    const uint32_t dmin = ctx->host_counters->dmin, dmax = ctx->host_counters->dmax;
+    const int dbits = bit_length(dmin ^ dmax);
+    uint32_t* ka = P<uint32_t>(ctx->dsort_a);
+    uint32_t* kb = P<uint32_t>(ctx->dsort_b);
+    uint32_t* slots = P<uint32_t>(ctx->slot_a);
+    uint32_t* slots_alt = P<uint32_t>(ctx->slot_b);
+    // values are the slots 0..S-1; the sort permutes a copy of the depth keys
+    launch_iota_copy(P<uint32_t>(ctx->depth_key), ka, slots, S, s);
+    int where = radix_sort_pairs(ka, slots, kb, slots_alt, S, dbits,
+                                 P<uint32_t>(ctx->counts), s);
+    uint32_t* sorted_slots = where ? slots_alt : slots;
+    HIP_TRY(mark(3));
+    // 2. emission in depth order
+    launch_emit(sorted_slots, S, g->n, proj, dviews, P<uint32_t>(ctx->scan_local),
+                P<uint32_t>(ctx->block_sums), inst_tile, inst_val, s);
+    HIP_TRY(mark(4));
+    // 3. stable sort by global tile
+    const int tbits = bit_length((uint64_t)(total_tiles - 1));
+    int w2 = radix_sort_pairs(inst_tile, inst_val, P<uint32_t>(ctx->inst_tile_alt),
+                              P<uint32_t>(ctx->inst_val_alt), (int64_t)M, tbits,
+                              P<uint32_t>(ctx->counts), s);
+    if (w2) {
+      inst_tile = P<uint32_t>(ctx->inst_tile_alt);
+      inst_val = P<uint32_t>(ctx->inst_val_alt);
+    }
+    HIP_TRY(mark(5));
+    // 4. ranges and gather
+    launch_ranges_gather(inst_tile, inst_val, (int64_t)M, proj, dviews, n_views, tw, th,
+                         P<uint2>(ctx->ranges), P<float4>(ctx->rec0), P<float4>(ctx->rec1),
+                         P<float>(ctx->rec2), s);
+  } else {
+    for (int k = 3; k <= 5; ++k) HIP_TRY(mark(k));
+  }
+  HIP_TRY(mark(6));
+  // 5. composite (also writes the background where no splat lands)
+  CompositeParams cp;
+  cp.log2_alpha_min = (float)std::log2((double)alpha_min);
+  cp.t_eps = opts->model == 0 ? t_eps : 0.0f;
+  for (int k = 0; k < 3; ++k) cp.bg[k] = opts->background[k];
+  cp.lds_batch = batch;
+  launch_composite(opts->model, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),
+                   P<float4>(ctx->rec0), P<float4>(ctx->rec1), P<float>(ctx->rec2), cp, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(mark(7));
+  HIP_TRY(hipEventRecord(ctx->done, s));
+  ctx->has_done = true;
+  ctx->ev_valid = ctx->timing;
+
+  ctx->last_m = (int64_t)M;
+  ctx->last_tiles = total_tiles;
+  ctx->last_slots = S;
+  ctx->last_n = g->n;
+  ctx->last_views = n_views;
+  ctx->last_inst_tile = inst_tile;
+  ctx->last_inst_val = inst_val;
+  return NXS_OK;
+}
+
+nxs_status nxs_set_timing(nxs_context* ctx, int32_t enable) {
+  if (!ctx) return NXS_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (enable && !ctx->ev[0])
+    for (int k = 0; k < 8; ++k) HIP_TRY(hipEventCreate(&ctx->ev[k]));
+  ctx->timing = enable != 0;
+  ctx->ev_valid = false;
+  return NXS_OK;
+}
+
+nxs_status nxs_inspect_stage_times(nxs_context* ctx, float* ms_host, int32_t n) {
+  if (!ctx || !ms_host || n < NXS_N_STAGES) return NXS_EINVAL;
+  if (!ctx->ev_valid) return fail(ctx, NXS_EINVAL, "no timed render on this context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipEventSynchronize(ctx->ev[7]));
+  // project, depth sort (incl. ranges clear), emit, tile sort, gather, composite
+  const int from[NXS_N_STAGES] = {0, 2, 3, 4, 5, 6};
+  const int to[NXS_N_STAGES] = {1, 3, 4, 5, 6, 7};
+  for (int k = 0; k < NXS_N_STAGES; ++k)
+    HIP_TRY(hipEventElapsedTime(&ms_host[k], ctx->ev[from[k]], ctx->ev[to[k]]));
+  return NXS_OK;
+}
+
+nxs_status nxs_inspect_counts(nxs_context* ctx, int64_t* n_instances, int64_t* n_tiles) {
+  if (!ctx || !n_instances || !n_tiles) return NXS_EINVAL;
+  *n_instances = ctx->last_m;
+  *n_tiles = ctx->last_tiles;
+  return NXS_OK;
+}
+
+nxs_status nxs_inspect_instances(nxs_context* ctx, uint64_t* keys_host, int32_t* ids_host,
+                                 int64_t capacity) {
+  if (!ctx || (!keys_host && ctx->last_m) || (!ids_host && ctx->last_m))
+    return NXS_EINVAL;
+  if (capacity < ctx->last_m) return fail(ctx, NXS_EINVAL, "capacity below instance count");
+  if (ctx->last_m == 0) return NXS_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipEventSynchronize(ctx->done));
+  std::vector<uint32_t> tile(ctx->last_m), val(ctx->last_m), dk(ctx->last_slots);
+  HIP_TRY(hipMemcpy(tile.data(), ctx->last_inst_tile, 4 * ctx->last_m, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(val.data(), ctx->last_inst_val, 4 * ctx->last_m, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(dk.data(), ctx->depth_key.p, 4 * ctx->last_slots, hipMemcpyDeviceToHost));
+  for (int64_t j = 0; j < ctx->last_m; ++j) {
+    keys_host[j] = ((uint64_t)tile[j] << 32) | dk[val[j]];
+    ids_host[j] = (int32_t)(val[j] % (uint32_t)ctx->last_n);
+  }
+  return NXS_OK;
+}
+
+nxs_status nxs_inspect_ranges(nxs_context* ctx, int32_t* ranges_host, int64_t capacity) {
+  if (!ctx || !ranges_host) return NXS_EINVAL;
+  if (capacity < 2 * ctx->last_tiles) return fail(ctx, NXS_EINVAL, "capacity below 2 * tiles");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipEventSynchronize(ctx->done));
+  HIP_TRY(hipMemcpy(ranges_host, ctx->ranges.p, 8 * ctx->last_tiles, hipMemcpyDeviceToHost));
+  return NXS_OK;
+}
+
+nxs_status nxs_inspect_projection(nxs_context* ctx, int32_t view, uint32_t* depth_bits_host,
+                                  int32_t* rect_host, int64_t capacity) {
+  if (!ctx || !depth_bits_host || !rect_host) return NXS_EINVAL;
+  if (view < 0 || view >= ctx->last_views) return fail(ctx, NXS_EINVAL, "bad view");
+  const int64_t n = ctx->last_n;
+  if (capacity < n) return fail(ctx, NXS_EINVAL, "capacity below n");
+  if (n == 0) return NXS_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipEventSynchronize(ctx->done));
+  std::vector<uint2> rect(n);
+  HIP_TRY(hipMemcpy(depth_bits_host, (uint32_t*)ctx->depth_key.p + view * n, 4 * n,
+                    hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(rect.data(), (uint2*)ctx->rect.p + view * n, 8 * n, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i) {
+    if (rect[i].x == 0xFFFFFFFFu) {
+      depth_bits_host[i] = 0;
+      for (int k = 0; k < 4; ++k) rect_host[4 * i + k] = -1;
+    } else {
+      rect_host[4 * i + 0] = (int32_t)(rect[i].x & 0xFFFF);
+      rect_host[4 * i + 1] = (int32_t)(rect[i].x >> 16);
+      rect_host[4 * i + 2] = (int32_t)(rect[i].y & 0xFFFF);
+      rect_host[4 * i + 3] = (int32_t)(rect[i].y >> 16);
+    }
+  }
+  return NXS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal declarations shared by the HIP translation units of libnxs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nxs {
+
+// Per-view parameters, one entry per view in a device table.
+struct ViewDev {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy, znear;
+  float campos[3];          // camera centre in world space, -R^T t
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_off;         // first global tile of this view
+  int32_t pad_;
+  float* rgb;               // [H, W, 3]
+  float* trans;             // [H, W]
+  int32_t* od;              // [H, W] or null
+};
+
+struct GaussDev {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  int32_t n;
+  int32_t sh_degree;
+};
+
+// Per projected slot (slot = view * n + gaussian) arrays written by the projection.
+struct ProjDev {
+  uint32_t* depth_key;      // float32 depth bits; 0xFFFFFFFF when culled
+  uint32_t* ntiles;         // covered tiles, 0 when culled
+  uint2* rect;              // (tx0 | tx1 << 16, ty0 | ty1 << 16)
+  double2* uv;              // image-plane centre, FP64
+  float4* geoA;             // A', B', C', log2(opacity): exponent coefficients
+  float4* geoB;             // r, g, b, 0
+};
+
+// Device counters filled by the projection: total instances, depth-bit range.
+struct Counters {
+  unsigned long long total;
+  uint32_t dmin, dmax;
+};
+
+// ---- launchers (all enqueue on `s`) ------------------------------------------
+void launch_init_counters(Counters* c, hipStream_t s);
+void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
+                    float kappa2, float alpha_min, int tile_w, int tile_h,
+                    const ProjDev& out, Counters* counters, hipStream_t s);
+
+// Stable LSD radix sort of (u32 key, u32 value) pairs on key bits [0, nbits).
+// Returns 0 if the result is in (keys, vals), 1 if in (keys_alt, vals_alt).
+// `counts` needs radix_counts_size(n) u32 entries.
+size_t radix_counts_size(int64_t n);
+int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                     uint32_t* vals_alt, int64_t n, int nbits, uint32_t* counts,
+                     hipStream_t s);
+
+// Exclusive scan of ntiles in sorted-slot order and emission of instances.
+size_t scan_blocks_size(int64_t n);
+void launch_emit(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
+                 const ProjDev& proj, const ViewDev* views, uint32_t* scan_local,
+                 uint32_t* block_sums, uint32_t* inst_tile, uint32_t* inst_val,
+                 hipStream_t s);
+
+// dst[i] = src[i], idx[i] = i.
+void launch_iota_copy(const uint32_t* src, uint32_t* dst, uint32_t* idx, int64_t n,
+                      hipStream_t s);
+
+// Tile ranges and gather of the composite records in sorted order.
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s);
+void launch_ranges_gather(const uint32_t* inst_tile, const uint32_t* inst_val,
+                          int64_t m, const ProjDev& proj, const ViewDev* views,
+                          int n_views, int tile_w, int tile_h, uint2* ranges,
+                          float4* rec0, float4* rec1, float* rec2, hipStream_t s);
+
+struct CompositeParams {
+  float log2_alpha_min;
+  float t_eps;              // exponential termination threshold (<= 0: never)
+  float bg[3];
+  int32_t lds_batch;
+};
+void launch_composite(int model, int tile_w, int tile_h, int64_t n_tiles,
+                      const ViewDev* views, int n_views, const uint2* ranges,
+                      const float4* rec0, const float4* rec1, const float* rec2,
+                      const CompositeParams& p, hipStream_t s);
+
+}  // namespace nxs

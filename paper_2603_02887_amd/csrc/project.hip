@@ -1,0 +1,293 @@
+// EWA projection, culling, tile rectangle and composite coefficients.
+//
+// One thread per (Gaussian, view).  Two computations live here:
+//   * the tile-key recipe in IEEE float32 (depth bits and covered tiles),
+//     evaluated operation by operation in a fixed order with no fused
+//     multiply-add, so that which tiles a Gaussian lands in, and at which
+//     depth key, is reproducible bit for bit;
+//   * the footprint used by the composite (Sec. 3: alpha = aleph * K), in
+//     FP64: centre, 2D covariance with 0.3 px^2 dilation and its inverse,
+//     folded into the exponent coefficients of log2(alpha).
+// The emission is the real SH expansion (degree <= 3) at the direction from
+// the camera centre to the mean, plus 1/2, clamped at 0.
+//
+// This translation unit is compiled with -ffp-contract=off; the pragma
+// below keeps the recipe uncontracted regardless.
+#include "nxs_internal.h"
+
+namespace nxs {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct KeyGeom {
+  bool visible;
+  uint32_t depth_bits;
+  int tx0, tx1, ty0, ty1;
+};
+
+__device__ __forceinline__ KeyGeom key_recipe(const float* m, const float* s,
+                                              const float* q, float aleph,
+                                              const ViewDev& v, float kappa2,
+                                              float alpha_min, int tile_w,
+                                              int tile_h) {
+#pragma clang fp contract(off)
+  KeyGeom out;
+  out.visible = false;
+  out.depth_bits = 0xFFFFFFFFu;
+  out.tx0 = out.tx1 = out.ty0 = out.ty1 = -1;
+  const float* R = v.R;
+  float px = ((R[0] * m[0] + R[1] * m[1]) + R[2] * m[2]) + v.t[0];
+  float py = ((R[3] * m[0] + R[4] * m[1]) + R[5] * m[2]) + v.t[1];
+  float pz = ((R[6] * m[0] + R[7] * m[1]) + R[8] * m[2]) + v.t[2];
+  if (!(pz > v.znear) || !(aleph >= alpha_min)) return out;
+  float n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
+  if (!(n2 > 0.0f)) return out;
+  float nr = __fsqrt_rn(n2);
+  float w = __fdiv_rn(q[0], nr), x = __fdiv_rn(q[1], nr);
+  float y = __fdiv_rn(q[2], nr), z = __fdiv_rn(q[3], nr);
+  float Rq[3][3];
+  Rq[0][0] = 1.0f - 2.0f * (y * y + z * z);
+  Rq[0][1] = 2.0f * (x * y - w * z);
+  Rq[0][2] = 2.0f * (x * z + w * y);
+  Rq[1][0] = 2.0f * (x * y + w * z);
+  Rq[1][1] = 1.0f - 2.0f * (x * x + z * z);
+  Rq[1][2] = 2.0f * (y * z - w * x);
+  Rq[2][0] = 2.0f * (x * z - w * y);
+  Rq[2][1] = 2.0f * (y * z + w * x);
+  Rq[2][2] = 1.0f - 2.0f * (x * x + y * y);
+  float M[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[i][j] = Rq[i][j] * s[j];
+  float G[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      G[i][j] = (R[3 * i] * M[0][j] + R[3 * i + 1] * M[1][j]) + R[3 * i + 2] * M[2][j];
+  float fxx = v.fx * px, fyy = v.fy * py, zz = pz * pz;
+  float j00 = __fdiv_rn(v.fx, pz), j02 = -__fdiv_rn(fxx, zz);
+  float j11 = __fdiv_rn(v.fy, pz), j12 = -__fdiv_rn(fyy, zz);
+  float A0[3], A1[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    A0[j] = j00 * G[0][j] + j02 * G[2][j];
+    A1[j] = j11 * G[1][j] + j12 * G[2][j];
+  }
+  float a = ((A0[0] * A0[0] + A0[1] * A0[1]) + A0[2] * A0[2]) + 0.3f;
+  float c = ((A1[0] * A1[0] + A1[1] * A1[1]) + A1[2] * A1[2]) + 0.3f;
+  float u = __fdiv_rn(fxx, pz) + v.cx;
+  float vv = __fdiv_rn(fyy, pz) + v.cy;
+  float rx = __fsqrt_rn(kappa2 * a);
+  float ry = __fsqrt_rn(kappa2 * c);
+  if (!(isfinite(u) && isfinite(vv) && isfinite(rx) && isfinite(ry))) return out;
+  float x0 = ceilf((u - rx) - 0.5f), x1 = floorf((u + rx) - 0.5f);
+  float y0 = ceilf((vv - ry) - 0.5f), y1 = floorf((vv + ry) - 0.5f);
+  x0 = x0 > 0.0f ? x0 : 0.0f;
+  y0 = y0 > 0.0f ? y0 : 0.0f;
+  float wm1 = (float)(v.width - 1), hm1 = (float)(v.height - 1);
+  x1 = x1 < wm1 ? x1 : wm1;
+  y1 = y1 < hm1 ? y1 : hm1;
+  if (!(x0 <= x1) || !(y0 <= y1)) return out;
+  out.visible = true;
+  out.depth_bits = __float_as_uint(pz);
+  out.tx0 = (int)x0 / tile_w;
+  out.tx1 = (int)x1 / tile_w;
+  out.ty0 = (int)y0 / tile_h;
+  out.ty1 = (int)y1 / tile_h;
+  return out;
+}
+
+// Real SH basis without the Condon-Shortley phase; index l*l + l + m.
+__device__ __forceinline__ void sh_colour(const float* sh, int degree, float dx,
+                                          float dy, float dz, float rgb[3]) {
+  float Y[16];
+  Y[0] = 0.28209479177387814f;
+  int K = 1;
+  if (degree >= 1) {
+    const float c1 = 0.4886025119029199f;
+    Y[1] = c1 * dy;
+    Y[2] = c1 * dz;
+    Y[3] = c1 * dx;
+    K = 4;
+  }
+  if (degree >= 2) {
+    const float c2a = 1.0925484305920792f;   // sqrt(15/pi)/2
+    const float c2b = 0.31539156525252005f;  // sqrt(5/pi)/4
+    const float c2c = 0.5462742152960396f;   // sqrt(15/pi)/4
+    Y[4] = c2a * dx * dy;
+    Y[5] = c2a * dy * dz;
+    Y[6] = c2b * (3.0f * dz * dz - 1.0f);
+    Y[7] = c2a * dx * dz;
+    Y[8] = c2c * (dx * dx - dy * dy);
+    K = 9;
+  }
+  if (degree >= 3) {
+    const float c3a = 0.5900435899266435f;   // sqrt(35/(2pi))/4
+    const float c3b = 2.890611442640554f;    // sqrt(105/pi)/2
+    const float c3c = 0.4570457994644658f;   // sqrt(21/(2pi))/4
+    const float c3d = 0.3731763325901154f;   // sqrt(7/pi)/4
+    const float c3e = 1.445305721320277f;    // sqrt(105/pi)/4
+    Y[9] = c3a * dy * (3.0f * dx * dx - dy * dy);
+    Y[10] = c3b * dx * dy * dz;
+    Y[11] = c3c * dy * (5.0f * dz * dz - 1.0f);
+    Y[12] = c3d * dz * (5.0f * dz * dz - 3.0f);
+    Y[13] = c3c * dx * (5.0f * dz * dz - 1.0f);
+    Y[14] = c3e * dz * (dx * dx - dy * dy);
+    Y[15] = c3a * dx * (dx * dx - 3.0f * dy * dy);
+    K = 16;
+  }
+  float r = 0.5f, g = 0.5f, b = 0.5f;
+  for (int k = 0; k < K; ++k) {
+    r += Y[k] * sh[3 * k + 0];
+    g += Y[k] * sh[3 * k + 1];
+    b += Y[k] * sh[3 * k + 2];
+  }
+  rgb[0] = r > 0.0f ? r : 0.0f;
+  rgb[1] = g > 0.0f ? g : 0.0f;
+  rgb[2] = b > 0.0f ? b : 0.0f;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, 64));
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o, 64));
+  return x;
+}
+
+__global__ __launch_bounds__(kBlock) void project_kernel(
+    GaussDev g, const ViewDev* __restrict__ views, float kappa2, float alpha_min,
+    int tile_w, int tile_h, ProjDev out, Counters* __restrict__ counters) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int vi = blockIdx.y;
+  const ViewDev& v = views[vi];
+  uint32_t nt = 0, dmin = 0xFFFFFFFFu, dmax = 0u;
+  if (i < g.n) {
+    const int64_t slot = (int64_t)vi * g.n + i;
+    float m[3] = {g.means[3 * i], g.means[3 * i + 1], g.means[3 * i + 2]};
+    float s[3] = {g.scales[3 * i], g.scales[3 * i + 1], g.scales[3 * i + 2]};
+    float q[4] = {g.quats[4 * i], g.quats[4 * i + 1], g.quats[4 * i + 2],
+                  g.quats[4 * i + 3]};
+    float aleph = g.opac[i];
+    KeyGeom kg = key_recipe(m, s, q, aleph, v, kappa2, alpha_min, tile_w, tile_h);
+    uint2 rect = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+    if (kg.visible) {
+      nt = (uint32_t)((kg.tx1 - kg.tx0 + 1) * (kg.ty1 - kg.ty0 + 1));
+      dmin = dmax = kg.depth_bits;
+      rect = make_uint2((uint32_t)kg.tx0 | ((uint32_t)kg.tx1 << 16),
+                        (uint32_t)kg.ty0 | ((uint32_t)kg.ty1 << 16));
+      // ---- composite footprint in FP64 -----------------------------------
+      double R[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) R[k] = (double)v.R[k];
+      double mx = m[0], my = m[1], mz = m[2];
+      double px = R[0] * mx + R[1] * my + R[2] * mz + (double)v.t[0];
+      double py = R[3] * mx + R[4] * my + R[5] * mz + (double)v.t[1];
+      double pz = R[6] * mx + R[7] * my + R[8] * mz + (double)v.t[2];
+      double qn = sqrt((double)q[0] * q[0] + (double)q[1] * q[1] +
+                       (double)q[2] * q[2] + (double)q[3] * q[3]);
+      double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+      double Rq[3][3] = {
+          {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+          {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+          {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+      double fx = v.fx, fy = v.fy;
+      double j00 = fx / pz, j02 = -fx * px / (pz * pz);
+      double j11 = fy / pz, j12 = -fy * py / (pz * pz);
+      // T = J R_cam (2x3); A = T R_q diag(s) (2x3); Sigma2D = A A^T
+      double T0[3], T1[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T0[k] = j00 * R[k] + j02 * R[6 + k];
+        T1[k] = j11 * R[3 + k] + j12 * R[6 + k];
+      }
+      double A0[3], A1[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double sj = s[j];
+        A0[j] = (T0[0] * Rq[0][j] + T0[1] * Rq[1][j] + T0[2] * Rq[2][j]) * sj;
+        A1[j] = (T1[0] * Rq[0][j] + T1[1] * Rq[1][j] + T1[2] * Rq[2][j]) * sj;
+      }
+      double a = A0[0] * A0[0] + A0[1] * A0[1] + A0[2] * A0[2] + 0.3;
+      double b = A0[0] * A1[0] + A0[1] * A1[1] + A0[2] * A1[2];
+      double c = A1[0] * A1[0] + A1[1] * A1[1] + A1[2] * A1[2] + 0.3;
+      double det = a * c - b * b;
+      double cA = c / det, cB = -b / det, cC = a / det;
+      // log2(alpha) = log2(aleph) - (1/2) log2(e) (cA dx^2 + 2 cB dx dy + cC dy^2)
+      const double kL2e = 1.4426950408889634;
+      out.uv[slot] = make_double2(fx * px / pz + (double)v.cx,
+                                  fy * py / pz + (double)v.cy);
+      out.geoA[slot] = make_float4((float)(-0.5 * kL2e * cA), (float)(-kL2e * cB),
+                                   (float)(-0.5 * kL2e * cC), (float)log2((double)aleph));
+      // ---- emission -------------------------------------------------------
+      double ddx = mx - (double)v.campos[0], ddy = my - (double)v.campos[1],
+             ddz = mz - (double)v.campos[2];
+      double dn = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+      float rgb[3];
+      const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+      sh_colour(g.sh + (int64_t)i * K * 3, g.sh_degree, (float)(ddx / dn),
+                (float)(ddy / dn), (float)(ddz / dn), rgb);
+      out.geoB[slot] = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+    }
+    out.depth_key[slot] = kg.depth_bits;
+    out.ntiles[slot] = nt;
+    out.rect[slot] = rect;
+  }
+  // block reductions: instance total and visible depth-bit range
+  __shared__ uint32_t s_sum[kBlock / 64], s_min[kBlock / 64], s_max[kBlock / 64];
+  uint32_t ws = wave_sum_u32(nt), wmn = wave_min_u32(dmin), wmx = wave_max_u32(dmax);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_sum[wid] = ws;
+    s_min[wid] = wmn;
+    s_max[wid] = wmx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+    for (int k = 0; k < kBlock / 64; ++k) {
+      tot += s_sum[k];
+      mn = min(mn, s_min[k]);
+      mx = max(mx, s_max[k]);
+    }
+    if (tot) atomicAdd(&counters->total, tot);
+    if (mn != 0xFFFFFFFFu) atomicMin(&counters->dmin, mn);
+    if (mx) atomicMax(&counters->dmax, mx);
+  }
+}
+
+__global__ void init_counters_kernel(Counters* c) {
+  c->total = 0ull;
+  c->dmin = 0xFFFFFFFFu;
+  c->dmax = 0u;
+}
+
+}  // namespace
+
+void launch_init_counters(Counters* c, hipStream_t s) {
+  hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(1), 0, s, c);
+}
+
+void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
+                    float kappa2, float alpha_min, int tile_w, int tile_h,
+                    const ProjDev& out, Counters* counters, hipStream_t s) {
+  if (g.n <= 0 || n_views <= 0) return;
+  dim3 grid((g.n + kBlock - 1) / kBlock, n_views);
+  hipLaunchKernelGGL(project_kernel, grid, dim3(kBlock), 0, s, g, views, kappa2,
+                     alpha_min, tile_w, tile_h, out, counters);
+}
+
+}  // namespace nxs

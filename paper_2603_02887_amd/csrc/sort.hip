@@ -1,0 +1,408 @@
+// Sorting and binning: stable LSD radix sort of (u32 key, u32 value) pairs,
+// the scan + emission of tile instances, tile ranges and the gather of the
+// composite records into sorted order.
+//
+// Front-to-back order inside each tile (Sec. 3: splats sorted by depth) is
+// obtained in two sorts instead of one wide one:
+//   1. the projected slots are sorted by their float32 depth bits (stable,
+//      so equal depths keep ascending Gaussian index);
+//   2. instances are emitted in that order and sorted stably by global tile.
+// The result is ordered by (tile, depth bits, Gaussian index), the same as a
+// single sort on the 64-bit key (tile << 32 | depth bits) with ties by index,
+// while moving 32-bit keys over fewer bits.
+//
+// Radix sort: reduce-then-scan, 8-bit digits, 4096 keys per work-group chunk.
+//   count   per chunk and digit            counts[d * nchunks + c]
+//   scan    per digit over chunks (one WG per digit) -> exclusive offsets,
+//           digit totals
+//   scatter per chunk: digit bases from the totals, stable local ranks via
+//           wave ballots, a local reorder in LDS, then coalesced stores.
+// No kernel waits on another work-group, so no launch can deadlock.
+#include "nxs_internal.h"
+
+namespace nxs {
+
+namespace {
+
+constexpr int kSortBlock = 256;
+constexpr int kItems = 16;
+constexpr int kChunk = kSortBlock * kItems;  // 4096
+constexpr int kRadix = 256;
+
+__device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift, uint32_t mask) {
+  return (k >> shift) & mask;
+}
+
+__global__ __launch_bounds__(kSortBlock) void rs_count(const uint32_t* __restrict__ keys,
+                                                       int64_t n, int shift, uint32_t mask,
+                                                       int nchunks,
+                                                       uint32_t* __restrict__ counts) {
+  __shared__ uint32_t hist[kRadix];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    int64_t idx = base + r * kSortBlock + threadIdx.x;
+    if (idx < n) atomicAdd(&hist[digit_of(keys[idx], shift, mask)], 1u);
+  }
+  __syncthreads();
+  counts[(int64_t)threadIdx.x * nchunks + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s_tmp,
+                                                         uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_tmp[wid] = incl;
+  __syncthreads();
+  uint32_t wave_off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kSortBlock / 64; ++w) {
+    uint32_t v = s_tmp[w];
+    if (w < wid) wave_off += v;
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return wave_off + incl - x;
+}
+
+// One WG per digit: exclusive scan of counts[d][0..nchunks) in place.
+__global__ __launch_bounds__(kSortBlock) void rs_scan_digit(uint32_t* __restrict__ counts,
+                                                            int nchunks,
+                                                            uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_tmp[kSortBlock / 64];
+  uint32_t* row = counts + (int64_t)blockIdx.x * nchunks;
+  uint32_t running = 0;
+  for (int b = 0; b < nchunks; b += kSortBlock * 4) {
+    uint32_t v[4];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int idx = b + threadIdx.x * 4 + k;
+      v[k] = idx < nchunks ? row[idx] : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(sum, s_tmp, &tot) + running;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int idx = b + threadIdx.x * 4 + k;
+      if (idx < nchunks) row[idx] = ex;
+      ex += v[k];
+    }
+    running += tot;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = running;
+}
+
+__global__ __launch_bounds__(kSortBlock) void rs_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n,
+    int shift, uint32_t mask, int nchunks, const uint32_t* __restrict__ counts,
+    const uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_key[kChunk];
+  __shared__ uint32_t s_val[kChunk];
+  __shared__ uint32_t s_gbase[kRadix];   // global position of this chunk's digit run
+  __shared__ uint32_t s_lbase[kRadix];   // local (in-chunk) start of the digit run
+  __shared__ uint32_t s_run[kRadix];     // keys of this digit placed so far
+  __shared__ uint32_t s_wave[kSortBlock / 64][kRadix];
+  __shared__ uint32_t s_tmp[kSortBlock / 64];
+
+  const int t = threadIdx.x;
+  const int c = blockIdx.x;
+  const int64_t base = (int64_t)c * kChunk;
+  const int chunk_n = (int)min((int64_t)kChunk, n - base);
+
+  // digit bases: exclusive scan of the digit totals + this chunk's offset
+  uint32_t dtot;
+  uint32_t dbase = block_exclusive_scan(totals[t], s_tmp, &dtot);
+  uint32_t off_c = counts[(int64_t)t * nchunks + c];
+  uint32_t next = (c + 1 < nchunks) ? counts[(int64_t)t * nchunks + c + 1] : totals[t];
+  uint32_t local_cnt = next - off_c;
+  uint32_t lb;
+  uint32_t ltot;
+  lb = block_exclusive_scan(local_cnt, s_tmp, &ltot);
+  s_gbase[t] = dbase + off_c;
+  s_lbase[t] = lb;
+  s_run[t] = 0;
+#pragma unroll
+  for (int w = 0; w < kSortBlock / 64; ++w) s_wave[w][t] = 0;
+
+  uint32_t k_reg[kItems], v_reg[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    int li = r * kSortBlock + t;
+    if (li < chunk_n) {
+      k_reg[r] = keys_in[base + li];
+      v_reg[r] = vals_in[base + li];
+    }
+  }
+  __syncthreads();
+
+  const int lane = t & 63, wid = t >> 6;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // fully unrolled: k_reg / v_reg must stay in registers
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int li = r * kSortBlock + t;
+    const bool valid = li < chunk_n;
+    const uint32_t d = valid ? digit_of(k_reg[r], shift, mask) : 0u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t rank = 0;
+    if (valid) {
+      rank = __popcll(peers & lt_mask);
+      if (rank == 0) s_wave[wid][d] = (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    if (valid) {
+      uint32_t off = s_run[d] + rank;
+      for (int w = 0; w < wid; ++w) off += s_wave[w][d];
+      const uint32_t lp = s_lbase[d] + off;
+      s_key[lp] = k_reg[r];
+      s_val[lp] = v_reg[r];
+    }
+    __syncthreads();
+    {
+      uint32_t add = 0;
+#pragma unroll
+      for (int w = 0; w < kSortBlock / 64; ++w) {
+        add += s_wave[w][t];
+        s_wave[w][t] = 0;
+      }
+      s_run[t] += add;
+    }
+    __syncthreads();
+  }
+  // coalesced write-out of the locally sorted chunk
+  for (int i = t; i < chunk_n; i += kSortBlock) {
+    const uint32_t k = s_key[i];
+    const uint32_t d = digit_of(k, shift, mask);
+    const uint32_t g = s_gbase[d] + (uint32_t)i - s_lbase[d];
+    keys_out[g] = k;
+    vals_out[g] = s_val[i];
+  }
+}
+
+// ---------------------------------------------------------------- scan + emit
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanChunk = kScanBlock * kScanItems;
+
+// Block-local exclusive scan of ntiles in sorted-slot order.
+__global__ __launch_bounds__(kScanBlock) void scan_local_kernel(
+    const uint32_t* __restrict__ sorted_slots, int64_t n,
+    const uint32_t* __restrict__ ntiles, uint32_t* __restrict__ local,
+    uint32_t* __restrict__ block_sums) {
+  __shared__ uint32_t s_tmp[kScanBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    v[k] = i < n ? ntiles[sorted_slots[i]] : 0u;
+    sum += v[k];
+  }
+  uint32_t tot;
+  uint32_t ex = block_exclusive_scan(sum, s_tmp, &tot);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    if (i < n) local[i] = ex;
+    ex += v[k];
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// Single work-group exclusive scan of the block sums (in place).
+__global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(uint32_t* __restrict__ sums,
+                                                                 int nblocks) {
+  __shared__ uint32_t s_tmp[kScanBlock / 64];
+  uint32_t running = 0;
+  for (int b = 0; b < nblocks; b += kScanBlock * 4) {
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int idx = b + threadIdx.x * 4 + k;
+      v[k] = idx < nblocks ? sums[idx] : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(sum, s_tmp, &tot) + running;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int idx = b + threadIdx.x * 4 + k;
+      if (idx < nblocks) sums[idx] = ex;
+      ex += v[k];
+    }
+    running += tot;
+  }
+}
+
+// One thread per sorted slot: write its (global tile, slot) instances.
+__global__ __launch_bounds__(kScanBlock) void emit_kernel(
+    const uint32_t* __restrict__ sorted_slots, int64_t n, int32_t n_gauss,
+    const uint32_t* __restrict__ ntiles, const uint2* __restrict__ rect,
+    const ViewDev* __restrict__ views, const uint32_t* __restrict__ local,
+    const uint32_t* __restrict__ block_off, uint32_t* __restrict__ inst_tile,
+    uint32_t* __restrict__ inst_val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t slot = sorted_slots[i];
+  const uint32_t nt = ntiles[slot];
+  if (nt == 0) return;
+  uint32_t off = block_off[i / kScanChunk] + local[i];
+  const uint2 r = rect[slot];
+  const int tx0 = r.x & 0xFFFF, tx1 = r.x >> 16, ty0 = r.y & 0xFFFF, ty1 = r.y >> 16;
+  const ViewDev& v = views[slot / (uint32_t)n_gauss];
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    const uint32_t row = (uint32_t)(v.tile_off + ty * v.tiles_x);
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      inst_tile[off] = row + (uint32_t)tx;
+      inst_val[off] = slot;
+      ++off;
+    }
+  }
+}
+
+// ----------------------------------------------------- ranges + gather
+
+__global__ void iota_copy_kernel(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                 uint32_t* __restrict__ idx, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    dst[i] = src[i];
+    idx[i] = (uint32_t)i;
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t value) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewDev* views, int n_views, uint32_t tile) {
+  int lo = 0, hi = n_views - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((uint32_t)views[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void ranges_gather_kernel(
+    const uint32_t* __restrict__ inst_tile, const uint32_t* __restrict__ inst_val,
+    int64_t m, ProjDev proj, const ViewDev* __restrict__ views, int n_views, int tile_w,
+    int tile_h, uint2* __restrict__ ranges, float4* __restrict__ rec0,
+    float4* __restrict__ rec1, float* __restrict__ rec2) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const uint32_t tile = inst_tile[j];
+  if (j == 0 || inst_tile[j - 1] != tile) ranges[tile].x = (uint32_t)j;
+  if (j == m - 1 || inst_tile[j + 1] != tile) ranges[tile].y = (uint32_t)(j + 1);
+  const uint32_t slot = inst_val[j];
+  const int vi = view_of_tile(views, n_views, tile);
+  const ViewDev& v = views[vi];
+  const int lt = (int)(tile - (uint32_t)v.tile_off);
+  const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
+  const double2 uv = proj.uv[slot];
+  const float4 ga = proj.geoA[slot];
+  const float4 gb = proj.geoB[slot];
+  // centre relative to the tile's corner: small numbers keep float32 exact enough
+  const float du = (float)(uv.x - (double)(tx * tile_w));
+  const float dv = (float)(uv.y - (double)(ty * tile_h));
+  rec0[j] = make_float4(du, dv, ga.x, ga.y);
+  rec1[j] = make_float4(ga.z, ga.w, gb.x, gb.y);
+  rec2[j] = gb.z;
+}
+
+}  // namespace
+
+size_t radix_counts_size(int64_t n) {
+  const int64_t nchunks = (n + kChunk - 1) / kChunk;
+  return (size_t)(nchunks > 0 ? nchunks : 1) * kRadix + kRadix;
+}
+
+int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                     uint32_t* vals_alt, int64_t n, int nbits, uint32_t* counts,
+                     hipStream_t s) {
+  if (n <= 1 || nbits <= 0) return 0;
+  const int nchunks = (int)((n + kChunk - 1) / kChunk);
+  uint32_t* totals = counts + (int64_t)nchunks * kRadix;
+  int cur = 0;
+  for (int shift = 0; shift < nbits; shift += 8) {
+    const int width = min(8, nbits - shift);
+    const uint32_t mask = (1u << width) - 1u;
+    uint32_t* kin = cur ? keys_alt : keys;
+    uint32_t* vin = cur ? vals_alt : vals;
+    uint32_t* kout = cur ? keys : keys_alt;
+    uint32_t* vout = cur ? vals : vals_alt;
+    hipLaunchKernelGGL(rs_count, dim3(nchunks), dim3(kSortBlock), 0, s, kin, n, shift,
+                       mask, nchunks, counts);
+    hipLaunchKernelGGL(rs_scan_digit, dim3(kRadix), dim3(kSortBlock), 0, s, counts,
+                       nchunks, totals);
+    hipLaunchKernelGGL(rs_scatter, dim3(nchunks), dim3(kSortBlock), 0, s, kin, vin, kout,
+                       vout, n, shift, mask, nchunks, counts, totals);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+size_t scan_blocks_size(int64_t n) {
+  return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1;
+}
+
+void launch_emit(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
+                 const ProjDev& proj, const ViewDev* views, uint32_t* scan_local,
+                 uint32_t* block_sums, uint32_t* inst_tile, uint32_t* inst_val,
+                 hipStream_t s) {
+  if (n_slots <= 0) return;
+  const int nblocks = (int)((n_slots + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(scan_local_kernel, dim3(nblocks), dim3(kScanBlock), 0, s,
+                     sorted_slots, n_slots, proj.ntiles, scan_local, block_sums);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanBlock), 0, s, block_sums,
+                     nblocks);
+  const int eb = (int)((n_slots + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(emit_kernel, dim3(eb), dim3(kScanBlock), 0, s, sorted_slots, n_slots,
+                     n_gauss, proj.ntiles, proj.rect, views, scan_local, block_sums,
+                     inst_tile, inst_val);
+}
+
+void launch_iota_copy(const uint32_t* src, uint32_t* dst, uint32_t* idx, int64_t n,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(iota_copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     src, dst, idx, n);
+}
+
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     p, n, value);
+}
+
+void launch_ranges_gather(const uint32_t* inst_tile, const uint32_t* inst_val, int64_t m,
+                          const ProjDev& proj, const ViewDev* views, int n_views,
+                          int tile_w, int tile_h, uint2* ranges, float4* rec0,
+                          float4* rec1, float* rec2, hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(ranges_gather_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0,
+                     s, inst_tile, inst_val, m, proj, views, n_views, tile_w, tile_h,
+                     ranges, rec0, rec1, rec2);
+}
+
+}  // namespace nxs

@@ -1,0 +1,228 @@
+"""Python binding of libnxs (ctypes): argument marshalling only.
+
+Every step of the render runs in the HIP library; this module checks that
+tensors are on the GPU, float32 and contiguous, fills the C structs of
+include/nxs.h and passes device pointers and the current HIP stream.
+Loading fails loudly when libnxs.so has not been built.
+"""
+import ctypes
+from ctypes import POINTER, byref, c_float, c_int32, c_int64, c_uint32, c_uint64, c_void_p
+from pathlib import Path
+
+import numpy as np
+import torch
+
+LIB_PATH = Path(__file__).resolve().parent / "libnxs.so"
+
+MODEL_IDS = {"exponential": 0, "linear": 1, "sublinear": 2, "superlinear": 3}
+STATUS = {0: "NXS_OK", -1: "NXS_EINVAL", -2: "NXS_ENOMEM", -3: "NXS_EHIP",
+          -4: "NXS_ECAPACITY", -5: "NXS_EUNSUPPORTED"}
+SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_last_error",
+           "nxs_set_timing", "nxs_inspect_stage_times", "nxs_inspect_counts", "nxs_inspect_instances", "nxs_inspect_ranges",
+           "nxs_inspect_projection"]
+
+
+class NxsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("sh_degree", c_int32), ("means", c_void_p),
+                ("scales", c_void_p), ("quats", c_void_p), ("opacities", c_void_p),
+                ("sh", c_void_p)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", c_float * 9), ("t", c_float * 3), ("fx", c_float), ("fy", c_float),
+                ("cx", c_float), ("cy", c_float), ("znear", c_float),
+                ("width", c_int32), ("height", c_int32)]
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("model", c_int32), ("background", c_float * 3), ("alpha_min", c_float),
+                ("t_eps", c_float), ("tile_w", c_int32), ("tile_h", c_int32),
+                ("lds_batch", c_int32)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("rgb", c_void_p), ("trans", c_void_p), ("overdraw", c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libnxs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} not found: build it with "
+                               "`python -m paper_2603_02887_amd.build`")
+        L = ctypes.CDLL(str(LIB_PATH))
+        L.nxs_create.argtypes = [POINTER(c_void_p), ctypes.c_int]
+        L.nxs_destroy.argtypes = [c_void_p]
+        L.nxs_render_forward.argtypes = [c_void_p, POINTER(Gaussians), POINTER(Camera), c_int32,
+                                         POINTER(RenderOpts), POINTER(Image), c_void_p]
+        L.nxs_last_error.argtypes = [c_void_p]
+        L.nxs_last_error.restype = ctypes.c_char_p
+        L.nxs_set_timing.argtypes = [c_void_p, c_int32]
+        L.nxs_inspect_stage_times.argtypes = [c_void_p, c_void_p, c_int32]
+        L.nxs_inspect_counts.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64)]
+        L.nxs_inspect_instances.argtypes = [c_void_p, c_void_p, c_void_p, c_int64]
+        L.nxs_inspect_ranges.argtypes = [c_void_p, c_void_p, c_int64]
+        L.nxs_inspect_projection.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int64]
+        for name in SYMBOLS:
+            if name not in ("nxs_last_error",):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _f32(t, name, shape_tail=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    return t
+
+
+def scene_to_device(scene, device="cuda"):
+    """Upload a synth.Scene's arrays as contiguous float32 GPU tensors."""
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+    return {"means": f(scene.means), "scales": f(scene.scales), "quats": f(scene.quats),
+            "opacities": f(scene.opacities), "sh": f(scene.sh),
+            "sh_degree": int(scene.sh_degree)}
+
+
+def make_camera(cam):
+    """C camera struct from any object with R, t, fx, fy, cx, cy, znear, width, height."""
+    c = Camera()
+    R = np.asarray(cam.R, np.float32).reshape(9)
+    t = np.asarray(cam.t, np.float32).reshape(3)
+    for k in range(9):
+        c.R[k] = float(R[k])
+    for k in range(3):
+        c.t[k] = float(t[k])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.znear = float(getattr(cam, "znear", 0.01))
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+class Renderer:
+    """A library context on one GPU; render() enqueues on the current stream."""
+
+    def __init__(self, device=0):
+        self._L = lib()
+        self._ctx = c_void_p()
+        st = self._L.nxs_create(byref(self._ctx), int(device))
+        if st != 0:
+            raise NxsError(st, "nxs_create failed")
+        self.device = torch.device("cuda", int(device))
+
+    def close(self):
+        if self._ctx:
+            self._L.nxs_destroy(self._ctx)
+            self._ctx = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            msg = self._L.nxs_last_error(self._ctx)
+            raise NxsError(st, msg.decode() if msg else "")
+
+    def render(self, g, cams, model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0,
+               t_eps=0.0, tile=(16, 16), lds_batch=0, outputs=None, overdraw=True,
+               stream=None):
+        """Render the Gaussians `g` (dict of GPU tensors, see scene_to_device) in
+        every camera of `cams`.  Returns a list of dicts {rgb [H,W,3], trans [H,W],
+        overdraw [H,W] int32} (or fills `outputs`, a list of such dicts)."""
+        if isinstance(model, str):
+            model = MODEL_IDS[model]
+        n = int(g["means"].shape[0])
+        gs = Gaussians()
+        gs.n, gs.sh_degree = n, int(g["sh_degree"])
+        if n:
+            gs.means = _f32(g["means"], "means").data_ptr()
+            gs.scales = _f32(g["scales"], "scales").data_ptr()
+            gs.quats = _f32(g["quats"], "quats").data_ptr()
+            gs.opacities = _f32(g["opacities"], "opacities").data_ptr()
+            gs.sh = _f32(g["sh"], "sh").data_ptr()
+            K = (gs.sh_degree + 1) ** 2
+            if tuple(g["sh"].shape[1:]) != (K, 3) or tuple(g["means"].shape[1:]) != (3,):
+                raise ValueError("bad Gaussian array shapes")
+        V = len(cams)
+        carr = (Camera * V)(*[make_camera(c) for c in cams])
+        if outputs is None:
+            outputs = []
+            for c in cams:
+                H, W = int(c.height), int(c.width)
+                outputs.append({
+                    "rgb": torch.empty((H, W, 3), dtype=torch.float32, device=self.device),
+                    "trans": torch.empty((H, W), dtype=torch.float32, device=self.device),
+                    "overdraw": (torch.empty((H, W), dtype=torch.int32, device=self.device)
+                                 if overdraw else None)})
+        imgs = (Image * V)()
+        for k, o in enumerate(outputs):
+            imgs[k].rgb = _f32(o["rgb"], "rgb").data_ptr()
+            imgs[k].trans = _f32(o["trans"], "trans").data_ptr()
+            od = o.get("overdraw")
+            imgs[k].overdraw = od.data_ptr() if od is not None else None
+        opts = RenderOpts()
+        opts.model = int(model)
+        for k in range(3):
+            opts.background[k] = float(background[k])
+        opts.alpha_min, opts.t_eps = float(alpha_min), float(t_eps)
+        opts.tile_w, opts.tile_h = int(tile[0]), int(tile[1])
+        opts.lds_batch = int(lds_batch)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        st = self._L.nxs_render_forward(self._ctx, byref(gs), carr, V, byref(opts), imgs,
+                                        c_void_p(stream.cuda_stream))
+        self._check(st)
+        return outputs
+
+    # -------------------------------------------------------- inspection
+    STAGES = ("project", "depth_sort", "emit", "tile_sort", "gather", "composite")
+
+    def set_timing(self, enable=True):
+        self._check(self._L.nxs_set_timing(self._ctx, int(bool(enable))))
+
+    def stage_times(self):
+        """Milliseconds per stage of the last render (needs set_timing(True))."""
+        ms = np.zeros(len(self.STAGES), np.float32)
+        self._check(self._L.nxs_inspect_stage_times(self._ctx, ms.ctypes.data, ms.size))
+        return dict(zip(self.STAGES, ms.astype(float).tolist()))
+
+    def counts(self):
+        m, t = c_int64(), c_int64()
+        self._check(self._L.nxs_inspect_counts(self._ctx, byref(m), byref(t)))
+        return m.value, t.value
+
+    def instances(self):
+        m, _ = self.counts()
+        keys = np.zeros(max(m, 1), np.uint64)
+        ids = np.zeros(max(m, 1), np.int32)
+        self._check(self._L.nxs_inspect_instances(self._ctx, keys.ctypes.data,
+                                                  ids.ctypes.data, keys.size))
+        return keys[:m], ids[:m]
+
+    def ranges(self):
+        _, t = self.counts()
+        r = np.zeros(2 * max(t, 1), np.int32)
+        self._check(self._L.nxs_inspect_ranges(self._ctx, r.ctypes.data, r.size))
+        return r[:2 * t].reshape(t, 2)
+
+    def projection(self, view, n):
+        d = np.zeros(max(n, 1), np.uint32)
+        r = np.zeros(4 * max(n, 1), np.int32)
+        self._check(self._L.nxs_inspect_projection(self._ctx, int(view), d.ctypes.data,
+                                                   r.ctypes.data, max(n, 1)))
+        return d[:n], r[:4 * n].reshape(n, 4)

@@ -1,0 +1,187 @@
+"""GPU parity of the forward render against the FP64 oracle, through the C ABI.
+
+Tolerances: tile keys, sort order, tile ranges, per-Gaussian depth bits and
+tile rectangles bit-exact; colour and transmittance within 1e-4 absolute per
+channel; overdraw exact except at pixels the oracle flags as boundary cases
+(an alpha within 1e-5 relative of alpha_min, or a transmittance step within
+1e-6 of the cutoff).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2603_02887_amd import nxs
+    r = nxs.Renderer(0)
+    yield r
+    r.close()
+
+
+def _render(R, scene, cams, model, **kw):
+    from paper_2603_02887_amd import nxs
+    g = nxs.scene_to_device(scene)
+    out = R.render(g, cams, model=model, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("model", [0, 1, 2, 3])
+def test_tiny_scene_full_image(R, model):
+    """4,096 Gaussians, 128x128, SH degree 0: every pixel, every model."""
+    sc, cams = synth.tiny_scene()
+    out = _render(R, sc, cams, model)
+    parity.compare_keys(R, sc, cams)
+    st = parity.compare_view(out[0], sc, cams[0], model)
+    print("tiny", model, st)
+
+
+@pytest.mark.parametrize("tile,batch", [((8, 8), 128), ((32, 8), 512), ((16, 16), 128)])
+def test_tile_shapes_and_batches(R, tile, batch):
+    sc, cams = synth.tiny_scene(seed=5, n=3000)
+    cam = synth.look_at_camera((0.2, 0.1, -2.6), width=150, height=97)  # ragged tiles
+    for model in (0, 3):
+        out = _render(R, sc, [cam], model, tile=tile, lds_batch=batch)
+        parity.compare_keys(R, sc, [cam], tile_w=tile[0], tile_h=tile[1])
+        parity.compare_view(out[0], sc, cam, model)
+
+
+def test_multi_view_uneven_sizes(R):
+    sc = synth.random_scene(7, 2500, sh_degree=2, log_scale=(-3.2, 0.4))
+    cams = [synth.look_at_camera((0, 0, -3), width=64, height=64),
+            synth.look_at_camera((2.5, 0.5, -2), width=131, height=77),
+            synth.look_at_camera((-1, 2, -2.2), width=40, height=120)]
+    for model in (0, 2):
+        out = _render(R, sc, cams, model, background=(0.2, 0.3, 0.4))
+        parity.compare_keys(R, sc, cams)
+        for v, cam in enumerate(cams):
+            parity.compare_view(out[v], sc, cam, model, background=(0.2, 0.3, 0.4))
+
+
+def test_sh_degree3_and_background(R):
+    sc = synth.random_scene(8, 2000, sh_degree=3, log_scale=(-3.0, 0.5), logit=(1.0, 1.5))
+    cam = synth.look_at_camera((0.5, -0.3, -2.8), width=96, height=80)
+    for model in range(4):
+        out = _render(R, sc, [cam], model, background=(1.0, 0.5, 0.0))
+        parity.compare_view(out[0], sc, cam, model, background=(1.0, 0.5, 0.0))
+
+
+def test_empty_and_culled_scenes(R):
+    cam = synth.look_at_camera((0, 0, -3), width=40, height=30)
+    empty = synth.random_scene(1, 0)
+    behind = synth.random_scene(2, 50)
+    behind.means[:, 2] = -10.0                 # all behind the camera
+    for sc in (empty, behind):
+        out = _render(R, sc, [cam], 1, background=(0.1, 0.2, 0.3))
+        assert R.counts()[0] == 0
+        assert np.allclose(out[0]["rgb"].cpu().numpy(), [0.1, 0.2, 0.3])
+        assert np.all(out[0]["trans"].cpu().numpy() == 1.0)
+        assert np.all(out[0]["overdraw"].cpu().numpy() == 0)
+
+
+def test_single_opaque_gaussian_saturates(R):
+    """alpha = 1 at the centre: every model saturates there (p = 1, T = 0)."""
+    sc = synth.Scene(np.array([[0, 0, 0]], np.float32), np.full((1, 3), 0.05, np.float32),
+                     np.array([[1, 0, 0, 0]], np.float32), np.ones(1, np.float32),
+                     np.zeros((1, 1, 3), np.float32), 0)
+    R_ = np.eye(3, dtype=np.float32)
+    cam = synth.Camera(R_, np.array([0, 0, 2], np.float32), 64.0, 64.0, 16.5, 16.5, 33, 33)
+    for model in range(4):
+        out = _render(R, sc, [cam], model, background=(1, 1, 1))
+        assert out[0]["trans"].cpu().numpy()[16, 16] == 0.0
+        assert out[0]["overdraw"].cpu().numpy()[16, 16] == 1
+        parity.compare_view(out[0], sc, cam, model, background=(1, 1, 1))
+
+
+def _concentric(n, sigmas, opac, rgbs, fx=512.0):
+    SH_C0 = 0.5 / math.sqrt(math.pi)
+    means, scales, sh = [], [], []
+    for i in range(n):
+        z = 1.0 + 0.01 * i
+        s = math.sqrt(sigmas[i] ** 2 - 0.3) * z / fx
+        means.append((0.0, 0.0, z))
+        scales.append((s, s, s))
+        sh.append([(np.asarray(rgbs[i]) - 0.5) / SH_C0])
+    sc = synth.Scene(np.array(means, np.float32), np.array(scales, np.float32),
+                     np.tile(np.array([[1, 0, 0, 0]], np.float32), (n, 1)),
+                     np.full(n, opac, np.float32), np.array(sh, np.float32), 0)
+    cam = synth.Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32), fx, fx,
+                       256.5, 256.5, 512, 512)
+    return sc, cam
+
+
+def test_blending_figure_on_gpu(R):
+    """Fig. 'Blending comparison' (a) rendered by the GPU: the centre row matches
+    the paper's printed per-splat contributions (6 decimals)."""
+    from tests.golden import fixtures
+    sc, cam = _concentric(3, (40.0, 60.0, 80.0), 1.0, [(1, 0, 0), (0, 1, 0), (0, 0, 1)])
+    rows = fixtures.blending_concentric()
+    for model, name in ((0, "exponential"), (1, "linear"), (2, "quadratic_c-0.5"),
+                        (3, "quadratic_c0.5")):
+        out = _render(R, sc, [cam], model, t_eps=-1.0)
+        rgb = out[0]["rgb"].cpu().numpy()[256, rows[name][:, 0].astype(int)]
+        assert np.abs(rgb - rows[name][:, 1:4]).max() < 5e-6, name
+
+
+def test_transmittance_figure_on_gpu(R):
+    """Fig. 'Transmittance comparison' dots: T after 5j concentric splats of 0.02."""
+    from tests.golden import fixtures
+    dots = fixtures.transmittance_dots()
+    for model, name in ((1, "linear"), (3, "quadratic_c0.5"), (0, "exponential")):
+        for tau, want in dots[name][1::2]:
+            n = int(round(tau / 0.02))
+            sc, cam = _concentric(n, [3.0] * n, 0.02, [(0.5, 0.5, 0.5)] * n)
+            out = _render(R, sc, [cam], model, t_eps=-1.0)
+            assert abs(out[0]["trans"].cpu().numpy()[256, 256] - want) < 2e-6, (name, tau)
+
+
+def test_deterministic(R):
+    sc, cams = synth.tiny_scene(seed=9)
+    a = _render(R, sc, cams, 0)
+    b = _render(R, sc, cams, 0)
+    for k in ("rgb", "trans", "overdraw"):
+        assert torch.equal(a[0][k], b[0][k])
+
+
+def test_invalid_arguments(R):
+    from paper_2603_02887_amd import nxs
+    sc, cams = synth.tiny_scene(n=10)
+    g = nxs.scene_to_device(sc)
+    with pytest.raises(nxs.NxsError) as e:
+        R.render(g, cams, model=7)
+    assert e.value.status == -1
+    with pytest.raises(nxs.NxsError):
+        R.render(g, cams, tile=(12, 12))
+    with pytest.raises(nxs.NxsError):
+        R.render(g, cams, lds_batch=100)
+
+
+@pytest.fixture(scope="module")
+def scene_scale():
+    return synth.scene_scale()
+
+
+@pytest.mark.parametrize("model", [0, 1, 2, 3])
+def test_scene_scale_1m_1080p(R, scene_scale, model):
+    """The benchmark workload (1M Gaussians, SH degree 3, 1920x1080) in the
+    benchmark's launch configuration: every key and the tile ranges
+    bit-exact, 1,500 sampled pixels against the oracle."""
+    sc, cams = scene_scale
+    out = _render(R, sc, cams, model)
+    if model == 0:
+        m = parity.compare_keys(R, sc, cams)
+        print("instances", m)
+    st = parity.compare_view(out[0], sc, cams[0], model,
+                             pixels=parity.sample_pixels(cams[0], 1500, seed=model))
+    print("scene", model, st)

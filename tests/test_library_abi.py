@@ -1,0 +1,53 @@
+"""CPU-side checks of the C-ABI library: it builds' artefact loads and exports
+every entry point include/nxs.h declares; calls that fail argument checks
+before touching the GPU return NXS_EINVAL."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "nxs.h"
+LIB = ROOT / "paper_2603_02887_amd" / "libnxs.so"
+
+
+def declared_symbols():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nxs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_last_error"):
+        assert s in syms
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not LIB.exists():
+        pytest.fail(f"{LIB} missing: run python -m paper_2603_02887_amd.build")
+    return ctypes.CDLL(str(LIB))
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_binding_symbol_list_matches_header():
+    from paper_2603_02887_amd import nxs
+    assert sorted(nxs.SYMBOLS) == declared_symbols()
+
+
+def test_null_context_is_rejected_without_gpu(lib):
+    lib.nxs_render_forward.restype = ctypes.c_int
+    lib.nxs_render_forward.argtypes = [ctypes.c_void_p] * 7
+    assert lib.nxs_render_forward(None, None, None, 1, None, None, None) == -1
+    lib.nxs_last_error.restype = ctypes.c_char_p
+    lib.nxs_last_error.argtypes = [ctypes.c_void_p]
+    assert lib.nxs_last_error(None) == b""
+    lib.nxs_create.restype = ctypes.c_int
+    lib.nxs_create.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    assert lib.nxs_create(None, 0) == -1

@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--cpu-pixels", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (untimed) so that "
+                         "counter runs can scale FETCH_SIZE / WRITE_SIZE by a kernel "
+                         "of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -103,6 +107,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     tw, th = (int(x) for x in args.tile.split("x"))
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     scene, cams = synth.scene_scale()
     cam = cams[0]
     W, H = cam.width, cam.height

@@ -27,10 +27,10 @@ struct nxs_context {
   std::string err;
   // workspace
   DevBuf views, counters;
-  DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, ntiles, rect, uv, geoA, geoB;
+  DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, ntiles, rect, prec;
   DevBuf scan_local, block_sums, counts;
   DevBuf inst_tile, inst_tile_alt, inst_val, inst_val_alt;
-  DevBuf rec0, rec1, rec2, ranges;
+  DevBuf crec, ranges;
   Counters* host_counters = nullptr;  // pinned
   ViewDev* host_views = nullptr;      // pinned
   int host_views_cap = 0;
@@ -131,10 +131,9 @@ nxs_status nxs_destroy(nxs_context* ctx) {
   (void)hipDeviceSynchronize();
   DevBuf* all[] = {&ctx->views,      &ctx->counters,      &ctx->depth_key, &ctx->dsort_a, &ctx->dsort_b,
                    &ctx->slot_a,     &ctx->slot_b,        &ctx->ntiles,    &ctx->rect,
-                   &ctx->uv,         &ctx->geoA,          &ctx->geoB,      &ctx->scan_local,
+                   &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
-                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->rec0,      &ctx->rec1,
-                   &ctx->rec2,       &ctx->ranges};
+                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->crec,      &ctx->ranges};
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
@@ -231,12 +230,11 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
       (st = ensure(ctx, ctx->dsort_b, 4 * S)) ||
       (st = ensure(ctx, ctx->slot_a, 4 * S)) || (st = ensure(ctx, ctx->slot_b, 4 * S)) ||
       (st = ensure(ctx, ctx->ntiles, 4 * S)) || (st = ensure(ctx, ctx->rect, 8 * S)) ||
-      (st = ensure(ctx, ctx->uv, 16 * S)) || (st = ensure(ctx, ctx->geoA, 16 * S)) ||
-      (st = ensure(ctx, ctx->geoB, 16 * S)) || (st = ensure(ctx, ctx->scan_local, 4 * S)) ||
+      (st = ensure(ctx, ctx->prec, 48 * S)) || (st = ensure(ctx, ctx->scan_local, 4 * S)) ||
       (st = ensure(ctx, ctx->block_sums, 4 * scan_blocks_size(S))))
     return st;
   ProjDev proj{P<uint32_t>(ctx->depth_key), P<uint32_t>(ctx->ntiles), P<uint2>(ctx->rect),
-               P<double2>(ctx->uv), P<float4>(ctx->geoA), P<float4>(ctx->geoB)};
+               P<float4>(ctx->prec)};
   GaussDev gd{g->means, g->scales, g->quats, g->opacities, g->sh, g->n, g->sh_degree};
   Counters* dcount = P<Counters>(ctx->counters);
   const float kappa2 = (float)(2.0 * std::log(1.0 / (double)alpha_min));
@@ -261,8 +259,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_size(sort_n))) ||
       (st = ensure(ctx, ctx->inst_tile, 4 * M)) || (st = ensure(ctx, ctx->inst_tile_alt, 4 * M)) ||
       (st = ensure(ctx, ctx->inst_val, 4 * M)) || (st = ensure(ctx, ctx->inst_val_alt, 4 * M)) ||
-      (st = ensure(ctx, ctx->rec0, 16 * M)) || (st = ensure(ctx, ctx->rec1, 16 * M)) ||
-      (st = ensure(ctx, ctx->rec2, 4 * M)) || (st = ensure(ctx, ctx->ranges, 8 * total_tiles)))
+      (st = ensure(ctx, ctx->crec, 48 * M)) || (st = ensure(ctx, ctx->ranges, 8 * total_tiles)))
     return st;
 
   uint32_t* inst_tile = P<uint32_t>(ctx->inst_tile);
@@ -299,8 +296,8 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
     HIP_TRY(mark(5));
     // 4. ranges and gather
     launch_ranges_gather(inst_tile, inst_val, (int64_t)M, proj, dviews, n_views, tw, th,
-                         P<uint2>(ctx->ranges), P<float4>(ctx->rec0), P<float4>(ctx->rec1),
-                         P<float>(ctx->rec2), s);
+                         (float)std::log2((double)alpha_min), P<uint2>(ctx->ranges),
+                         P<float4>(ctx->crec), s);
   } else {
     for (int k = 3; k <= 5; ++k) HIP_TRY(mark(k));
   }
@@ -312,7 +309,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   for (int k = 0; k < 3; ++k) cp.bg[k] = opts->background[k];
   cp.lds_batch = batch;
   launch_composite(opts->model, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),
-                   P<float4>(ctx->rec0), P<float4>(ctx->rec1), P<float>(ctx->rec2), cp, s);
+                   P<float4>(ctx->crec), cp, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(7));
   HIP_TRY(hipEventRecord(ctx->done, s));

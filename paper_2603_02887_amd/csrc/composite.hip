@@ -1,9 +1,12 @@
 // Per-tile front-to-back composite with a pluggable transmittance operator.
 //
-// One work-group per screen tile, one thread per pixel.  The tile's splats,
-// already gathered into depth order and contiguous in HBM, are staged into
-// LDS in batches (coalesced loads); every pixel then walks the batch in
-// order.  Per pixel (Sec. 4, eq. generalized_gaussian and eq. nexp_p):
+// One work-group per screen tile, one thread per pixel; each wave owns an
+// 8x8 pixel block of the tile and runs on its own (no LDS, no barriers).
+// The tile's splats, gathered into depth order and contiguous in HBM, are
+// the same for every lane of a wave, so they are read with scalar loads into
+// SGPRs: no per-lane copies, no LDS bandwidth.  A splat whose footprint box
+// misses the wave's block (one bit of its record) is skipped by a scalar
+// branch.  Per pixel (Sec. 4, eq. generalized_gaussian and eq. nexp_p):
 //   alpha = aleph exp(-q/2), evaluated as exp2 of a precomputed quadratic;
 //   splats with alpha < alpha_min are skipped;
 //   p = alpha * T                (exponential, T <- T (1 - alpha))
@@ -13,8 +16,7 @@
 //   exactly 0 and the pixel stops (saturation); the exponential also stops
 //   after the first splat that leaves T < t_eps;
 //   L += E p, overdraw += 1 for every composited splat.
-// A pixel that has stopped leaves the inner loop; the work-group leaves the
-// tile as soon as a block-wide vote finds every pixel stopped.
+// A wave leaves the tile when a ballot finds all its pixels stopped.
 #include "nxs_internal.h"
 
 namespace nxs {
@@ -28,16 +30,11 @@ template <> struct OpC<1> { static constexpr float c = 0.0f; };   // linear
 template <> struct OpC<2> { static constexpr float c = -0.5f; };  // quadratic, sublinear
 template <> struct OpC<3> { static constexpr float c = 0.5f; };   // quadratic, superlinear
 
-template <int MODEL, int TW, int TH, int BATCH>
+template <int MODEL, int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void composite_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-    const float* __restrict__ rec2, CompositeParams prm) {
-  constexpr int NT = TW * TH;
-  __shared__ float4 s0[BATCH];
-  __shared__ float4 s1[BATCH];
-  __shared__ float s2[BATCH];
-
+    const float4* __restrict__ crec, CompositeParams prm) {
+  static_assert(TW % 8 == 0 && TH % 8 == 0, "waves cover 8x8 blocks");
   const uint32_t tile = blockIdx.x;
   int vi = 0;
   {
@@ -51,10 +48,14 @@ __global__ __launch_bounds__(TW* TH) void composite_kernel(
   const ViewDev& v = views[vi];
   const int lt = (int)(tile - (uint32_t)v.tile_off);
   const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
-  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int bx = (wid % (TW / 8)) * 8, by = (wid / (TW / 8)) * 8;   // wave's 8x8 block
+  const int lx = bx + (lane & 7), ly = by + (lane >> 3);
   const int px = tx * TW + lx, py = ty * TH + ly;
   const bool inside = px < v.width && py < v.height;
   const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
+  const uint32_t wbit = 1u << wid;
 
   const uint2 rg = ranges[tile];
   const float amin = prm.log2_alpha_min;
@@ -68,46 +69,57 @@ __global__ __launch_bounds__(TW* TH) void composite_kernel(
   int od = 0;
   bool done = !inside;
 
-  for (uint32_t base = rg.x; base < rg.y; base += BATCH) {
-    if (!__syncthreads_or(!done)) break;
-    const int cnt = (int)min((uint32_t)BATCH, rg.y - base);
-    for (int i = threadIdx.x; i < cnt; i += NT) {
-      s0[i] = rec0[base + i];
-      s1[i] = rec1[base + i];
-      s2[i] = rec2[base + i];
+  // Batches of 64 splats: lane j loads splat (base + j) into registers with
+  // coalesced loads; a ballot of the block bits gives the wave a bitmap of the
+  // splats whose footprint reaches its 8x8 block; those are visited in order,
+  // each field broadcast from its lane into a scalar register.
+  for (uint32_t base = rg.x; base < rg.y; base += 64) {
+    if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
+    const uint32_t j = base + (uint32_t)lane;
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
+    if (j < rg.y) {
+      q0 = crec[3 * (size_t)j];
+      q1 = crec[3 * (size_t)j + 1];
+      q2 = crec[3 * (size_t)j + 2];
     }
-    __syncthreads();
-    if (!done) {
-      for (int k = 0; k < cnt; ++k) {
-        const float4 g0 = s0[k];   // du, dv, A', B'
-        const float4 g1 = s1[k];   // C', log2(aleph), r, g
-        const float dx = fx - g0.x, dy = fy - g0.y;
-        const float e = g1.y + dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy;
-        if (e < amin) continue;
-        const float a = __builtin_amdgcn_exp2f(e);
-        float p;
-        if (MODEL == 0) {
-          p = a * T;
-          T = T * (1.0f - a);
-          if (!(T >= t_eps) || T == 0.0f) done = true;
-        } else {
-          p = (MODEL == 1) ? a : a * (1.0f + c * tau);
-          if (MODEL >= 2) tau += a;
-          const float Sn = S + p;
-          if (Sn >= 1.0f) {
-            p = 1.0f - S;
-            S = 1.0f;
-            done = true;
+    uint64_t rel = __builtin_amdgcn_ballot_w64((__float_as_uint(q2.y) & wbit) != 0);
+    while (rel) {
+      const int k = __builtin_ctzll(rel);
+      rel &= rel - 1;
+      const float s_du = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.x), k));
+      const float s_dv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.y), k));
+      const float s_A = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.z), k));
+      const float s_B = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.w), k));
+      const float s_C = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.x), k));
+      const float s_lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.y), k));
+      if (!done) {
+        const float dx = fx - s_du, dy = fy - s_dv;
+        const float e = fmaf(dx, fmaf(s_A, dx, s_B * dy), fmaf(s_C * dy, dy, s_lo));
+        if (e >= amin) {
+          const float a = __builtin_amdgcn_exp2f(e);
+          float p;
+          if (MODEL == 0) {
+            p = a * T;
+            T = T * (1.0f - a);
+            done = !(T >= t_eps) || T == 0.0f;
           } else {
-            S = Sn;
+            p = (MODEL == 1) ? a : a * fmaf(c, tau, 1.0f);
+            if (MODEL >= 2) tau += a;
+            const float Sn = S + p;
+            done = Sn >= 1.0f;
+            p = done ? 1.0f - S : p;
+            S = done ? 1.0f : Sn;
           }
+          const float s_r = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.z), k));
+          const float s_g = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.w), k));
+          const float s_b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.x), k));
+          L0 = fmaf(s_r, p, L0);
+          L1 = fmaf(s_g, p, L1);
+          L2 = fmaf(s_b, p, L2);
+          ++od;
         }
-        L0 += g1.z * p;
-        L1 += g1.w * p;
-        L2 += s2[k] * p;
-        ++od;
-        if (done) break;
       }
+      if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
     }
   }
   if (inside) {
@@ -122,49 +134,35 @@ __global__ __launch_bounds__(TW* TH) void composite_kernel(
 }
 
 template <int MODEL, int TW, int TH>
-void launch_b(int64_t n_tiles, int batch, const ViewDev* views, int n_views,
-              const uint2* ranges, const float4* r0, const float4* r1, const float* r2,
-              const CompositeParams& p, hipStream_t s) {
-  dim3 grid((unsigned)n_tiles), block(TW * TH);
-  switch (batch) {
-    case 128:
-      hipLaunchKernelGGL((composite_kernel<MODEL, TW, TH, 128>), grid, block, 0, s, views,
-                         n_views, ranges, r0, r1, r2, p);
-      break;
-    case 512:
-      hipLaunchKernelGGL((composite_kernel<MODEL, TW, TH, 512>), grid, block, 0, s, views,
-                         n_views, ranges, r0, r1, r2, p);
-      break;
-    default:
-      hipLaunchKernelGGL((composite_kernel<MODEL, TW, TH, 256>), grid, block, 0, s, views,
-                         n_views, ranges, r0, r1, r2, p);
-  }
+void launch_t(int64_t n_tiles, const ViewDev* views, int n_views, const uint2* ranges,
+              const float4* crec, const CompositeParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((composite_kernel<MODEL, TW, TH>), dim3((unsigned)n_tiles),
+                     dim3(TW * TH), 0, s, views, n_views, ranges, crec, p);
 }
 
 template <int MODEL>
 void launch_m(int tile_w, int tile_h, int64_t n_tiles, const ViewDev* views, int n_views,
-              const uint2* ranges, const float4* r0, const float4* r1, const float* r2,
-              const CompositeParams& p, hipStream_t s) {
+              const uint2* ranges, const float4* crec, const CompositeParams& p,
+              hipStream_t s) {
   if (tile_w == 8 && tile_h == 8)
-    launch_b<MODEL, 8, 8>(n_tiles, p.lds_batch, views, n_views, ranges, r0, r1, r2, p, s);
+    launch_t<MODEL, 8, 8>(n_tiles, views, n_views, ranges, crec, p, s);
   else if (tile_w == 32 && tile_h == 8)
-    launch_b<MODEL, 32, 8>(n_tiles, p.lds_batch, views, n_views, ranges, r0, r1, r2, p, s);
+    launch_t<MODEL, 32, 8>(n_tiles, views, n_views, ranges, crec, p, s);
   else
-    launch_b<MODEL, 16, 16>(n_tiles, p.lds_batch, views, n_views, ranges, r0, r1, r2, p, s);
+    launch_t<MODEL, 16, 16>(n_tiles, views, n_views, ranges, crec, p, s);
 }
 
 }  // namespace
 
 void launch_composite(int model, int tile_w, int tile_h, int64_t n_tiles,
                       const ViewDev* views, int n_views, const uint2* ranges,
-                      const float4* rec0, const float4* rec1, const float* rec2,
-                      const CompositeParams& p, hipStream_t s) {
+                      const float4* crec, const CompositeParams& p, hipStream_t s) {
   if (n_tiles <= 0) return;
   switch (model) {
-    case 0: launch_m<0>(tile_w, tile_h, n_tiles, views, n_views, ranges, rec0, rec1, rec2, p, s); break;
-    case 1: launch_m<1>(tile_w, tile_h, n_tiles, views, n_views, ranges, rec0, rec1, rec2, p, s); break;
-    case 2: launch_m<2>(tile_w, tile_h, n_tiles, views, n_views, ranges, rec0, rec1, rec2, p, s); break;
-    default: launch_m<3>(tile_w, tile_h, n_tiles, views, n_views, ranges, rec0, rec1, rec2, p, s); break;
+    case 0: launch_m<0>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
+    case 1: launch_m<1>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
+    case 2: launch_m<2>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
+    default: launch_m<3>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
   }
 }
 

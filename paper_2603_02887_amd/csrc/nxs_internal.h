@@ -36,9 +36,11 @@ struct ProjDev {
   uint32_t* depth_key;      // float32 depth bits; 0xFFFFFFFF when culled
   uint32_t* ntiles;         // covered tiles, 0 when culled
   uint2* rect;              // (tx0 | tx1 << 16, ty0 | ty1 << 16)
-  double2* uv;              // image-plane centre, FP64
-  float4* geoA;             // A', B', C', log2(opacity): exponent coefficients
-  float4* geoB;             // r, g, b, 0
+  // 3 float4 per slot:
+  //   (u_hi, u_lo, v_hi, v_lo)  image-plane centre as float hi + lo parts
+  //   (A', B', C', log2 aleph)  log2(alpha) = log2 aleph + A' dx^2 + B' dx dy + C' dy^2
+  //   (r, g, b, 0)              emission
+  float4* rec;
 };
 
 // Device counters filled by the projection: total instances, depth-bit range.
@@ -74,10 +76,17 @@ void launch_iota_copy(const uint32_t* src, uint32_t* dst, uint32_t* idx, int64_t
 
 // Tile ranges and gather of the composite records in sorted order.
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s);
+// Composite records, 3 float4 (12 dwords) per instance in sorted order:
+//   du, dv             centre relative to the tile corner (pixels)
+//   A', B', C', lo     log2(alpha) = lo + A' dx^2 + B' dx dy + C' dy^2
+//   r, g, b            emission
+//   mask               bit i set if the box where alpha >= alpha_min reaches
+//                      the tile's i-th 8x8 pixel block (row-major)
+//   0, 0
 void launch_ranges_gather(const uint32_t* inst_tile, const uint32_t* inst_val,
                           int64_t m, const ProjDev& proj, const ViewDev* views,
-                          int n_views, int tile_w, int tile_h, uint2* ranges,
-                          float4* rec0, float4* rec1, float* rec2, hipStream_t s);
+                          int n_views, int tile_w, int tile_h, float log2_alpha_min,
+                          uint2* ranges, float4* crec, hipStream_t s);
 
 struct CompositeParams {
   float log2_alpha_min;
@@ -87,7 +96,6 @@ struct CompositeParams {
 };
 void launch_composite(int model, int tile_w, int tile_h, int64_t n_tiles,
                       const ViewDev* views, int n_views, const uint2* ranges,
-                      const float4* rec0, const float4* rec1, const float* rec2,
-                      const CompositeParams& p, hipStream_t s);
+                      const float4* crec, const CompositeParams& p, hipStream_t s);
 
 }  // namespace nxs

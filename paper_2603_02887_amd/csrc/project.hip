@@ -13,6 +13,8 @@
 //
 // This translation unit is compiled with -ffp-contract=off; the pragma
 // below keeps the recipe uncontracted regardless.
+#include <hip/hip_fp16.h>
+
 #include "nxs_internal.h"
 
 namespace nxs {
@@ -102,19 +104,20 @@ __device__ __forceinline__ KeyGeom key_recipe(const float* m, const float* s,
 }
 
 // Real SH basis without the Condon-Shortley phase; index l*l + l + m.
-__device__ __forceinline__ void sh_colour(const float* sh, int degree, float dx,
-                                          float dy, float dz, float rgb[3]) {
-  float Y[16];
+// `sh` points at K*3 coefficients (channel fastest) in LDS.
+template <int DEG>
+__device__ __forceinline__ void sh_colour(const float* sh, float dx, float dy, float dz,
+                                          float rgb[3]) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  float Y[K];
   Y[0] = 0.28209479177387814f;
-  int K = 1;
-  if (degree >= 1) {
+  if (DEG >= 1) {
     const float c1 = 0.4886025119029199f;
     Y[1] = c1 * dy;
     Y[2] = c1 * dz;
     Y[3] = c1 * dx;
-    K = 4;
   }
-  if (degree >= 2) {
+  if (DEG >= 2) {
     const float c2a = 1.0925484305920792f;   // sqrt(15/pi)/2
     const float c2b = 0.31539156525252005f;  // sqrt(5/pi)/4
     const float c2c = 0.5462742152960396f;   // sqrt(15/pi)/4
@@ -123,9 +126,8 @@ __device__ __forceinline__ void sh_colour(const float* sh, int degree, float dx,
     Y[6] = c2b * (3.0f * dz * dz - 1.0f);
     Y[7] = c2a * dx * dz;
     Y[8] = c2c * (dx * dx - dy * dy);
-    K = 9;
   }
-  if (degree >= 3) {
+  if (DEG >= 3) {
     const float c3a = 0.5900435899266435f;   // sqrt(35/(2pi))/4
     const float c3b = 2.890611442640554f;    // sqrt(105/pi)/2
     const float c3c = 0.4570457994644658f;   // sqrt(21/(2pi))/4
@@ -138,9 +140,9 @@ __device__ __forceinline__ void sh_colour(const float* sh, int degree, float dx,
     Y[13] = c3c * dx * (5.0f * dz * dz - 1.0f);
     Y[14] = c3e * dz * (dx * dx - dy * dy);
     Y[15] = c3a * dx * (dx * dx - 3.0f * dy * dy);
-    K = 16;
   }
   float r = 0.5f, g = 0.5f, b = 0.5f;
+#pragma unroll
   for (int k = 0; k < K; ++k) {
     r += Y[k] * sh[3 * k + 0];
     g += Y[k] * sh[3 * k + 1];
@@ -167,46 +169,72 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
   return x;
 }
 
+// One work-group projects 256 consecutive Gaussians into every view.  The
+// block's SH coefficients (contiguous in HBM) are staged into LDS with
+// coalesced loads, padded to an odd stride so that per-thread reads are free
+// of bank conflicts; each Gaussian's inputs are read once for all views.
+template <int DEG>
 __global__ __launch_bounds__(kBlock) void project_kernel(
-    GaussDev g, const ViewDev* __restrict__ views, float kappa2, float alpha_min,
-    int tile_w, int tile_h, ProjDev out, Counters* __restrict__ counters) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const int vi = blockIdx.y;
-  const ViewDev& v = views[vi];
-  uint32_t nt = 0, dmin = 0xFFFFFFFFu, dmax = 0u;
-  if (i < g.n) {
+    GaussDev g, const ViewDev* __restrict__ views, int n_views, float kappa2,
+    float alpha_min, int tile_w, int tile_h, ProjDev out, Counters* __restrict__ counters) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr int NC = 3 * K;
+  constexpr int STRIDE = NC + 1;
+  __shared__ float s_sh[kBlock * STRIDE];
+  const int base = blockIdx.x * kBlock;
+  const int cnt = min(kBlock, g.n - base);
+  {
+    const float* src = g.sh + (int64_t)base * NC;
+    for (int e = threadIdx.x; e < cnt * NC; e += kBlock) {
+      const int gi = e / NC, j = e - gi * NC;
+      s_sh[gi * STRIDE + j] = src[e];
+    }
+  }
+  __syncthreads();
+  const int i = base + threadIdx.x;
+  const bool valid = i < g.n;
+  float m[3] = {0, 0, 0}, s[3] = {0, 0, 0}, q[4] = {0, 0, 0, 0}, aleph = 0.0f;
+  if (valid) {
+    m[0] = g.means[3 * i]; m[1] = g.means[3 * i + 1]; m[2] = g.means[3 * i + 2];
+    s[0] = g.scales[3 * i]; s[1] = g.scales[3 * i + 1]; s[2] = g.scales[3 * i + 2];
+    q[0] = g.quats[4 * i]; q[1] = g.quats[4 * i + 1];
+    q[2] = g.quats[4 * i + 2]; q[3] = g.quats[4 * i + 3];
+    aleph = g.opac[i];
+  }
+  uint32_t nt_sum = 0, dmin = 0xFFFFFFFFu, dmax = 0u;
+  for (int vi = 0; vi < n_views; ++vi) {
+    if (!valid) break;
+    const ViewDev& v = views[vi];
     const int64_t slot = (int64_t)vi * g.n + i;
-    float m[3] = {g.means[3 * i], g.means[3 * i + 1], g.means[3 * i + 2]};
-    float s[3] = {g.scales[3 * i], g.scales[3 * i + 1], g.scales[3 * i + 2]};
-    float q[4] = {g.quats[4 * i], g.quats[4 * i + 1], g.quats[4 * i + 2],
-                  g.quats[4 * i + 3]};
-    float aleph = g.opac[i];
     KeyGeom kg = key_recipe(m, s, q, aleph, v, kappa2, alpha_min, tile_w, tile_h);
     uint2 rect = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+    uint32_t nt = 0;
     if (kg.visible) {
       nt = (uint32_t)((kg.tx1 - kg.tx0 + 1) * (kg.ty1 - kg.ty0 + 1));
-      dmin = dmax = kg.depth_bits;
+      dmin = min(dmin, kg.depth_bits);
+      dmax = max(dmax, kg.depth_bits);
       rect = make_uint2((uint32_t)kg.tx0 | ((uint32_t)kg.tx1 << 16),
                         (uint32_t)kg.ty0 | ((uint32_t)kg.ty1 << 16));
       // ---- composite footprint in FP64 -----------------------------------
       double R[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) R[k] = (double)v.R[k];
-      double mx = m[0], my = m[1], mz = m[2];
-      double px = R[0] * mx + R[1] * my + R[2] * mz + (double)v.t[0];
-      double py = R[3] * mx + R[4] * my + R[5] * mz + (double)v.t[1];
-      double pz = R[6] * mx + R[7] * my + R[8] * mz + (double)v.t[2];
-      double qn = sqrt((double)q[0] * q[0] + (double)q[1] * q[1] +
-                       (double)q[2] * q[2] + (double)q[3] * q[3]);
-      double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
-      double Rq[3][3] = {
+      const double mx = m[0], my = m[1], mz = m[2];
+      const double px = R[0] * mx + R[1] * my + R[2] * mz + (double)v.t[0];
+      const double py = R[3] * mx + R[4] * my + R[5] * mz + (double)v.t[1];
+      const double pz = R[6] * mx + R[7] * my + R[8] * mz + (double)v.t[2];
+      const double iq = 1.0 / sqrt((double)q[0] * q[0] + (double)q[1] * q[1] +
+                                   (double)q[2] * q[2] + (double)q[3] * q[3]);
+      const double w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, z = q[3] * iq;
+      const double Rq[3][3] = {
           {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
           {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
           {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
-      double fx = v.fx, fy = v.fy;
-      double j00 = fx / pz, j02 = -fx * px / (pz * pz);
-      double j11 = fy / pz, j12 = -fy * py / (pz * pz);
-      // T = J R_cam (2x3); A = T R_q diag(s) (2x3); Sigma2D = A A^T
+      const double fx = v.fx, fy = v.fy;
+      const double iz = 1.0 / pz;
+      const double j00 = fx * iz, j02 = -fx * px * iz * iz;
+      const double j11 = fy * iz, j12 = -fy * py * iz * iz;
+      // T = J R_cam (2x3); A = T R_q diag(s) (2x3); Sigma2D = A A^T + 0.3 I
       double T0[3], T1[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -216,38 +244,48 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
       double A0[3], A1[3];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        double sj = s[j];
+        const double sj = s[j];
         A0[j] = (T0[0] * Rq[0][j] + T0[1] * Rq[1][j] + T0[2] * Rq[2][j]) * sj;
         A1[j] = (T1[0] * Rq[0][j] + T1[1] * Rq[1][j] + T1[2] * Rq[2][j]) * sj;
       }
-      double a = A0[0] * A0[0] + A0[1] * A0[1] + A0[2] * A0[2] + 0.3;
-      double b = A0[0] * A1[0] + A0[1] * A1[1] + A0[2] * A1[2];
-      double c = A1[0] * A1[0] + A1[1] * A1[1] + A1[2] * A1[2] + 0.3;
-      double det = a * c - b * b;
-      double cA = c / det, cB = -b / det, cC = a / det;
+      const double a = A0[0] * A0[0] + A0[1] * A0[1] + A0[2] * A0[2] + 0.3;
+      const double b = A0[0] * A1[0] + A0[1] * A1[1] + A0[2] * A1[2];
+      const double c = A1[0] * A1[0] + A1[1] * A1[1] + A1[2] * A1[2] + 0.3;
+      const double idet = 1.0 / (a * c - b * b);
       // log2(alpha) = log2(aleph) - (1/2) log2(e) (cA dx^2 + 2 cB dx dy + cC dy^2)
       const double kL2e = 1.4426950408889634;
-      out.uv[slot] = make_double2(fx * px / pz + (double)v.cx,
-                                  fy * py / pz + (double)v.cy);
-      out.geoA[slot] = make_float4((float)(-0.5 * kL2e * cA), (float)(-kL2e * cB),
-                                   (float)(-0.5 * kL2e * cC), (float)log2((double)aleph));
+      const double u = fx * px * iz + (double)v.cx;
+      const double vv = fy * py * iz + (double)v.cy;
+      const float u_hi = (float)u, v_hi = (float)vv;
       // ---- emission -------------------------------------------------------
-      double ddx = mx - (double)v.campos[0], ddy = my - (double)v.campos[1],
-             ddz = mz - (double)v.campos[2];
-      double dn = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+      const double ddx = mx - (double)v.campos[0], ddy = my - (double)v.campos[1],
+                   ddz = mz - (double)v.campos[2];
+      const double idn = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
       float rgb[3];
-      const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
-      sh_colour(g.sh + (int64_t)i * K * 3, g.sh_degree, (float)(ddx / dn),
-                (float)(ddy / dn), (float)(ddz / dn), rgb);
-      out.geoB[slot] = make_float4(rgb[0], rgb[1], rgb[2], 0.0f);
+      sh_colour<DEG>(s_sh + threadIdx.x * STRIDE, (float)(ddx * idn), (float)(ddy * idn),
+                     (float)(ddz * idn), rgb);
+      // half-extents of the box where alpha >= alpha_min: q <= 2 ln(aleph / alpha_min),
+      // q the Mahalanobis form of Sigma2D; enlarged, rounded up (to +inf beyond the
+      // fp16 range), packed as fp16
+      const double kq = 2.0 * (log((double)aleph) - log((double)alpha_min));
+      const float ex = (float)(sqrt(fmax(kq, 0.0) * a) * 1.001 + 0.01);
+      const float ey = (float)(sqrt(fmax(kq, 0.0) * c) * 1.001 + 0.01);
+      const uint32_t hx = (uint32_t)__half_as_ushort(__float2half_ru(ex));
+      const uint32_t hy = (uint32_t)__half_as_ushort(__float2half_ru(ey));
+      float4* rec = out.rec + 3 * slot;
+      rec[0] = make_float4(u_hi, (float)(u - (double)u_hi), v_hi, (float)(vv - (double)v_hi));
+      rec[1] = make_float4((float)(-0.5 * kL2e * c * idet), (float)(kL2e * b * idet),
+                           (float)(-0.5 * kL2e * a * idet), __log2f(aleph));
+      rec[2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(hx | (hy << 16)));
     }
     out.depth_key[slot] = kg.depth_bits;
     out.ntiles[slot] = nt;
     out.rect[slot] = rect;
+    nt_sum += nt;
   }
   // block reductions: instance total and visible depth-bit range
   __shared__ uint32_t s_sum[kBlock / 64], s_min[kBlock / 64], s_max[kBlock / 64];
-  uint32_t ws = wave_sum_u32(nt), wmn = wave_min_u32(dmin), wmx = wave_max_u32(dmax);
+  uint32_t ws = wave_sum_u32(nt_sum), wmn = wave_min_u32(dmin), wmx = wave_max_u32(dmax);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
     s_sum[wid] = ws;
@@ -285,9 +323,17 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
                     float kappa2, float alpha_min, int tile_w, int tile_h,
                     const ProjDev& out, Counters* counters, hipStream_t s) {
   if (g.n <= 0 || n_views <= 0) return;
-  dim3 grid((g.n + kBlock - 1) / kBlock, n_views);
-  hipLaunchKernelGGL(project_kernel, grid, dim3(kBlock), 0, s, g, views, kappa2,
-                     alpha_min, tile_w, tile_h, out, counters);
+  dim3 grid((g.n + kBlock - 1) / kBlock);
+#define NXS_PROJECT(D)                                                                 \
+  hipLaunchKernelGGL(project_kernel<D>, grid, dim3(kBlock), 0, s, g, views, n_views,  \
+                     kappa2, alpha_min, tile_w, tile_h, out, counters)
+  switch (g.sh_degree) {
+    case 0: NXS_PROJECT(0); break;
+    case 1: NXS_PROJECT(1); break;
+    case 2: NXS_PROJECT(2); break;
+    default: NXS_PROJECT(3); break;
+  }
+#undef NXS_PROJECT
 }
 
 }  // namespace nxs

@@ -18,6 +18,8 @@
 //   scatter per chunk: digit bases from the totals, stable local ranks via
 //           wave ballots, a local reorder in LDS, then coalesced stores.
 // No kernel waits on another work-group, so no launch can deadlock.
+#include <hip/hip_fp16.h>
+
 #include "nxs_internal.h"
 
 namespace nxs {
@@ -307,8 +309,8 @@ __device__ __forceinline__ int view_of_tile(const ViewDev* views, int n_views, u
 __global__ __launch_bounds__(256) void ranges_gather_kernel(
     const uint32_t* __restrict__ inst_tile, const uint32_t* __restrict__ inst_val,
     int64_t m, ProjDev proj, const ViewDev* __restrict__ views, int n_views, int tile_w,
-    int tile_h, uint2* __restrict__ ranges, float4* __restrict__ rec0,
-    float4* __restrict__ rec1, float* __restrict__ rec2) {
+    int tile_h, float log2_alpha_min, uint2* __restrict__ ranges,
+    float4* __restrict__ crec) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const uint32_t tile = inst_tile[j];
@@ -319,15 +321,32 @@ __global__ __launch_bounds__(256) void ranges_gather_kernel(
   const ViewDev& v = views[vi];
   const int lt = (int)(tile - (uint32_t)v.tile_off);
   const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
-  const double2 uv = proj.uv[slot];
-  const float4 ga = proj.geoA[slot];
-  const float4 gb = proj.geoB[slot];
-  // centre relative to the tile's corner: small numbers keep float32 exact enough
-  const float du = (float)(uv.x - (double)(tx * tile_w));
-  const float dv = (float)(uv.y - (double)(ty * tile_h));
-  rec0[j] = make_float4(du, dv, ga.x, ga.y);
-  rec1[j] = make_float4(ga.z, ga.w, gb.x, gb.y);
-  rec2[j] = gb.z;
+  const float4 r0 = proj.rec[3 * (int64_t)slot + 0];
+  const float4 r1 = proj.rec[3 * (int64_t)slot + 1];
+  const float4 r2 = proj.rec[3 * (int64_t)slot + 2];
+  // centre relative to the tile corner: (hi - corner) is exact, then + lo
+  const float du = (r0.x - (float)(tx * tile_w)) + r0.y;
+  const float dv = (r0.z - (float)(ty * tile_h)) + r0.w;
+  // half-extents of the alpha >= alpha_min box, packed as two fp16 (rounded up)
+  const uint32_t hx = __float_as_uint(r2.w);
+  const float rx = __half2float(__ushort_as_half((unsigned short)(hx & 0xFFFFu)));
+  const float ry = __half2float(__ushort_as_half((unsigned short)(hx >> 16)));
+  // which 8x8 pixel blocks of the tile (bit by * (tile_w / 8) + bx) the box
+  // reaches, judged at pixel centres; the composite's waves skip the others
+  uint32_t mask = 0;
+  const int nbx = tile_w >> 3, nby = tile_h >> 3;
+  for (int by = 0; by < nby; ++by) {
+    const float y0 = (float)(8 * by) + 0.5f, y1 = (float)(8 * by) + 7.5f;
+    if (dv - ry > y1 || dv + ry < y0) continue;
+    for (int bx = 0; bx < nbx; ++bx) {
+      const float x0 = (float)(8 * bx) + 0.5f, x1 = (float)(8 * bx) + 7.5f;
+      if (du - rx > x1 || du + rx < x0) continue;
+      mask |= 1u << (by * nbx + bx);
+    }
+  }
+  crec[3 * j + 0] = make_float4(du, dv, r1.x, r1.y);
+  crec[3 * j + 1] = make_float4(r1.z, r1.w, r2.x, r2.y);
+  crec[3 * j + 2] = make_float4(r2.z, __uint_as_float(mask), 0.0f, 0.0f);
 }
 
 }  // namespace
@@ -397,12 +416,12 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {
 
 void launch_ranges_gather(const uint32_t* inst_tile, const uint32_t* inst_val, int64_t m,
                           const ProjDev& proj, const ViewDev* views, int n_views,
-                          int tile_w, int tile_h, uint2* ranges, float4* rec0,
-                          float4* rec1, float* rec2, hipStream_t s) {
+                          int tile_w, int tile_h, float log2_alpha_min, uint2* ranges,
+                          float4* crec, hipStream_t s) {
   if (m <= 0) return;
   hipLaunchKernelGGL(ranges_gather_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0,
                      s, inst_tile, inst_val, m, proj, views, n_views, tile_w, tile_h,
-                     ranges, rec0, rec1, rec2);
+                     log2_alpha_min, ranges, crec);
 }
 
 }  // namespace nxs

@@ -282,7 +282,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
     HIP_TRY(mark(3));
     // 2. emission in depth order
     launch_emit(sorted_slots, S, g->n, proj, dviews, P<uint32_t>(ctx->scan_local),
-                P<uint32_t>(ctx->block_sums), inst_tile, inst_val, s);
+                P<uint32_t>(ctx->block_sums), (uint32_t)M, inst_tile, inst_val, s);
     HIP_TRY(mark(4));
     // 3. stable sort by global tile
     const int tbits = bit_length((uint64_t)(total_tiles - 1));

@@ -67,8 +67,8 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
 size_t scan_blocks_size(int64_t n);
 void launch_emit(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
                  const ProjDev& proj, const ViewDev* views, uint32_t* scan_local,
-                 uint32_t* block_sums, uint32_t* inst_tile, uint32_t* inst_val,
-                 hipStream_t s);
+                 uint32_t* block_sums, uint32_t total, uint32_t* inst_tile,
+                 uint32_t* inst_val, hipStream_t s);
 
 // dst[i] = src[i], idx[i] = i.
 void launch_iota_copy(const uint32_t* src, uint32_t* dst, uint32_t* idx, int64_t n,

@@ -184,10 +184,39 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   const int base = blockIdx.x * kBlock;
   const int cnt = min(kBlock, g.n - base);
   {
+    // every load of the block's coefficients is issued before any is used:
+    // NC/4 float4 per thread (the region is 16-byte aligned when sh is)
     const float* src = g.sh + (int64_t)base * NC;
-    for (int e = threadIdx.x; e < cnt * NC; e += kBlock) {
-      const int gi = e / NC, j = e - gi * NC;
-      s_sh[gi * STRIDE + j] = src[e];
+    const int nf = cnt * NC;
+    constexpr int kIter = (kBlock * NC / 4 + kBlock - 1) / kBlock;
+    if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0) {
+      float4 buf[kIter];
+#pragma unroll
+      for (int r = 0; r < kIter; ++r) {
+        const int f = 4 * (r * kBlock + threadIdx.x);
+        buf[r] = f + 3 < nf ? *reinterpret_cast<const float4*>(src + f)
+                            : make_float4(f < nf ? src[f] : 0.0f,
+                                          f + 1 < nf ? src[f + 1] : 0.0f,
+                                          f + 2 < nf ? src[f + 2] : 0.0f, 0.0f);
+      }
+#pragma unroll
+      for (int r = 0; r < kIter; ++r) {
+        const int f = 4 * (r * kBlock + threadIdx.x);
+        const float vals[4] = {buf[r].x, buf[r].y, buf[r].z, buf[r].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int e = f + c;
+          if (e < nf) {
+            const int gi = e / NC, j = e - gi * NC;
+            s_sh[gi * STRIDE + j] = vals[c];
+          }
+        }
+      }
+    } else {
+      for (int e = threadIdx.x; e < nf; e += kBlock) {
+        const int gi = e / NC, j = e - gi * NC;
+        s_sh[gi * STRIDE + j] = src[e];
+      }
     }
   }
   __syncthreads();
@@ -267,15 +296,16 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
       // half-extents of the box where alpha >= alpha_min: q <= 2 ln(aleph / alpha_min),
       // q the Mahalanobis form of Sigma2D; enlarged, rounded up (to +inf beyond the
       // fp16 range), packed as fp16
-      const double kq = 2.0 * (log((double)aleph) - log((double)alpha_min));
-      const float ex = (float)(sqrt(fmax(kq, 0.0) * a) * 1.001 + 0.01);
-      const float ey = (float)(sqrt(fmax(kq, 0.0) * c) * 1.001 + 0.01);
+      const float lo2 = __log2f(aleph);
+      const float kq = fmaxf(2.0f * 0.6931471805599453f * (lo2 - __log2f(alpha_min)), 0.0f);
+      const float ex = sqrtf(kq * (float)a) * 1.001f + 0.01f;
+      const float ey = sqrtf(kq * (float)c) * 1.001f + 0.01f;
       const uint32_t hx = (uint32_t)__half_as_ushort(__float2half_ru(ex));
       const uint32_t hy = (uint32_t)__half_as_ushort(__float2half_ru(ey));
       float4* rec = out.rec + 3 * slot;
       rec[0] = make_float4(u_hi, (float)(u - (double)u_hi), v_hi, (float)(vv - (double)v_hi));
       rec[1] = make_float4((float)(-0.5 * kL2e * c * idet), (float)(kL2e * b * idet),
-                           (float)(-0.5 * kL2e * a * idet), __log2f(aleph));
+                           (float)(-0.5 * kL2e * a * idet), lo2);
       rec[2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(hx | (hy << 16)));
     }
     out.depth_key[slot] = kg.depth_bits;

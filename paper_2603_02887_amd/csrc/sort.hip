@@ -27,6 +27,7 @@ namespace nxs {
 namespace {
 
 constexpr int kSortBlock = 256;
+constexpr uint32_t kXcds = 8;   // accelerator complex dies of an MI355X
 constexpr int kItems = 16;
 constexpr int kChunk = kSortBlock * kItems;  // 4096
 constexpr int kRadix = 256;
@@ -255,29 +256,46 @@ __global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(uint32_t* __res
   }
 }
 
-// One thread per sorted slot: write its (global tile, slot) instances.
+// One work-group per 1024 sorted slots writes all of their instances as one
+// contiguous run: each output position finds its slot by binary search over
+// the block's offsets in LDS, so consecutive threads write consecutive
+// addresses however unevenly the Gaussians' tile counts are spread.
 __global__ __launch_bounds__(kScanBlock) void emit_kernel(
     const uint32_t* __restrict__ sorted_slots, int64_t n, int32_t n_gauss,
-    const uint32_t* __restrict__ ntiles, const uint2* __restrict__ rect,
-    const ViewDev* __restrict__ views, const uint32_t* __restrict__ local,
-    const uint32_t* __restrict__ block_off, uint32_t* __restrict__ inst_tile,
-    uint32_t* __restrict__ inst_val) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t slot = sorted_slots[i];
-  const uint32_t nt = ntiles[slot];
-  if (nt == 0) return;
-  uint32_t off = block_off[i / kScanChunk] + local[i];
-  const uint2 r = rect[slot];
-  const int tx0 = r.x & 0xFFFF, tx1 = r.x >> 16, ty0 = r.y & 0xFFFF, ty1 = r.y >> 16;
-  const ViewDev& v = views[slot / (uint32_t)n_gauss];
-  for (int ty = ty0; ty <= ty1; ++ty) {
-    const uint32_t row = (uint32_t)(v.tile_off + ty * v.tiles_x);
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      inst_tile[off] = row + (uint32_t)tx;
-      inst_val[off] = slot;
-      ++off;
+    const uint2* __restrict__ rect, const ViewDev* __restrict__ views,
+    const uint32_t* __restrict__ local, const uint32_t* __restrict__ block_off,
+    uint32_t total, uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_val) {
+  __shared__ uint32_t s_off[kScanChunk + 1];
+  __shared__ uint32_t s_slot[kScanChunk];
+  __shared__ uint2 s_rect[kScanChunk];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
+  const int cnt = (int)min((int64_t)kScanChunk, n - b0);
+  const uint32_t out0 = block_off[blockIdx.x];
+  const uint32_t out1 = (b0 + kScanChunk < n) ? block_off[blockIdx.x + 1] : total;
+  for (int k = threadIdx.x; k < cnt; k += kScanBlock) {
+    const uint32_t slot = sorted_slots[b0 + k];
+    s_slot[k] = slot;
+    s_off[k] = local[b0 + k];
+    s_rect[k] = rect[slot];
+  }
+  if (threadIdx.x == 0) s_off[cnt] = out1 - out0;
+  __syncthreads();
+  const uint32_t tot = out1 - out0;
+  for (uint32_t q = threadIdx.x; q < tot; q += kScanBlock) {
+    int lo = 0, hi = cnt - 1;   // last slot whose offset is <= q (it has q inside)
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= q) lo = mid; else hi = mid - 1;
     }
+    const uint32_t slot = s_slot[lo];
+    const uint2 r = s_rect[lo];
+    const int tx0 = r.x & 0xFFFF, tx1 = r.x >> 16, ty0 = r.y & 0xFFFF;
+    const int w = tx1 - tx0 + 1;
+    const int l = (int)(q - s_off[lo]);
+    const ViewDev& v = views[slot / (uint32_t)n_gauss];
+    inst_tile[out0 + q] =
+        (uint32_t)(v.tile_off + (ty0 + l / w) * v.tiles_x + tx0 + l % w);
+    inst_val[out0 + q] = slot;
   }
 }
 
@@ -310,8 +328,12 @@ __global__ __launch_bounds__(256) void ranges_gather_kernel(
     const uint32_t* __restrict__ inst_tile, const uint32_t* __restrict__ inst_val,
     int64_t m, ProjDev proj, const ViewDev* __restrict__ views, int n_views, int tile_w,
     int tile_h, float log2_alpha_min, uint2* __restrict__ ranges,
-    float4* __restrict__ crec) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float4* __restrict__ crec, uint32_t per_xcd) {
+  // Work-groups go to the 8 XCDs round-robin; give each XCD one contiguous
+  // eighth of the sorted list (a band of tile rows), so that the records of
+  // Gaussians shared by neighbouring tiles are re-read from that XCD's L2.
+  const uint32_t lb = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  const int64_t j = (int64_t)lb * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const uint32_t tile = inst_tile[j];
   if (j == 0 || inst_tile[j - 1] != tile) ranges[tile].x = (uint32_t)j;
@@ -387,17 +409,16 @@ size_t scan_blocks_size(int64_t n) {
 
 void launch_emit(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
                  const ProjDev& proj, const ViewDev* views, uint32_t* scan_local,
-                 uint32_t* block_sums, uint32_t* inst_tile, uint32_t* inst_val,
-                 hipStream_t s) {
+                 uint32_t* block_sums, uint32_t total, uint32_t* inst_tile,
+                 uint32_t* inst_val, hipStream_t s) {
   if (n_slots <= 0) return;
   const int nblocks = (int)((n_slots + kScanChunk - 1) / kScanChunk);
   hipLaunchKernelGGL(scan_local_kernel, dim3(nblocks), dim3(kScanBlock), 0, s,
                      sorted_slots, n_slots, proj.ntiles, scan_local, block_sums);
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanBlock), 0, s, block_sums,
                      nblocks);
-  const int eb = (int)((n_slots + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(emit_kernel, dim3(eb), dim3(kScanBlock), 0, s, sorted_slots, n_slots,
-                     n_gauss, proj.ntiles, proj.rect, views, scan_local, block_sums,
+  hipLaunchKernelGGL(emit_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, sorted_slots,
+                     n_slots, n_gauss, proj.rect, views, scan_local, block_sums, total,
                      inst_tile, inst_val);
 }
 
@@ -419,9 +440,11 @@ void launch_ranges_gather(const uint32_t* inst_tile, const uint32_t* inst_val, i
                           int tile_w, int tile_h, float log2_alpha_min, uint2* ranges,
                           float4* crec, hipStream_t s) {
   if (m <= 0) return;
-  hipLaunchKernelGGL(ranges_gather_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0,
-                     s, inst_tile, inst_val, m, proj, views, n_views, tile_w, tile_h,
-                     log2_alpha_min, ranges, crec);
+  const uint32_t nb = (uint32_t)((m + 255) / 256);
+  const uint32_t per = (nb + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(ranges_gather_kernel, dim3(per * kXcds), dim3(256), 0, s, inst_tile,
+                     inst_val, m, proj, views, n_views, tile_w, tile_h, log2_alpha_min,
+                     ranges, crec, per);
 }
 
 }  // namespace nxs

@@ -26,7 +26,7 @@ struct nxs_context {
   int device = 0;
   std::string err;
   // workspace
-  DevBuf views, counters;
+  DevBuf views, counters, partials;
   DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, ntiles, rect, prec;
   DevBuf scan_local, block_sums, counts;
   DevBuf inst_tile, inst_tile_alt, inst_val, inst_val_alt;
@@ -129,7 +129,7 @@ nxs_status nxs_destroy(nxs_context* ctx) {
   if (!ctx) return NXS_EINVAL;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  DevBuf* all[] = {&ctx->views,      &ctx->counters,      &ctx->depth_key, &ctx->dsort_a, &ctx->dsort_b,
+  DevBuf* all[] = {&ctx->views,      &ctx->counters,      &ctx->partials,      &ctx->depth_key, &ctx->dsort_a, &ctx->dsort_b,
                    &ctx->slot_a,     &ctx->slot_b,        &ctx->ntiles,    &ctx->rect,
                    &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
@@ -221,6 +221,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   nxs_status st;
   if ((st = ensure(ctx, ctx->views, sizeof(ViewDev) * n_views))) return st;
   if ((st = ensure(ctx, ctx->counters, sizeof(Counters)))) return st;
+  if ((st = ensure(ctx, ctx->partials, sizeof(uint4) * project_partials_size(g->n)))) return st;
   HIP_TRY(hipMemcpyAsync(ctx->views.p, ctx->host_views, sizeof(ViewDev) * n_views,
                          hipMemcpyHostToDevice, s));
   const ViewDev* dviews = P<ViewDev>(ctx->views);
@@ -244,7 +245,8 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   ctx->ev_valid = false;
   HIP_TRY(mark(0));
   launch_init_counters(dcount, s);
-  launch_project(gd, dviews, n_views, kappa2, alpha_min, tw, th, proj, dcount, s);
+  launch_project(gd, dviews, n_views, kappa2, alpha_min, tw, th, proj,
+                 P<uint4>(ctx->partials), dcount, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(1));
   HIP_TRY(hipMemcpyAsync(ctx->host_counters, dcount, sizeof(Counters), hipMemcpyDeviceToHost, s));

@@ -51,9 +51,11 @@ struct Counters {
 
 // ---- launchers (all enqueue on `s`) ------------------------------------------
 void launch_init_counters(Counters* c, hipStream_t s);
+// `partials` needs project_partials_size(n) entries.
+size_t project_partials_size(int n);
 void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
                     float kappa2, float alpha_min, int tile_w, int tile_h,
-                    const ProjDev& out, Counters* counters, hipStream_t s);
+                    const ProjDev& out, uint4* partials, Counters* counters, hipStream_t s);
 
 // Stable LSD radix sort of (u32 key, u32 value) pairs on key bits [0, nbits).
 // Returns 0 if the result is in (keys, vals), 1 if in (keys_alt, vals_alt).

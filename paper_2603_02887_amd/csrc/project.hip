@@ -5,9 +5,10 @@
 //     evaluated operation by operation in a fixed order with no fused
 //     multiply-add, so that which tiles a Gaussian lands in, and at which
 //     depth key, is reproducible bit for bit;
-//   * the footprint used by the composite (Sec. 3: alpha = aleph * K), in
-//     FP64: centre, 2D covariance with 0.3 px^2 dilation and its inverse,
-//     folded into the exponent coefficients of log2(alpha).
+//   * the footprint used by the composite (Sec. 3: alpha = aleph * K): the
+//     2D covariance with 0.3 px^2 dilation and its inverse, folded into the
+//     exponent coefficients of log2(alpha); the centre in FP64, so that the
+//     composite's pixel offsets keep ~1e-7 px accuracy.
 // The emission is the real SH expansion (degree <= 3) at the direction from
 // the camera centre to the mean, plus 1/2, clamped at 0.
 //
@@ -27,6 +28,7 @@ struct KeyGeom {
   bool visible;
   uint32_t depth_bits;
   int tx0, tx1, ty0, ty1;
+  float A0[3], A1[3];   // J R R_q diag(s): Sigma2D = A A^T + 0.3 I
 };
 
 __device__ __forceinline__ KeyGeom key_recipe(const float* m, const float* s,
@@ -78,6 +80,11 @@ __device__ __forceinline__ KeyGeom key_recipe(const float* m, const float* s,
   for (int j = 0; j < 3; ++j) {
     A0[j] = j00 * G[0][j] + j02 * G[2][j];
     A1[j] = j11 * G[1][j] + j12 * G[2][j];
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    out.A0[j] = A0[j];
+    out.A1[j] = A1[j];
   }
   float a = ((A0[0] * A0[0] + A0[1] * A0[1]) + A0[2] * A0[2]) + 0.3f;
   float c = ((A1[0] * A1[0] + A1[1] * A1[1]) + A1[2] * A1[2]) + 0.3f;
@@ -176,7 +183,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void project_kernel(
     GaussDev g, const ViewDev* __restrict__ views, int n_views, float kappa2,
-    float alpha_min, int tile_w, int tile_h, ProjDev out, Counters* __restrict__ counters) {
+    float alpha_min, int tile_w, int tile_h, ProjDev out, uint4* __restrict__ partials) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr int NC = 3 * K;
   constexpr int STRIDE = NC + 1;
@@ -244,68 +251,53 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
       dmax = max(dmax, kg.depth_bits);
       rect = make_uint2((uint32_t)kg.tx0 | ((uint32_t)kg.tx1 << 16),
                         (uint32_t)kg.ty0 | ((uint32_t)kg.ty1 << 16));
-      // ---- composite footprint in FP64 -----------------------------------
-      double R[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) R[k] = (double)v.R[k];
-      const double mx = m[0], my = m[1], mz = m[2];
-      const double px = R[0] * mx + R[1] * my + R[2] * mz + (double)v.t[0];
-      const double py = R[3] * mx + R[4] * my + R[5] * mz + (double)v.t[1];
-      const double pz = R[6] * mx + R[7] * my + R[8] * mz + (double)v.t[2];
-      const double iq = 1.0 / sqrt((double)q[0] * q[0] + (double)q[1] * q[1] +
-                                   (double)q[2] * q[2] + (double)q[3] * q[3]);
-      const double w = q[0] * iq, x = q[1] * iq, y = q[2] * iq, z = q[3] * iq;
-      const double Rq[3][3] = {
-          {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
-          {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
-          {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
-      const double fx = v.fx, fy = v.fy;
-      const double iz = 1.0 / pz;
-      const double j00 = fx * iz, j02 = -fx * px * iz * iz;
-      const double j11 = fy * iz, j12 = -fy * py * iz * iz;
-      // T = J R_cam (2x3); A = T R_q diag(s) (2x3); Sigma2D = A A^T + 0.3 I
-      double T0[3], T1[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        T0[k] = j00 * R[k] + j02 * R[6 + k];
-        T1[k] = j11 * R[3 + k] + j12 * R[6 + k];
-      }
-      double A0[3], A1[3];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const double sj = s[j];
-        A0[j] = (T0[0] * Rq[0][j] + T0[1] * Rq[1][j] + T0[2] * Rq[2][j]) * sj;
-        A1[j] = (T1[0] * Rq[0][j] + T1[1] * Rq[1][j] + T1[2] * Rq[2][j]) * sj;
-      }
-      const double a = A0[0] * A0[0] + A0[1] * A0[1] + A0[2] * A0[2] + 0.3;
-      const double b = A0[0] * A1[0] + A0[1] * A1[1] + A0[2] * A1[2];
-      const double c = A1[0] * A1[0] + A1[1] * A1[1] + A1[2] * A1[2] + 0.3;
-      const double idet = 1.0 / (a * c - b * b);
+      // ---- composite footprint ----------------------------------------------
+      // Sigma2D = A A^T + 0.3 I from the recipe's A (float32).  Its determinant
+      // by Cauchy-Binet, |A0 x A1|^2 + 0.3 (|A0|^2 + |A1|^2) + 0.09, is a sum
+      // of non-negative terms: no cancellation, however elongated the splat.
+      const float* A0 = kg.A0;
+      const float* A1 = kg.A1;
+      const float aa = A0[0] * A0[0] + A0[1] * A0[1] + A0[2] * A0[2];
+      const float cc = A1[0] * A1[0] + A1[1] * A1[1] + A1[2] * A1[2];
+      const float bb = A0[0] * A1[0] + A0[1] * A1[1] + A0[2] * A1[2];
+      const float x0 = A0[1] * A1[2] - A0[2] * A1[1];
+      const float x1 = A0[2] * A1[0] - A0[0] * A1[2];
+      const float x2 = A0[0] * A1[1] - A0[1] * A1[0];
+      const float a = aa + 0.3f, c = cc + 0.3f;
+      const float det = (x0 * x0 + x1 * x1 + x2 * x2) + 0.3f * (aa + cc) + 0.09f;
+      const float idet = 1.0f / det;
       // log2(alpha) = log2(aleph) - (1/2) log2(e) (cA dx^2 + 2 cB dx dy + cC dy^2)
-      const double kL2e = 1.4426950408889634;
-      const double u = fx * px * iz + (double)v.cx;
-      const double vv = fy * py * iz + (double)v.cy;
+      const float kL2e = 1.4426950408889634f;
+      // image-plane centre in FP64 (kept as float hi + lo for the composite)
+      const double px = ((double)v.R[0] * m[0] + (double)v.R[1] * m[1]) +
+                        ((double)v.R[2] * m[2] + (double)v.t[0]);
+      const double py = ((double)v.R[3] * m[0] + (double)v.R[4] * m[1]) +
+                        ((double)v.R[5] * m[2] + (double)v.t[1]);
+      const double pz = ((double)v.R[6] * m[0] + (double)v.R[7] * m[1]) +
+                        ((double)v.R[8] * m[2] + (double)v.t[2]);
+      const double iz = 1.0 / pz;
+      const double u = (double)v.fx * px * iz + (double)v.cx;
+      const double vv = (double)v.fy * py * iz + (double)v.cy;
       const float u_hi = (float)u, v_hi = (float)vv;
       // ---- emission -------------------------------------------------------
-      const double ddx = mx - (double)v.campos[0], ddy = my - (double)v.campos[1],
-                   ddz = mz - (double)v.campos[2];
-      const double idn = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+      const float ddx = m[0] - v.campos[0], ddy = m[1] - v.campos[1],
+                  ddz = m[2] - v.campos[2];
+      const float idn = 1.0f / sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
       float rgb[3];
-      sh_colour<DEG>(s_sh + threadIdx.x * STRIDE, (float)(ddx * idn), (float)(ddy * idn),
-                     (float)(ddz * idn), rgb);
+      sh_colour<DEG>(s_sh + threadIdx.x * STRIDE, ddx * idn, ddy * idn, ddz * idn, rgb);
       // half-extents of the box where alpha >= alpha_min: q <= 2 ln(aleph / alpha_min),
       // q the Mahalanobis form of Sigma2D; enlarged, rounded up (to +inf beyond the
       // fp16 range), packed as fp16
       const float lo2 = __log2f(aleph);
       const float kq = fmaxf(2.0f * 0.6931471805599453f * (lo2 - __log2f(alpha_min)), 0.0f);
-      const float ex = sqrtf(kq * (float)a) * 1.001f + 0.01f;
-      const float ey = sqrtf(kq * (float)c) * 1.001f + 0.01f;
+      const float ex = sqrtf(kq * a) * 1.001f + 0.01f;
+      const float ey = sqrtf(kq * c) * 1.001f + 0.01f;
       const uint32_t hx = (uint32_t)__half_as_ushort(__float2half_ru(ex));
       const uint32_t hy = (uint32_t)__half_as_ushort(__float2half_ru(ey));
       float4* rec = out.rec + 3 * slot;
       rec[0] = make_float4(u_hi, (float)(u - (double)u_hi), v_hi, (float)(vv - (double)v_hi));
-      rec[1] = make_float4((float)(-0.5 * kL2e * c * idet), (float)(kL2e * b * idet),
-                           (float)(-0.5 * kL2e * a * idet), lo2);
+      rec[1] = make_float4(-0.5f * kL2e * c * idet, kL2e * bb * idet,
+                           -0.5f * kL2e * a * idet, lo2);
       rec[2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(hx | (hy << 16)));
     }
     out.depth_key[slot] = kg.depth_bits;
@@ -324,16 +316,53 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long tot = 0;
-    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+    uint32_t tot = 0, mn = 0xFFFFFFFFu, mx = 0u;
     for (int k = 0; k < kBlock / 64; ++k) {
       tot += s_sum[k];
       mn = min(mn, s_min[k]);
       mx = max(mx, s_max[k]);
     }
-    if (tot) atomicAdd(&counters->total, tot);
-    if (mn != 0xFFFFFFFFu) atomicMin(&counters->dmin, mn);
-    if (mx) atomicMax(&counters->dmax, mx);
+    // one partial per block (no same-address atomics across thousands of blocks)
+    partials[blockIdx.x] = make_uint4(tot, mn, mx, 0u);
+  }
+}
+
+// One work-group folds the per-block partials into the counters read by the host.
+__global__ __launch_bounds__(1024) void reduce_counters_kernel(const uint4* __restrict__ partials,
+                                                               int nblocks,
+                                                               Counters* __restrict__ c) {
+  __shared__ unsigned long long s_tot[16];
+  __shared__ uint32_t s_mn[16], s_mx[16];
+  unsigned long long tot = 0;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  for (int b = threadIdx.x; b < nblocks; b += 1024) {
+    const uint4 p = partials[b];
+    tot += p.x;
+    mn = min(mn, p.y);
+    mx = max(mx, p.z);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    tot += __shfl_xor(tot, o, 64);
+    mn = min(mn, (uint32_t)__shfl_xor(mn, o, 64));
+    mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_tot[wid] = tot;
+    s_mn[wid] = mn;
+    s_mx[wid] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) {
+      tot += s_tot[w];
+      mn = min(mn, s_mn[w]);
+      mx = max(mx, s_mx[w]);
+    }
+    c->total = tot;
+    c->dmin = mn;
+    c->dmax = mx;
   }
 }
 
@@ -351,12 +380,12 @@ void launch_init_counters(Counters* c, hipStream_t s) {
 
 void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
                     float kappa2, float alpha_min, int tile_w, int tile_h,
-                    const ProjDev& out, Counters* counters, hipStream_t s) {
+                    const ProjDev& out, uint4* partials, Counters* counters, hipStream_t s) {
   if (g.n <= 0 || n_views <= 0) return;
   dim3 grid((g.n + kBlock - 1) / kBlock);
 #define NXS_PROJECT(D)                                                                 \
   hipLaunchKernelGGL(project_kernel<D>, grid, dim3(kBlock), 0, s, g, views, n_views,  \
-                     kappa2, alpha_min, tile_w, tile_h, out, counters)
+                     kappa2, alpha_min, tile_w, tile_h, out, partials)
   switch (g.sh_degree) {
     case 0: NXS_PROJECT(0); break;
     case 1: NXS_PROJECT(1); break;
@@ -364,6 +393,10 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
     default: NXS_PROJECT(3); break;
   }
 #undef NXS_PROJECT
+  hipLaunchKernelGGL(reduce_counters_kernel, dim3(1), dim3(1024), 0, s, partials,
+                     (int)grid.x, counters);
 }
+
+size_t project_partials_size(int n) { return (size_t)((n + kBlock - 1) / kBlock) + 1; }
 
 }  // namespace nxs

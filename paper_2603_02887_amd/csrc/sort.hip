@@ -11,7 +11,8 @@
 // single sort on the 64-bit key (tile << 32 | depth bits) with ties by index,
 // while moving 32-bit keys over fewer bits.
 //
-// Radix sort: reduce-then-scan, 8-bit digits, 4096 keys per work-group chunk.
+// Radix sort: reduce-then-scan with digits of up to 9 bits (as few passes as
+// that allows, widths balanced) and 2048 keys per work-group chunk.
 //   count   per chunk and digit            counts[d * nchunks + c]
 //   scan    per digit over chunks (one WG per digit) -> exclusive offsets,
 //           digit totals
@@ -28,9 +29,11 @@ namespace {
 
 constexpr int kSortBlock = 256;
 constexpr uint32_t kXcds = 8;   // accelerator complex dies of an MI355X
-constexpr int kItems = 16;
-constexpr int kChunk = kSortBlock * kItems;  // 4096
-constexpr int kRadix = 256;
+constexpr int kItems = 8;
+constexpr int kChunk = kSortBlock * kItems;  // 2048 keys per work-group
+constexpr int kRadixBits = 9;                // digits of up to 9 bits
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kPer = kRadix / kSortBlock;    // digits per thread in digit-wide loops
 
 __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift, uint32_t mask) {
   return (k >> shift) & mask;
@@ -41,16 +44,24 @@ __global__ __launch_bounds__(kSortBlock) void rs_count(const uint32_t* __restric
                                                        int nchunks,
                                                        uint32_t* __restrict__ counts) {
   __shared__ uint32_t hist[kRadix];
-  hist[threadIdx.x] = 0;
+  const uint32_t nd = mask + 1;
+  for (uint32_t d = threadIdx.x; d < nd; d += kSortBlock) hist[d] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kChunk;
+  uint32_t k[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    int64_t idx = base + r * kSortBlock + threadIdx.x;
-    if (idx < n) atomicAdd(&hist[digit_of(keys[idx], shift, mask)], 1u);
+    const int64_t idx = base + r * kSortBlock + threadIdx.x;
+    k[r] = idx < n ? keys[idx] : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t idx = base + r * kSortBlock + threadIdx.x;
+    if (idx < n) atomicAdd(&hist[digit_of(k[r], shift, mask)], 1u);
   }
   __syncthreads();
-  counts[(int64_t)threadIdx.x * nchunks + blockIdx.x] = hist[threadIdx.x];
+  for (uint32_t d = threadIdx.x; d < nd; d += kSortBlock)
+    counts[(int64_t)d * nchunks + blockIdx.x] = hist[d];
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads).
@@ -106,90 +117,115 @@ __global__ __launch_bounds__(kSortBlock) void rs_scan_digit(uint32_t* __restrict
   if (threadIdx.x == 0) totals[blockIdx.x] = running;
 }
 
+// Stable scatter of one 2048-key chunk.  Each wave ranks its own contiguous
+// quarter of the chunk (8 rounds of 64 keys) by matching digits with one
+// ballot per digit bit, keeping its running digit counts in its own LDS row,
+// so the rounds need no barriers.  The waves' counts then give every key its
+// place in the chunk; the chunk is reordered by digit in LDS and written out
+// in runs (coalesced).
 __global__ __launch_bounds__(kSortBlock) void rs_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n,
-    int shift, uint32_t mask, int nchunks, const uint32_t* __restrict__ counts,
+    int shift, int width, int nchunks, const uint32_t* __restrict__ counts,
     const uint32_t* __restrict__ totals) {
+  constexpr int kWaves = kSortBlock / 64;
+  constexpr int kPerWave = kChunk / kWaves;   // 512 keys, 8 rounds of 64
   __shared__ uint32_t s_key[kChunk];
   __shared__ uint32_t s_val[kChunk];
   __shared__ uint32_t s_gbase[kRadix];   // global position of this chunk's digit run
   __shared__ uint32_t s_lbase[kRadix];   // local (in-chunk) start of the digit run
-  __shared__ uint32_t s_run[kRadix];     // keys of this digit placed so far
-  __shared__ uint32_t s_wave[kSortBlock / 64][kRadix];
-  __shared__ uint32_t s_tmp[kSortBlock / 64];
+  __shared__ uint32_t s_wave[kWaves][kRadix];
+  __shared__ uint32_t s_tmp[kWaves];
 
   const int t = threadIdx.x;
   const int c = blockIdx.x;
+  const int lane = t & 63, wid = t >> 6;
+  const uint32_t mask = (1u << width) - 1u;
+  const int nd = 1 << width;
   const int64_t base = (int64_t)c * kChunk;
   const int chunk_n = (int)min((int64_t)kChunk, n - base);
-
-  // digit bases: exclusive scan of the digit totals + this chunk's offset
-  uint32_t dtot;
-  uint32_t dbase = block_exclusive_scan(totals[t], s_tmp, &dtot);
-  uint32_t off_c = counts[(int64_t)t * nchunks + c];
-  uint32_t next = (c + 1 < nchunks) ? counts[(int64_t)t * nchunks + c + 1] : totals[t];
-  uint32_t local_cnt = next - off_c;
-  uint32_t lb;
-  uint32_t ltot;
-  lb = block_exclusive_scan(local_cnt, s_tmp, &ltot);
-  s_gbase[t] = dbase + off_c;
-  s_lbase[t] = lb;
-  s_run[t] = 0;
-#pragma unroll
-  for (int w = 0; w < kSortBlock / 64; ++w) s_wave[w][t] = 0;
 
   uint32_t k_reg[kItems], v_reg[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    int li = r * kSortBlock + t;
+    const int li = wid * kPerWave + r * 64 + lane;
     if (li < chunk_n) {
       k_reg[r] = keys_in[base + li];
       v_reg[r] = vals_in[base + li];
     }
   }
+  // digit bases: exclusive scans over digits (kPer consecutive digits per thread)
+  {
+    uint32_t tot_d[kPer], loc_d[kPer], off_d[kPer];
+    uint32_t st = 0, sl = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int d = t * kPer + q;
+      if (d < nd) {
+        tot_d[q] = totals[d];
+        off_d[q] = counts[(int64_t)d * nchunks + c];
+        const uint32_t next =
+            (c + 1 < nchunks) ? counts[(int64_t)d * nchunks + c + 1] : tot_d[q];
+        loc_d[q] = next - off_d[q];
+      } else {
+        tot_d[q] = loc_d[q] = off_d[q] = 0;
+      }
+      st += tot_d[q];
+      sl += loc_d[q];
+    }
+    uint32_t dummy;
+    uint32_t ex_t = block_exclusive_scan(st, s_tmp, &dummy);
+    uint32_t ex_l = block_exclusive_scan(sl, s_tmp, &dummy);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int d = t * kPer + q;
+      s_gbase[d] = ex_t + off_d[q];
+      s_lbase[d] = ex_l;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) s_wave[w][d] = 0;
+      ex_t += tot_d[q];
+      ex_l += loc_d[q];
+    }
+  }
   __syncthreads();
 
-  const int lane = t & 63, wid = t >> 6;
+  // per-wave ranking: rank[r] = keys of the same digit earlier in this wave's quarter
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  // fully unrolled: k_reg / v_reg must stay in registers
+  uint32_t rank[kItems], dig[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const int li = r * kSortBlock + t;
+    const int li = wid * kPerWave + r * 64 + lane;
     const bool valid = li < chunk_n;
     const uint32_t d = valid ? digit_of(k_reg[r], shift, mask) : 0u;
     uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < width; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
-    uint32_t rank = 0;
+    dig[r] = d;
+    rank[r] = 0;
     if (valid) {
-      rank = __popcll(peers & lt_mask);
-      if (rank == 0) s_wave[wid][d] = (uint32_t)__popcll(peers);
+      const uint32_t before = s_wave[wid][d];   // same value for every peer
+      const uint32_t pos = (uint32_t)__popcll(peers & lt_mask);
+      rank[r] = before + pos;
+      if (pos == 0) s_wave[wid][d] = before + (uint32_t)__popcll(peers);
     }
-    __syncthreads();
-    if (valid) {
-      uint32_t off = s_run[d] + rank;
-      for (int w = 0; w < wid; ++w) off += s_wave[w][d];
-      const uint32_t lp = s_lbase[d] + off;
-      s_key[lp] = k_reg[r];
-      s_val[lp] = v_reg[r];
-    }
-    __syncthreads();
-    {
-      uint32_t add = 0;
-#pragma unroll
-      for (int w = 0; w < kSortBlock / 64; ++w) {
-        add += s_wave[w][t];
-        s_wave[w][t] = 0;
-      }
-      s_run[t] += add;
-    }
-    __syncthreads();
   }
+  __syncthreads();
+  // place every key: digit start in the chunk + keys of that digit in earlier waves
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int li = wid * kPerWave + r * 64 + lane;
+    if (li < chunk_n) {
+      const uint32_t d = dig[r];
+      uint32_t off = s_lbase[d] + rank[r];
+      for (int w = 0; w < wid; ++w) off += s_wave[w][d];
+      s_key[off] = k_reg[r];
+      s_val[off] = v_reg[r];
+    }
+  }
+  __syncthreads();
   // coalesced write-out of the locally sorted chunk
   for (int i = t; i < chunk_n; i += kSortBlock) {
     const uint32_t k = s_key[i];
@@ -261,24 +297,52 @@ __global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(uint32_t* __res
 // the block's offsets in LDS, so consecutive threads write consecutive
 // addresses however unevenly the Gaussians' tile counts are spread.
 __global__ __launch_bounds__(kScanBlock) void emit_kernel(
-    const uint32_t* __restrict__ sorted_slots, int64_t n, int32_t n_gauss,
+    const uint32_t* __restrict__ sorted_slots, int64_t n, int32_t n_gauss, int n_views,
     const uint2* __restrict__ rect, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ local, const uint32_t* __restrict__ block_off,
     uint32_t total, uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_val) {
   __shared__ uint32_t s_off[kScanChunk + 1];
   __shared__ uint32_t s_slot[kScanChunk];
-  __shared__ uint2 s_rect[kScanChunk];
+  __shared__ uint32_t s_tile0[kScanChunk];   // global tile of the rectangle's first tile
+  __shared__ uint32_t s_geom[kScanChunk];    // width | tiles_x << 16
   const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
   const int cnt = (int)min((int64_t)kScanChunk, n - b0);
   const uint32_t out0 = block_off[blockIdx.x];
   const uint32_t out1 = (b0 + kScanChunk < n) ? block_off[blockIdx.x + 1] : total;
-  for (int k = threadIdx.x; k < cnt; k += kScanBlock) {
-    const uint32_t slot = sorted_slots[b0 + k];
-    s_slot[k] = slot;
-    s_off[k] = local[b0 + k];
-    s_rect[k] = rect[slot];
+  // loads first (all independent), then the LDS tables
+  constexpr int kPerT = kScanChunk / kScanBlock;
+  uint32_t slot_r[kPerT], off_r[kPerT];
+  uint2 rect_r[kPerT];
+#pragma unroll
+  for (int q = 0; q < kPerT; ++q) {
+    const int k = q * kScanBlock + threadIdx.x;
+    slot_r[q] = k < cnt ? sorted_slots[b0 + k] : 0u;
+    off_r[q] = k < cnt ? local[b0 + k] : 0u;
   }
-  if (threadIdx.x == 0) s_off[cnt] = out1 - out0;
+#pragma unroll
+  for (int q = 0; q < kPerT; ++q) {
+    const int k = q * kScanBlock + threadIdx.x;
+    rect_r[q] = k < cnt ? rect[slot_r[q]] : make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+  }
+#pragma unroll
+  for (int q = 0; q < kPerT; ++q) {
+    const int k = q * kScanBlock + threadIdx.x;
+    if (k >= cnt) continue;
+    s_slot[k] = slot_r[q];
+    s_off[k] = off_r[q];
+    const uint2 r = rect_r[q];
+    if (r.x != 0xFFFFFFFFu) {
+      const uint32_t vi = n_views == 1 ? 0u : slot_r[q] / (uint32_t)n_gauss;
+      const uint32_t tile_off = (uint32_t)views[vi].tile_off;
+      const uint32_t tiles_x = (uint32_t)views[vi].tiles_x;
+      const uint32_t tx0 = r.x & 0xFFFF, tx1 = r.x >> 16, ty0 = r.y & 0xFFFF;
+      s_tile0[k] = tile_off + ty0 * tiles_x + tx0;
+      s_geom[k] = (tx1 - tx0 + 1) | (tiles_x << 16);
+    } else {
+      s_tile0[k] = 0;
+      s_geom[k] = 1;
+    }
+  }
   __syncthreads();
   const uint32_t tot = out1 - out0;
   for (uint32_t q = threadIdx.x; q < tot; q += kScanBlock) {
@@ -287,15 +351,15 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
       const int mid = (lo + hi + 1) >> 1;
       if (s_off[mid] <= q) lo = mid; else hi = mid - 1;
     }
-    const uint32_t slot = s_slot[lo];
-    const uint2 r = s_rect[lo];
-    const int tx0 = r.x & 0xFFFF, tx1 = r.x >> 16, ty0 = r.y & 0xFFFF;
-    const int w = tx1 - tx0 + 1;
-    const int l = (int)(q - s_off[lo]);
-    const ViewDev& v = views[slot / (uint32_t)n_gauss];
-    inst_tile[out0 + q] =
-        (uint32_t)(v.tile_off + (ty0 + l / w) * v.tiles_x + tx0 + l % w);
-    inst_val[out0 + q] = slot;
+    const uint32_t geom = s_geom[lo];
+    const uint32_t w = geom & 0xFFFF, tiles_x = geom >> 16;
+    const uint32_t l = q - s_off[lo];
+    // row = l / w in float (exact for l < 2^24 after the +-1 fix-up)
+    uint32_t row = (uint32_t)((float)l * __frcp_rn((float)w));
+    if (row * w > l) --row;
+    if ((row + 1) * w <= l) ++row;
+    inst_tile[out0 + q] = s_tile0[lo] + row * tiles_x + (l - row * w);
+    inst_val[out0 + q] = s_slot[lo];
   }
 }
 
@@ -384,9 +448,11 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
   if (n <= 1 || nbits <= 0) return 0;
   const int nchunks = (int)((n + kChunk - 1) / kChunk);
   uint32_t* totals = counts + (int64_t)nchunks * kRadix;
-  int cur = 0;
-  for (int shift = 0; shift < nbits; shift += 8) {
-    const int width = min(8, nbits - shift);
+  // as few passes as digits of <= kRadixBits allow, widths as even as possible
+  const int passes = (nbits + kRadixBits - 1) / kRadixBits;
+  int cur = 0, shift = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int width = (nbits - shift + (passes - p) - 1) / (passes - p);
     const uint32_t mask = (1u << width) - 1u;
     uint32_t* kin = cur ? keys_alt : keys;
     uint32_t* vin = cur ? vals_alt : vals;
@@ -394,11 +460,12 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
     uint32_t* vout = cur ? vals : vals_alt;
     hipLaunchKernelGGL(rs_count, dim3(nchunks), dim3(kSortBlock), 0, s, kin, n, shift,
                        mask, nchunks, counts);
-    hipLaunchKernelGGL(rs_scan_digit, dim3(kRadix), dim3(kSortBlock), 0, s, counts,
+    hipLaunchKernelGGL(rs_scan_digit, dim3(1u << width), dim3(kSortBlock), 0, s, counts,
                        nchunks, totals);
     hipLaunchKernelGGL(rs_scatter, dim3(nchunks), dim3(kSortBlock), 0, s, kin, vin, kout,
-                       vout, n, shift, mask, nchunks, counts, totals);
+                       vout, n, shift, width, nchunks, counts, totals);
     cur ^= 1;
+    shift += width;
   }
   return cur;
 }
@@ -417,9 +484,10 @@ void launch_emit(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
                      sorted_slots, n_slots, proj.ntiles, scan_local, block_sums);
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanBlock), 0, s, block_sums,
                      nblocks);
+  const int n_views = (int)(n_slots / n_gauss);
   hipLaunchKernelGGL(emit_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, sorted_slots,
-                     n_slots, n_gauss, proj.rect, views, scan_local, block_sums, total,
-                     inst_tile, inst_val);
+                     n_slots, n_gauss, n_views, proj.rect, views, scan_local, block_sums,
+                     total, inst_tile, inst_val);
 }
 
 void launch_iota_copy(const uint32_t* src, uint32_t* dst, uint32_t* idx, int64_t n,

@@ -60,7 +60,20 @@ typedef enum {
   NXS_EXPONENTIAL = 0,
   NXS_LINEAR = 1,
   NXS_QUAD_SUBLINEAR = 2,
-  NXS_QUAD_SUPERLINEAR = 3
+  NXS_QUAD_SUPERLINEAR = 3,
+  /* The remaining operators of Table 1, with their parameter in opts.param:
+   *   QUADRATIC   T = [1 - tau - c tau^2 / 2]_+, c = param >= -0.5
+   *   BLENDED     T = [lerp(1 - tau, exp(-tau), gamma)]_+:
+   *               p_i = a_i (1 - gamma + gamma prod_{j<i} (1 - a_j)), gamma = param in [0, 1]
+   *   VICINI      lerp of the complete linear and exponential operators, each
+   *               saturating / stopping on its own (the exponential part obeys
+   *               t_eps), gamma = param in [0, 1]
+   *   POWER_LAW   T = [(1 + v tau)^(-1/v)]_+: p_i = a_i (1 + v tau_i)^(-(1+v)/v),
+   *               v = param != 0; where 1 + v tau_i <= 0 the splat saturates */
+  NXS_QUADRATIC = 4,
+  NXS_BLENDED = 5,
+  NXS_VICINI = 6,
+  NXS_POWER_LAW = 7
 } nxs_model;
 
 /* Gaussians (Sec. 3: centre, covariance, opacity aleph, directional emission).
@@ -102,11 +115,13 @@ typedef struct {
   float background[3];    /* L_b of eq. generalized_gaussian (default 0) */
   float alpha_min;        /* splats with alpha < alpha_min are skipped;
                              0 -> 1e-3 */
-  float t_eps;            /* exponential only: stop after the first splat that
-                             leaves T < t_eps; 0 -> 1e-4, < 0 -> never */
+  float t_eps;            /* exponential (and Vicini's exponential part): stop
+                             after the first splat that leaves T < t_eps;
+                             0 -> 1e-4, < 0 -> never */
   int32_t tile_w, tile_h; /* 8x8, 16x16 or 32x8; 0 -> 16x16 */
-  int32_t lds_batch;      /* splats staged in LDS per batch: 0, 128, 256, 512
-                             (0 -> 256) */
+  int32_t lds_batch;      /* accepted for compatibility: 0, 128, 256, 512 (the
+                             composite walks its tile in batches of 64 splats) */
+  float param;            /* operator parameter of models 4..7 (c, gamma or v) */
 } nxs_render_opts;
 
 /* Per-view outputs (device pointers), row-major:

@@ -71,6 +71,11 @@ def composite_pixel(alphas, rgb, op, alpha_min, t_eps, background):
     """Composite one pixel's front-to-back list (alphas already >= alpha_min
     or near it) and derive its ambiguity flag from the composited steps."""
     res = _ops.composite_sequence(alphas, op, rgb, background, alpha_min, t_eps)
+    if op.kind == "vicini":
+        # its two parts stop on their own: a boundary case of either is one of it
+        _, a1 = composite_pixel(alphas, rgb, _ops.LINEAR, alpha_min, t_eps, background)
+        _, a2 = composite_pixel(alphas, rgb, _ops.EXPONENTIAL, alpha_min, t_eps, background)
+        return res, a1 or a2
     amb = bool(np.any(np.abs(np.asarray(alphas) - alpha_min) <= ALPHA_REL * alpha_min))
     T, p_raw = res["T"], res["p_raw"]
     for i in range(res["k"] + 1):
@@ -90,13 +95,13 @@ def render(scene, cam, op, alpha_min=1e-3, t_eps=None, background=(0.0, 0.0, 0.0
     """Render `pixels` (an [P,2] int array of (x, y); default: the whole image).
 
     op: an operators.Op (or a library model id 0..3).  t_eps defaults to 1e-4
-    for the exponential and 0 otherwise.  Returns a dict of per-pixel arrays:
+    for the exponential (and Vicini's exponential part) and 0 otherwise.  Returns a dict of per-pixel arrays:
     rgb [P,3], trans [P], od [P] (int), ambiguous [P] (bool), pixels [P,2].
     """
     if isinstance(op, int):
         op = _ops.MODELS[op]
     if t_eps is None:
-        t_eps = 1e-4 if op.kind == "exponential" else 0.0
+        t_eps = 1e-4 if op.kind in ("exponential", "vicini") else 0.0
     W, H = cam.width, cam.height
     if pixels is None:
         yy, xx = np.mgrid[0:H, 0:W]
@@ -146,7 +151,7 @@ def render_brute(scene, cam, op, alpha_min=1e-3, t_eps=None, background=(0.0, 0.
     if isinstance(op, int):
         op = _ops.MODELS[op]
     if t_eps is None:
-        t_eps = 1e-4 if op.kind == "exponential" else 0.0
+        t_eps = 1e-4 if op.kind in ("exponential", "vicini") else 0.0
     proj = _project.project(scene, cam)
     geom = _keys.geometry(scene, cam, alpha_min)
     vis = np.nonzero(geom["visible"])[0]

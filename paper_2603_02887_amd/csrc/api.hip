@@ -160,7 +160,15 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
     return fail(ctx, NXS_EINVAL, "sh_degree must be 0..3");
   if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh))
     return fail(ctx, NXS_EINVAL, "null Gaussian array");
-  if (opts->model < 0 || opts->model > 3) return fail(ctx, NXS_EINVAL, "unknown model %d", opts->model);
+  if (opts->model < 0 || opts->model > 7) return fail(ctx, NXS_EINVAL, "unknown model %d", opts->model);
+  const float param = opts->param;
+  if (opts->model == NXS_QUADRATIC && !(param >= -0.5f))
+    return fail(ctx, NXS_EINVAL, "quadratic c must be >= -0.5");
+  if ((opts->model == NXS_BLENDED || opts->model == NXS_VICINI) &&
+      !(param >= 0.0f && param <= 1.0f))
+    return fail(ctx, NXS_EINVAL, "gamma must be in [0, 1]");
+  if (opts->model == NXS_POWER_LAW && !(param != 0.0f && std::isfinite(param)))
+    return fail(ctx, NXS_EINVAL, "power-law v must be finite and non-zero");
   int tw = opts->tile_w ? opts->tile_w : 16, th = opts->tile_h ? opts->tile_h : 16;
   if (!((tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 8)))
     return fail(ctx, NXS_EINVAL, "tile size %dx%d not supported (8x8, 16x16, 32x8)", tw, th);
@@ -307,7 +315,8 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   // 5. composite (also writes the background where no splat lands)
   CompositeParams cp;
   cp.log2_alpha_min = (float)std::log2((double)alpha_min);
-  cp.t_eps = opts->model == 0 ? t_eps : 0.0f;
+  cp.t_eps = (opts->model == NXS_EXPONENTIAL || opts->model == NXS_VICINI) ? t_eps : 0.0f;
+  cp.param = param;
   for (int k = 0; k < 3; ++k) cp.bg[k] = opts->background[k];
   cp.lds_batch = batch;
   launch_composite(opts->model, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),

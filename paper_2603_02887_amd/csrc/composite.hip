@@ -23,12 +23,75 @@ namespace nxs {
 
 namespace {
 
+// Per-pixel state and update of a Table 1 operator.  MODEL: 0 exponential,
+// 1 linear, 2 quadratic c = -0.5, 3 quadratic c = +0.5, 4 quadratic with
+// c = param, 5 blended (gamma = param), 6 Vicini et al. (gamma = param),
+// 7 power law (v = param).  `step` composites one splat of opacity a >=
+// alpha_min and returns its p; `done` is set once the pixel stops.
 template <int MODEL>
-struct OpC;
-template <> struct OpC<0> { static constexpr float c = 0.0f; };   // exponential
-template <> struct OpC<1> { static constexpr float c = 0.0f; };   // linear
-template <> struct OpC<2> { static constexpr float c = -0.5f; };  // quadratic, sublinear
-template <> struct OpC<3> { static constexpr float c = 0.5f; };   // quadratic, superlinear
+struct Op {
+  float S = 0.0f;      // running sum of p (T = 1 - S)
+  float tau = 0.0f;    // discrete optical depth
+  float T = 1.0f;      // running product of (1 - a) (exponential parts)
+  float S2 = 0.0f;     // Vicini: linear part's running sum
+  bool d1 = false;     // Vicini: linear part saturated
+  bool d2 = false;     // Vicini: exponential part stopped
+
+  __device__ __forceinline__ float saturate(float p, bool& done) {
+    const float Sn = S + p;
+    done = Sn >= 1.0f;
+    p = done ? 1.0f - S : p;
+    S = done ? 1.0f : Sn;
+    return p;
+  }
+  __device__ __forceinline__ float step(float a, float param, float t_eps, bool& done) {
+    if (MODEL == 0) {
+      const float p = a * T;
+      T = T * (1.0f - a);
+      done = !(T >= t_eps) || T == 0.0f;
+      return p;
+    } else if (MODEL == 1) {
+      return saturate(a, done);
+    } else if (MODEL <= 4) {
+      const float c = MODEL == 2 ? -0.5f : MODEL == 3 ? 0.5f : param;
+      const float p = a * fmaf(c, tau, 1.0f);
+      tau += a;
+      return saturate(p, done);
+    } else if (MODEL == 5) {
+      const float p = a * fmaf(param, T, 1.0f - param);
+      T = T * (1.0f - a);
+      return saturate(p, done);
+    } else if (MODEL == 6) {
+      float pl = 0.0f, pe = 0.0f;
+      if (!d1) {
+        const float Sn = S2 + a;
+        d1 = Sn >= 1.0f;
+        pl = d1 ? 1.0f - S2 : a;
+        S2 = d1 ? 1.0f : Sn;
+      }
+      if (!d2) {
+        pe = a * T;
+        T = T * (1.0f - a);
+        d2 = !(T >= t_eps) || T == 0.0f;
+      }
+      done = d1 && d2;
+      return fmaf(param, pe - pl, pl);
+    } else {
+      const float base = fmaf(param, tau, 1.0f);
+      tau += a;
+      const float p = base > 0.0f
+                          ? a * __builtin_amdgcn_exp2f(-(1.0f + param) / param *
+                                                      __builtin_amdgcn_logf(base))
+                          : __builtin_inff();
+      return saturate(p, done);
+    }
+  }
+  __device__ __forceinline__ float transmittance(float param) const {
+    if (MODEL == 0) return T;
+    if (MODEL == 6) return fmaf(param, T - (1.0f - S2), 1.0f - S2);
+    return 1.0f - S;
+  }
+};
 
 template <int MODEL, int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void composite_kernel(
@@ -60,70 +123,62 @@ __global__ __launch_bounds__(TW* TH) void composite_kernel(
   const uint2 rg = ranges[tile];
   const float amin = prm.log2_alpha_min;
   const float t_eps = prm.t_eps;
-  constexpr float c = OpC<MODEL>::c;
+  const float param = prm.param;
+  Op<MODEL> op;
 
   float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f;
-  float T = 1.0f;      // exponential: running product; others: 1 - S
-  float S = 0.0f;      // running sum of p (non-exponential)
-  float tau = 0.0f;    // discrete optical depth (quadratic)
   int od = 0;
   bool done = !inside;
 
-  // Batches of 64 splats: lane j loads splat (base + j) into registers with
-  // coalesced loads; a ballot of the block bits gives the wave a bitmap of the
-  // splats whose footprint reaches its 8x8 block; those are visited in order,
-  // each field broadcast from its lane into a scalar register.
-  for (uint32_t base = rg.x; base < rg.y; base += 64) {
-    if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
+  // Batches of 64 splats: lane j reads the block bits of splat (base + j)
+  // (one coalesced load); a ballot gives the wave a bitmap of the splats whose
+  // footprint reaches its 8x8 block.  Those are visited in order, each one's
+  // fields read with scalar loads into SGPRs (no per-lane copies, no LDS).
+  const float* crf = reinterpret_cast<const float*>(crec);
+  bool all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
+  for (uint32_t base = rg.x; base < rg.y && !all_done; base += 64) {
     const uint32_t j = base + (uint32_t)lane;
-    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
-    if (j < rg.y) {
-      q0 = crec[3 * (size_t)j];
-      q1 = crec[3 * (size_t)j + 1];
-      q2 = crec[3 * (size_t)j + 2];
-    }
-    uint64_t rel = __builtin_amdgcn_ballot_w64((__float_as_uint(q2.y) & wbit) != 0);
-    while (rel) {
-      const int k = __builtin_ctzll(rel);
-      rel &= rel - 1;
-      const float s_du = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.x), k));
-      const float s_dv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.y), k));
-      const float s_A = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.z), k));
-      const float s_B = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q0.w), k));
-      const float s_C = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.x), k));
-      const float s_lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.y), k));
-      if (!done) {
-        const float dx = fx - s_du, dy = fy - s_dv;
-        const float e = fmaf(dx, fmaf(s_A, dx, s_B * dy), fmaf(s_C * dy, dy, s_lo));
-        if (e >= amin) {
-          const float a = __builtin_amdgcn_exp2f(e);
-          float p;
-          if (MODEL == 0) {
-            p = a * T;
-            T = T * (1.0f - a);
-            done = !(T >= t_eps) || T == 0.0f;
-          } else {
-            p = (MODEL == 1) ? a : a * fmaf(c, tau, 1.0f);
-            if (MODEL >= 2) tau += a;
-            const float Sn = S + p;
-            done = Sn >= 1.0f;
-            p = done ? 1.0f - S : p;
-            S = done ? 1.0f : Sn;
+    const uint32_t bits = j < rg.y ? __float_as_uint(crf[12 * (size_t)j + 9]) : 0u;
+    uint64_t rel = __builtin_amdgcn_ballot_w64((bits & wbit) != 0);
+    if (rel == 0) continue;
+    // up to four relevant splats per step: their scalar loads are all issued
+    // before the first is composited, so the load latency overlaps the work
+    do {
+      uint32_t kk[4];
+      int cnt = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool have = rel != 0;
+        kk[q] = have ? base + (uint32_t)__builtin_ctzll(rel) : kk[0];
+        rel = have ? rel & (rel - 1) : 0ull;
+        cnt += have ? 1 : 0;
+      }
+      float cur[4][9];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int f = 0; f < 9; ++f) cur[q][f] = crf[12 * (size_t)kk[q] + f];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < cnt && !done) {
+          const float dx = fx - cur[q][0], dy = fy - cur[q][1];
+          const float e =
+              fmaf(dx, fmaf(cur[q][2], dx, cur[q][3] * dy), fmaf(cur[q][4] * dy, dy, cur[q][5]));
+          if (e >= amin) {
+            const float a = __builtin_amdgcn_exp2f(e);
+            const float p = op.step(a, param, t_eps, done);
+            L0 = fmaf(cur[q][6], p, L0);
+            L1 = fmaf(cur[q][7], p, L1);
+            L2 = fmaf(cur[q][8], p, L2);
+            ++od;
           }
-          const float s_r = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.z), k));
-          const float s_g = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q1.w), k));
-          const float s_b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2.x), k));
-          L0 = fmaf(s_r, p, L0);
-          L1 = fmaf(s_g, p, L1);
-          L2 = fmaf(s_b, p, L2);
-          ++od;
         }
       }
-      if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
-    }
+      all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
+    } while (rel != 0 && !all_done);
   }
   if (inside) {
-    const float Tf = (MODEL == 0) ? T : 1.0f - S;
+    const float Tf = op.transmittance(param);
     const int64_t pix = (int64_t)py * v.width + px;
     v.rgb[3 * pix + 0] = L0 + prm.bg[0] * Tf;
     v.rgb[3 * pix + 1] = L1 + prm.bg[1] * Tf;
@@ -159,10 +214,11 @@ void launch_composite(int model, int tile_w, int tile_h, int64_t n_tiles,
                       const float4* crec, const CompositeParams& p, hipStream_t s) {
   if (n_tiles <= 0) return;
   switch (model) {
-    case 0: launch_m<0>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
-    case 1: launch_m<1>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
-    case 2: launch_m<2>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
-    default: launch_m<3>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
+#define NXS_M(M) \
+  case M: launch_m<M>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
+    NXS_M(0) NXS_M(1) NXS_M(2) NXS_M(3) NXS_M(4) NXS_M(5) NXS_M(6) NXS_M(7)
+#undef NXS_M
+    default: break;
   }
 }
 

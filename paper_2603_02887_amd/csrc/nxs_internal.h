@@ -93,6 +93,7 @@ void launch_ranges_gather(const uint32_t* inst_tile, const uint32_t* inst_val,
 struct CompositeParams {
   float log2_alpha_min;
   float t_eps;              // exponential termination threshold (<= 0: never)
+  float param;              // operator parameter (c, gamma or v) for models 4..7
   float bg[3];
   int32_t lds_batch;
 };

@@ -14,7 +14,8 @@ import torch
 
 LIB_PATH = Path(__file__).resolve().parent / "libnxs.so"
 
-MODEL_IDS = {"exponential": 0, "linear": 1, "sublinear": 2, "superlinear": 3}
+MODEL_IDS = {"exponential": 0, "linear": 1, "sublinear": 2, "superlinear": 3,
+             "quadratic": 4, "blended": 5, "vicini": 6, "powerlaw": 7}
 STATUS = {0: "NXS_OK", -1: "NXS_EINVAL", -2: "NXS_ENOMEM", -3: "NXS_EHIP",
           -4: "NXS_ECAPACITY", -5: "NXS_EUNSUPPORTED"}
 SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_last_error",
@@ -43,7 +44,7 @@ class Camera(ctypes.Structure):
 class RenderOpts(ctypes.Structure):
     _fields_ = [("model", c_int32), ("background", c_float * 3), ("alpha_min", c_float),
                 ("t_eps", c_float), ("tile_w", c_int32), ("tile_h", c_int32),
-                ("lds_batch", c_int32)]
+                ("lds_batch", c_int32), ("param", c_float)]
 
 
 class Image(ctypes.Structure):
@@ -140,7 +141,7 @@ class Renderer:
 
     def render(self, g, cams, model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0,
                t_eps=0.0, tile=(16, 16), lds_batch=0, outputs=None, overdraw=True,
-               stream=None):
+               stream=None, param=0.0):
         """Render the Gaussians `g` (dict of GPU tensors, see scene_to_device) in
         every camera of `cams`.  Returns a list of dicts {rgb [H,W,3], trans [H,W],
         overdraw [H,W] int32} (or fills `outputs`, a list of such dicts)."""
@@ -182,6 +183,7 @@ class Renderer:
         opts.alpha_min, opts.t_eps = float(alpha_min), float(t_eps)
         opts.tile_w, opts.tile_h = int(tile[0]), int(tile[1])
         opts.lds_batch = int(lds_batch)
+        opts.param = float(param)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         st = self._L.nxs_render_forward(self._ctx, byref(gs), carr, V, byref(opts), imgs,

@@ -30,6 +30,7 @@ def R():
 
 
 def _render(R, scene, cams, model, **kw):
+    """Render through the C ABI and wait for the stream."""
     from paper_2603_02887_amd import nxs
     g = nxs.scene_to_device(scene)
     out = R.render(g, cams, model=model, **kw)
@@ -159,7 +160,7 @@ def test_invalid_arguments(R):
     sc, cams = synth.tiny_scene(n=10)
     g = nxs.scene_to_device(sc)
     with pytest.raises(nxs.NxsError) as e:
-        R.render(g, cams, model=7)
+        R.render(g, cams, model=9)
     assert e.value.status == -1
     with pytest.raises(nxs.NxsError):
         R.render(g, cams, tile=(12, 12))
@@ -185,3 +186,47 @@ def test_scene_scale_1m_1080p(R, scene_scale, model):
     st = parity.compare_view(out[0], sc, cams[0], model,
                              pixels=parity.sample_pixels(cams[0], 1500, seed=model))
     print("scene", model, st)
+
+
+# ------------------------------------------------- the other Table 1 operators
+
+FIG_MODELS = [  # (figure panel, library model id, parameter)
+    ("powerlaw_v2", 7, 2.0), ("quadratic_c-0.5", 2, 0.0), ("vicini_g0.5", 6, 0.5),
+    ("blended_g0.5", 5, 0.5), ("quadratic_c0.5", 3, 0.0), ("quadratic_c1", 4, 1.0),
+    ("powerlaw_vm1", 7, -2.0), ("linear", 1, 0.0), ("exponential", 0, 0.0)]
+
+
+@pytest.mark.parametrize("name,model,param", FIG_MODELS)
+def test_all_nine_figure_operators_on_gpu(R, name, model, param):
+    """Both figures of Sec. 4 for all nine operators, rendered by the GPU:
+    the blending scan-line (6 decimals) and the transmittance dots (8)."""
+    from tests.golden import fixtures
+    rows = fixtures.blending_concentric()[name]
+    sc, cam = _concentric(3, (40.0, 60.0, 80.0), 1.0, [(1, 0, 0), (0, 1, 0), (0, 0, 1)])
+    out = _render(R, sc, [cam], model, t_eps=-1.0, param=param)
+    rgb = out[0]["rgb"].cpu().numpy()[256, rows[:, 0].astype(int)]
+    assert np.abs(rgb - rows[:, 1:4]).max() < 5e-6, name
+    for tau, want in fixtures.transmittance_dots()[name][1::3]:
+        n = int(round(tau / 0.02))
+        sc, cam = _concentric(n, [3.0] * n, 0.02, [(0.5, 0.5, 0.5)] * n)
+        out = _render(R, sc, [cam], model, t_eps=-1.0, param=param)
+        assert abs(out[0]["trans"].cpu().numpy()[256, 256] - want) < 2e-6, (name, tau)
+
+
+@pytest.mark.parametrize("model,param,kind", [(4, 1.0, "quadratic"), (4, -0.25, "quadratic"),
+                                              (5, 0.5, "blended"), (6, 0.5, "vicini"),
+                                              (7, 2.0, "powerlaw"), (7, -2.0, "powerlaw")])
+def test_other_operators_tiny_scene(R, model, param, kind):
+    from oracle import operators as O
+    sc, cams = synth.tiny_scene(seed=3, n=3000)
+    out = _render(R, sc, cams, model, param=param)
+    parity.compare_view(out[0], sc, cams[0], O.Op(kind, param))
+
+
+def test_operator_parameter_checks(R):
+    from paper_2603_02887_amd import nxs
+    sc, cams = synth.tiny_scene(n=10)
+    g = nxs.scene_to_device(sc)
+    for model, param in ((4, -0.6), (5, 1.5), (6, -0.1), (7, 0.0)):
+        with pytest.raises(nxs.NxsError):
+            R.render(g, cams, model=model, param=param)

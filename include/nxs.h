@@ -122,6 +122,7 @@ typedef struct {
   int32_t lds_batch;      /* accepted for compatibility: 0, 128, 256, 512 (the
                              composite walks its tile in batches of 64 splats) */
   float param;            /* operator parameter of models 4..7 (c, gamma or v) */
+  int32_t keep_state;     /* nonzero: keep what nxs_render_backward needs */
 } nxs_render_opts;
 
 /* Per-view outputs (device pointers), row-major:
@@ -150,6 +151,36 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
                               const nxs_camera* cams, int32_t n_views,
                               const nxs_render_opts* opts, const nxs_image* out,
                               void* stream);
+
+/* Gradients of the Gaussians' parameters, device arrays shaped like the
+ * inputs of nxs_gaussians (means [n,3], scales [n,3], quats [n,4],
+ * opacities [n], sh [n,K,3]); overwritten by nxs_render_backward. */
+typedef struct {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacities;
+  float* sh;
+} nxs_gaussians_grad;
+
+/* Path-replay backward of the last nxs_render_forward on this context, which
+ * must have had opts.keep_state set (appendix "Adjoints": the linear and
+ * quadratic recursions; the front-to-back form for the exponential).
+ *   dL_drgb   [n_views] host array of device [H,W,3] upstream gradients
+ *   dL_dtrans [n_views] host array of device [H,W] gradients, or NULL (the
+ *             array itself, or any entry, may be NULL for "zero")
+ *   grads     device outputs, overwritten (sum over all views)
+ * Each tile's splats are re-walked front to back, rebuilding every pixel's
+ * state from the start with the same float32 decisions as the forward;
+ * nothing is stored per splat, only 12 floats per pixel.  The Gaussians and
+ * camera inputs of the forward must be unchanged.  Models 0..4 only
+ * (NXS_EUNSUPPORTED otherwise).  NXS_EINVAL if the last forward on the
+ * context (failed ones included) did not keep its state, or on a NULL
+ * dL_drgb entry or gradient array.  Enqueued on `stream` after that forward;
+ * the gradients are complete when the stream reaches this point. */
+nxs_status nxs_render_backward(nxs_context* ctx, const float* const* dL_drgb,
+                               const float* const* dL_dtrans,
+                               const nxs_gaussians_grad* grads, void* stream);
 
 /* Message for the last non-OK status returned on this context ("" if none).
  * The pointer stays valid until the next call on the context. */

@@ -16,5 +16,7 @@ Modules
              (depth bits and covered tiles), and the sorted instance list.
   render     per-pixel plain composite: every visible Gaussian evaluated at
              the pixel centre, sorted front to back, composited in FP64.
+  adjoint    the operators' adjoints on one sequence (the appendix "Adjoints"
+             for linear and quadratic; the front-to-back form for exponential).
 """
-from . import operators, sh, project, keys, render  # noqa: F401
+from . import operators, sh, project, keys, render, adjoint  # noqa: F401

@@ -30,7 +30,7 @@ struct nxs_context {
   DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, ntiles, rect, prec;
   DevBuf scan_local, block_sums, counts;
   DevBuf inst_tile, inst_tile_alt, inst_val, inst_val_alt;
-  DevBuf crec, ranges;
+  DevBuf crec, ranges, pstate, gslot;
   Counters* host_counters = nullptr;  // pinned
   ViewDev* host_views = nullptr;      // pinned
   int host_views_cap = 0;
@@ -40,6 +40,12 @@ struct nxs_context {
   bool timing = false;
   hipEvent_t ev[8] = {};
   bool ev_valid = false;
+  // what the backward of the last render needs
+  bool bwd_valid = false;
+  nxs_gaussians bwd_g{};
+  int bwd_model = 0, bwd_tw = 16, bwd_th = 16;
+  CompositeParams bwd_cp{};
+  std::vector<ViewDev> bwd_views;
   // state of the last render, for inspection
   int64_t last_m = 0, last_tiles = 0, last_slots = 0;
   int32_t last_n = 0, last_views = 0;
@@ -133,7 +139,8 @@ nxs_status nxs_destroy(nxs_context* ctx) {
                    &ctx->slot_a,     &ctx->slot_b,        &ctx->ntiles,    &ctx->rect,
                    &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
-                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->crec,      &ctx->ranges};
+                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->crec,      &ctx->ranges,
+                   &ctx->pstate,     &ctx->gslot};
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
@@ -153,6 +160,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
                               void* stream) {
   if (!ctx) return NXS_EINVAL;
   ctx->err.clear();
+  ctx->bwd_valid = false;   // any forward, even a failed one, ends the kept state
   if (!g || !cams || !opts || !out) return fail(ctx, NXS_EINVAL, "null argument");
   if (n_views < 1) return fail(ctx, NXS_EINVAL, "n_views must be >= 1");
   if (g->n < 0) return fail(ctx, NXS_EINVAL, "n must be >= 0");
@@ -208,7 +216,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   }
   // (the previous call's copy out of host_views finished before it returned:
   // it synchronised its stream after the projection)
-  int64_t off = 0;
+  int64_t off = 0, pix_off = 0;
   for (int v = 0; v < n_views; ++v) {
     const nxs_camera& c = cams[v];
     ViewDev& d = ctx->host_views[v];
@@ -224,6 +232,8 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
     d.tiles_y = (c.height + th - 1) / th;
     d.tile_off = (int32_t)off;
     off += (int64_t)d.tiles_x * d.tiles_y;
+    d.pix_off = pix_off;
+    pix_off += (int64_t)c.width * c.height;
     d.rgb = out[v].rgb; d.trans = out[v].trans; d.od = out[v].overdraw;
   }
   nxs_status st;
@@ -313,6 +323,11 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   }
   HIP_TRY(mark(6));
   // 5. composite (also writes the background where no splat lands)
+  float4* pstate = nullptr;
+  if (opts->keep_state) {
+    if ((st = ensure(ctx, ctx->pstate, 48 * (size_t)pix_off))) return st;
+    pstate = P<float4>(ctx->pstate);
+  }
   CompositeParams cp;
   cp.log2_alpha_min = (float)std::log2((double)alpha_min);
   cp.t_eps = (opts->model == NXS_EXPONENTIAL || opts->model == NXS_VICINI) ? t_eps : 0.0f;
@@ -320,11 +335,20 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   for (int k = 0; k < 3; ++k) cp.bg[k] = opts->background[k];
   cp.lds_batch = batch;
   launch_composite(opts->model, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),
-                   P<float4>(ctx->crec), cp, s);
+                   P<float4>(ctx->crec), cp, pstate, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(7));
   HIP_TRY(hipEventRecord(ctx->done, s));
   ctx->has_done = true;
+  if (opts->keep_state) {
+    ctx->bwd_valid = true;
+    ctx->bwd_g = *g;
+    ctx->bwd_model = opts->model;
+    ctx->bwd_tw = tw;
+    ctx->bwd_th = th;
+    ctx->bwd_cp = cp;
+    ctx->bwd_views.assign(ctx->host_views, ctx->host_views + n_views);
+  }
   ctx->ev_valid = ctx->timing;
 
   ctx->last_m = (int64_t)M;
@@ -334,6 +358,49 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   ctx->last_views = n_views;
   ctx->last_inst_tile = inst_tile;
   ctx->last_inst_val = inst_val;
+  return NXS_OK;
+}
+
+nxs_status nxs_render_backward(nxs_context* ctx, const float* const* dL_drgb,
+                               const float* const* dL_dtrans,
+                               const nxs_gaussians_grad* grads, void* stream) {
+  if (!ctx) return NXS_EINVAL;
+  ctx->err.clear();
+  if (!ctx->bwd_valid)
+    return fail(ctx, NXS_EINVAL, "no forward with keep_state since the last forward");
+  if (ctx->bwd_model > NXS_QUADRATIC)
+    return fail(ctx, NXS_EUNSUPPORTED, "backward supports models 0..4, not %d", ctx->bwd_model);
+  if (!dL_drgb || !grads) return fail(ctx, NXS_EINVAL, "null argument");
+  const nxs_gaussians& g = ctx->bwd_g;
+  if (g.n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacities ||
+                  !grads->sh))
+    return fail(ctx, NXS_EINVAL, "null gradient array");
+  const int n_views = (int)ctx->bwd_views.size();
+  std::vector<ViewDev> views = ctx->bwd_views;
+  for (int v = 0; v < n_views; ++v) {
+    if (!dL_drgb[v]) return fail(ctx, NXS_EINVAL, "view %d: null dL_drgb", v);
+    views[v].g_rgb = dL_drgb[v];
+    views[v].g_trans = dL_dtrans ? dL_dtrans[v] : nullptr;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamWaitEvent(s, ctx->done, 0));
+  nxs_status st;
+  const int64_t S = (int64_t)g.n * n_views;
+  if ((st = ensure(ctx, ctx->gslot, 36 * (size_t)S))) return st;
+  // pageable source: the copy has consumed `views` when the call returns
+  HIP_TRY(hipMemcpyAsync(ctx->views.p, views.data(), sizeof(ViewDev) * n_views,
+                         hipMemcpyHostToDevice, s));
+  launch_fill_u32(P<uint32_t>(ctx->gslot), 9 * S, 0u, s);
+  launch_composite_bwd(ctx->bwd_model, ctx->bwd_tw, ctx->bwd_th, ctx->last_tiles,
+                       P<ViewDev>(ctx->views), n_views, P<uint2>(ctx->ranges),
+                       P<float4>(ctx->crec), ctx->bwd_cp, P<float4>(ctx->pstate),
+                       P<float>(ctx->gslot), s);
+  GaussDev gd{g.means, g.scales, g.quats, g.opacities, g.sh, g.n, g.sh_degree};
+  GaussGradDev gg{grads->means, grads->scales, grads->quats, grads->opacities, grads->sh};
+  launch_project_bwd(gd, P<ViewDev>(ctx->views), n_views, P<float>(ctx->gslot), gg, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(ctx->done, s));
   return NXS_OK;
 }
 

@@ -18,85 +18,16 @@
 //   L += E p, overdraw += 1 for every composited splat.
 // A wave leaves the tile when a ballot finds all its pixels stopped.
 #include "nxs_internal.h"
+#include "nxs_ops.h"
 
 namespace nxs {
 
 namespace {
 
-// Per-pixel state and update of a Table 1 operator.  MODEL: 0 exponential,
-// 1 linear, 2 quadratic c = -0.5, 3 quadratic c = +0.5, 4 quadratic with
-// c = param, 5 blended (gamma = param), 6 Vicini et al. (gamma = param),
-// 7 power law (v = param).  `step` composites one splat of opacity a >=
-// alpha_min and returns its p; `done` is set once the pixel stops.
-template <int MODEL>
-struct Op {
-  float S = 0.0f;      // running sum of p (T = 1 - S)
-  float tau = 0.0f;    // discrete optical depth
-  float T = 1.0f;      // running product of (1 - a) (exponential parts)
-  float S2 = 0.0f;     // Vicini: linear part's running sum
-  bool d1 = false;     // Vicini: linear part saturated
-  bool d2 = false;     // Vicini: exponential part stopped
-
-  __device__ __forceinline__ float saturate(float p, bool& done) {
-    const float Sn = S + p;
-    done = Sn >= 1.0f;
-    p = done ? 1.0f - S : p;
-    S = done ? 1.0f : Sn;
-    return p;
-  }
-  __device__ __forceinline__ float step(float a, float param, float t_eps, bool& done) {
-    if (MODEL == 0) {
-      const float p = a * T;
-      T = T * (1.0f - a);
-      done = !(T >= t_eps) || T == 0.0f;
-      return p;
-    } else if (MODEL == 1) {
-      return saturate(a, done);
-    } else if (MODEL <= 4) {
-      const float c = MODEL == 2 ? -0.5f : MODEL == 3 ? 0.5f : param;
-      const float p = a * fmaf(c, tau, 1.0f);
-      tau += a;
-      return saturate(p, done);
-    } else if (MODEL == 5) {
-      const float p = a * fmaf(param, T, 1.0f - param);
-      T = T * (1.0f - a);
-      return saturate(p, done);
-    } else if (MODEL == 6) {
-      float pl = 0.0f, pe = 0.0f;
-      if (!d1) {
-        const float Sn = S2 + a;
-        d1 = Sn >= 1.0f;
-        pl = d1 ? 1.0f - S2 : a;
-        S2 = d1 ? 1.0f : Sn;
-      }
-      if (!d2) {
-        pe = a * T;
-        T = T * (1.0f - a);
-        d2 = !(T >= t_eps) || T == 0.0f;
-      }
-      done = d1 && d2;
-      return fmaf(param, pe - pl, pl);
-    } else {
-      const float base = fmaf(param, tau, 1.0f);
-      tau += a;
-      const float p = base > 0.0f
-                          ? a * __builtin_amdgcn_exp2f(-(1.0f + param) / param *
-                                                      __builtin_amdgcn_logf(base))
-                          : __builtin_inff();
-      return saturate(p, done);
-    }
-  }
-  __device__ __forceinline__ float transmittance(float param) const {
-    if (MODEL == 0) return T;
-    if (MODEL == 6) return fmaf(param, T - (1.0f - S2), 1.0f - S2);
-    return 1.0f - S;
-  }
-};
-
-template <int MODEL, int TW, int TH>
+template <int MODEL, int TW, int TH, bool STATE>
 __global__ __launch_bounds__(TW* TH) void composite_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const float4* __restrict__ crec, CompositeParams prm) {
+    const float4* __restrict__ crec, CompositeParams prm, float4* __restrict__ pstate) {
   static_assert(TW % 8 == 0 && TH % 8 == 0, "waves cover 8x8 blocks");
   const uint32_t tile = blockIdx.x;
   int vi = 0;
@@ -129,6 +60,10 @@ __global__ __launch_bounds__(TW* TH) void composite_kernel(
   float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f;
   int od = 0;
   bool done = !inside;
+  // backward state (linear and quadratic): E_k, tau_k, U
+  constexpr bool kSat = STATE && MODEL >= 1 && MODEL <= 4;
+  float ek0 = prm.bg[0], ek1 = prm.bg[1], ek2 = prm.bg[2], tau_s = 0.0f;
+  float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
 
   // Batches of 64 splats: lane j reads the block bits of splat (base + j)
   // (one coalesced load); a ballot gives the wave a bitmap of the splats whose
@@ -167,6 +102,18 @@ __global__ __launch_bounds__(TW* TH) void composite_kernel(
           if (e >= amin) {
             const float a = __builtin_amdgcn_exp2f(e);
             const float p = op.step(a, param, t_eps, done);
+            if (kSat) {
+              if (done) {
+                ek0 = cur[q][6];
+                ek1 = cur[q][7];
+                ek2 = cur[q][8];
+              } else {
+                u0 = fmaf(cur[q][6], a, u0);
+                u1 = fmaf(cur[q][7], a, u1);
+                u2 = fmaf(cur[q][8], a, u2);
+                tau_s += a;
+              }
+            }
             L0 = fmaf(cur[q][6], p, L0);
             L1 = fmaf(cur[q][7], p, L1);
             L2 = fmaf(cur[q][8], p, L2);
@@ -185,37 +132,48 @@ __global__ __launch_bounds__(TW* TH) void composite_kernel(
     v.rgb[3 * pix + 2] = L2 + prm.bg[2] * Tf;
     v.trans[pix] = Tf;
     if (v.od) v.od[pix] = od;
+    if (STATE) {
+      float4* st = pstate + 3 * (v.pix_off + pix);
+      st[0] = make_float4(L0 + prm.bg[0] * Tf, L1 + prm.bg[1] * Tf, L2 + prm.bg[2] * Tf, Tf);
+      st[1] = make_float4(ek0, ek1, ek2, tau_s);
+      st[2] = make_float4(u0, u1, u2, 0.0f);
+    }
   }
 }
 
 template <int MODEL, int TW, int TH>
 void launch_t(int64_t n_tiles, const ViewDev* views, int n_views, const uint2* ranges,
-              const float4* crec, const CompositeParams& p, hipStream_t s) {
-  hipLaunchKernelGGL((composite_kernel<MODEL, TW, TH>), dim3((unsigned)n_tiles),
-                     dim3(TW * TH), 0, s, views, n_views, ranges, crec, p);
+              const float4* crec, const CompositeParams& p, float4* pstate, hipStream_t s) {
+  if (pstate)
+    hipLaunchKernelGGL((composite_kernel<MODEL, TW, TH, true>), dim3((unsigned)n_tiles),
+                       dim3(TW * TH), 0, s, views, n_views, ranges, crec, p, pstate);
+  else
+    hipLaunchKernelGGL((composite_kernel<MODEL, TW, TH, false>), dim3((unsigned)n_tiles),
+                       dim3(TW * TH), 0, s, views, n_views, ranges, crec, p, pstate);
 }
 
 template <int MODEL>
 void launch_m(int tile_w, int tile_h, int64_t n_tiles, const ViewDev* views, int n_views,
               const uint2* ranges, const float4* crec, const CompositeParams& p,
-              hipStream_t s) {
+              float4* pstate, hipStream_t s) {
   if (tile_w == 8 && tile_h == 8)
-    launch_t<MODEL, 8, 8>(n_tiles, views, n_views, ranges, crec, p, s);
+    launch_t<MODEL, 8, 8>(n_tiles, views, n_views, ranges, crec, p, pstate, s);
   else if (tile_w == 32 && tile_h == 8)
-    launch_t<MODEL, 32, 8>(n_tiles, views, n_views, ranges, crec, p, s);
+    launch_t<MODEL, 32, 8>(n_tiles, views, n_views, ranges, crec, p, pstate, s);
   else
-    launch_t<MODEL, 16, 16>(n_tiles, views, n_views, ranges, crec, p, s);
+    launch_t<MODEL, 16, 16>(n_tiles, views, n_views, ranges, crec, p, pstate, s);
 }
 
 }  // namespace
 
 void launch_composite(int model, int tile_w, int tile_h, int64_t n_tiles,
                       const ViewDev* views, int n_views, const uint2* ranges,
-                      const float4* crec, const CompositeParams& p, hipStream_t s) {
+                      const float4* crec, const CompositeParams& p, float4* pstate,
+                      hipStream_t s) {
   if (n_tiles <= 0) return;
   switch (model) {
 #define NXS_M(M) \
-  case M: launch_m<M>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, s); break;
+  case M: launch_m<M>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, pstate, s); break;
     NXS_M(0) NXS_M(1) NXS_M(2) NXS_M(3) NXS_M(4) NXS_M(5) NXS_M(6) NXS_M(7)
 #undef NXS_M
     default: break;

@@ -16,9 +16,12 @@ struct ViewDev {
   int32_t tiles_x, tiles_y;
   int32_t tile_off;         // first global tile of this view
   int32_t pad_;
+  int64_t pix_off;          // first pixel of this view in per-pixel state buffers
   float* rgb;               // [H, W, 3]
   float* trans;             // [H, W]
   int32_t* od;              // [H, W] or null
+  const float* g_rgb;       // backward: dLoss/drgb [H, W, 3]
+  const float* g_trans;     // backward: dLoss/dtrans [H, W] or null
 };
 
 struct GaussDev {
@@ -84,7 +87,8 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s);
 //   r, g, b            emission
 //   mask               bit i set if the box where alpha >= alpha_min reaches
 //                      the tile's i-th 8x8 pixel block (row-major)
-//   0, 0
+//   slot               the projected slot (view * n + Gaussian), for gradients
+//   0
 void launch_ranges_gather(const uint32_t* inst_tile, const uint32_t* inst_val,
                           int64_t m, const ProjDev& proj, const ViewDev* views,
                           int n_views, int tile_w, int tile_h, float log2_alpha_min,
@@ -97,8 +101,33 @@ struct CompositeParams {
   float bg[3];
   int32_t lds_batch;
 };
+// pstate: null, or 3 float4 per pixel kept for the backward pass:
+//   (L0, L1, L2, T_final), (E_k, tau_k), (U, 0) with E_k the saturating splat's
+//   emission (background if none), tau_k the optical depth before it and
+//   U = sum_{j<k} E_j alpha_j.
 void launch_composite(int model, int tile_w, int tile_h, int64_t n_tiles,
                       const ViewDev* views, int n_views, const uint2* ranges,
-                      const float4* crec, const CompositeParams& p, hipStream_t s);
+                      const float4* crec, const CompositeParams& p, float4* pstate,
+                      hipStream_t s);
+
+// Path-replay backward of the composite (models 0..4): per-slot gradients
+// gslot[9 * slot + f] for f = dLoss/d(opacity, u, v, conic A, B, C, r, g, b),
+// accumulated with atomics (the caller zeroes gslot).
+void launch_composite_bwd(int model, int tile_w, int tile_h, int64_t n_tiles,
+                          const ViewDev* views, int n_views, const uint2* ranges,
+                          const float4* crec, const CompositeParams& p,
+                          const float4* pstate, float* gslot, hipStream_t s);
+
+// Gradients of the Gaussians' parameters from the per-slot gradients (summed
+// over views; overwrites the outputs).
+struct GaussGradDev {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opac;
+  float* sh;
+};
+void launch_project_bwd(const GaussDev& g, const ViewDev* views, int n_views,
+                        const float* gslot, const GaussGradDev& out, hipStream_t s);
 
 }  // namespace nxs

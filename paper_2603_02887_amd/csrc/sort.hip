@@ -432,7 +432,7 @@ __global__ __launch_bounds__(256) void ranges_gather_kernel(
   }
   crec[3 * j + 0] = make_float4(du, dv, r1.x, r1.y);
   crec[3 * j + 1] = make_float4(r1.z, r1.w, r2.x, r2.y);
-  crec[3 * j + 2] = make_float4(r2.z, __uint_as_float(mask), 0.0f, 0.0f);
+  crec[3 * j + 2] = make_float4(r2.z, __uint_as_float(mask), __uint_as_float(slot), 0.0f);
 }
 
 }  // namespace

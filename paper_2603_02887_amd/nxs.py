@@ -6,6 +6,7 @@ include/nxs.h and passes device pointers and the current HIP stream.
 Loading fails loudly when libnxs.so has not been built.
 """
 import ctypes
+import math
 from ctypes import POINTER, byref, c_float, c_int32, c_int64, c_uint32, c_uint64, c_void_p
 from pathlib import Path
 
@@ -18,7 +19,8 @@ MODEL_IDS = {"exponential": 0, "linear": 1, "sublinear": 2, "superlinear": 3,
              "quadratic": 4, "blended": 5, "vicini": 6, "powerlaw": 7}
 STATUS = {0: "NXS_OK", -1: "NXS_EINVAL", -2: "NXS_ENOMEM", -3: "NXS_EHIP",
           -4: "NXS_ECAPACITY", -5: "NXS_EUNSUPPORTED"}
-SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_last_error",
+SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_render_backward",
+           "nxs_last_error",
            "nxs_set_timing", "nxs_inspect_stage_times", "nxs_inspect_counts", "nxs_inspect_instances", "nxs_inspect_ranges",
            "nxs_inspect_projection"]
 
@@ -44,11 +46,16 @@ class Camera(ctypes.Structure):
 class RenderOpts(ctypes.Structure):
     _fields_ = [("model", c_int32), ("background", c_float * 3), ("alpha_min", c_float),
                 ("t_eps", c_float), ("tile_w", c_int32), ("tile_h", c_int32),
-                ("lds_batch", c_int32), ("param", c_float)]
+                ("lds_batch", c_int32), ("param", c_float), ("keep_state", c_int32)]
 
 
 class Image(ctypes.Structure):
     _fields_ = [("rgb", c_void_p), ("trans", c_void_p), ("overdraw", c_void_p)]
+
+
+class GaussiansGrad(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p),
+                ("opacities", c_void_p), ("sh", c_void_p)]
 
 
 _lib = None
@@ -66,6 +73,8 @@ def lib():
         L.nxs_destroy.argtypes = [c_void_p]
         L.nxs_render_forward.argtypes = [c_void_p, POINTER(Gaussians), POINTER(Camera), c_int32,
                                          POINTER(RenderOpts), POINTER(Image), c_void_p]
+        L.nxs_render_backward.argtypes = [c_void_p, c_void_p, c_void_p,
+                                          POINTER(GaussiansGrad), c_void_p]
         L.nxs_last_error.argtypes = [c_void_p]
         L.nxs_last_error.restype = ctypes.c_char_p
         L.nxs_set_timing.argtypes = [c_void_p, c_int32]
@@ -122,6 +131,8 @@ class Renderer:
         if st != 0:
             raise NxsError(st, "nxs_create failed")
         self.device = torch.device("cuda", int(device))
+        self.generation = 0      # forwards issued on this context
+        self._last_shapes = []
 
     def close(self):
         if self._ctx:
@@ -141,7 +152,7 @@ class Renderer:
 
     def render(self, g, cams, model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0,
                t_eps=0.0, tile=(16, 16), lds_batch=0, outputs=None, overdraw=True,
-               stream=None, param=0.0):
+               stream=None, param=0.0, keep_state=False):
         """Render the Gaussians `g` (dict of GPU tensors, see scene_to_device) in
         every camera of `cams`.  Returns a list of dicts {rgb [H,W,3], trans [H,W],
         overdraw [H,W] int32} (or fills `outputs`, a list of such dicts)."""
@@ -184,12 +195,59 @@ class Renderer:
         opts.tile_w, opts.tile_h = int(tile[0]), int(tile[1])
         opts.lds_batch = int(lds_batch)
         opts.param = float(param)
+        opts.keep_state = int(bool(keep_state))
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         st = self._L.nxs_render_forward(self._ctx, byref(gs), carr, V, byref(opts), imgs,
                                         c_void_p(stream.cuda_stream))
+        self.generation += 1
+        self._last_shapes = [(int(c.height), int(c.width)) for c in cams]
         self._check(st)
         return outputs
+
+    def backward(self, g, dL_drgb, dL_dtrans=None, stream=None):
+        """Gradients of the Gaussians (dict of tensors shaped like `g`) from the
+        upstream gradients of the last forward, which had keep_state=True:
+        dL_drgb a list of [H,W,3] per view, dL_dtrans None or a list of [H,W]
+        (entries may be None)."""
+        V = len(dL_drgb)
+        if V != len(self._last_shapes):
+            raise ValueError(f"{V} upstream gradients for {len(self._last_shapes)} views")
+        if dL_dtrans is not None and len(dL_dtrans) != V:
+            raise ValueError("dL_dtrans needs one entry per view")
+        keep = []
+        for v, (H, W) in enumerate(self._last_shapes):
+            t = _f32(dL_drgb[v].contiguous(), "dL_drgb")
+            if tuple(t.shape) != (H, W, 3):
+                raise ValueError(f"view {v}: dL_drgb must be [{H},{W},3]")
+            keep.append(t)
+            if dL_dtrans is not None and dL_dtrans[v] is not None:
+                t = _f32(dL_dtrans[v].contiguous(), "dL_dtrans")
+                if tuple(t.shape) != (H, W):
+                    raise ValueError(f"view {v}: dL_dtrans must be [{H},{W}]")
+                keep.append(t)
+            else:
+                keep.append(None)
+        rgb_ptrs = (c_void_p * V)(*[keep[2 * v].data_ptr() for v in range(V)])
+        tr_ptrs = None
+        if dL_dtrans is not None:
+            tr_ptrs = (c_void_p * V)(*[(keep[2 * v + 1].data_ptr()
+                                        if keep[2 * v + 1] is not None else None)
+                                       for v in range(V)])
+        out = {k: torch.empty_like(g[k]) for k in ("means", "scales", "quats", "opacities", "sh")}
+        gg = GaussiansGrad(out["means"].data_ptr(), out["scales"].data_ptr(),
+                           out["quats"].data_ptr(), out["opacities"].data_ptr(),
+                           out["sh"].data_ptr())
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        elif stream != torch.cuda.current_stream(self.device):
+            for t in keep:
+                if t is not None:
+                    t.record_stream(stream)
+        st = self._L.nxs_render_backward(self._ctx, rgb_ptrs, tr_ptrs, byref(gg),
+                                         c_void_p(stream.cuda_stream))
+        self._check(st)
+        return out
 
     # -------------------------------------------------------- inspection
     STAGES = ("project", "depth_sort", "emit", "tile_sort", "gather", "composite")
@@ -228,3 +286,43 @@ class Renderer:
         self._check(self._L.nxs_inspect_projection(self._ctx, int(view), d.ctypes.data,
                                                    r.ctypes.data, max(n, 1)))
         return d[:n], r[:4 * n].reshape(n, 4)
+
+
+class RenderFunction(torch.autograd.Function):
+    """Differentiable render: (means, scales, quats, opacities, sh) -> per view
+    (rgb [H,W,3], trans [H,W]).  The backward is the library's path replay; it
+    must run before the next forward on the same Renderer."""
+
+    @staticmethod
+    def forward(ctx, renderer, cams, opts, means, scales, quats, opacities, sh):
+        g = {"means": means.detach().contiguous(), "scales": scales.detach().contiguous(),
+             "quats": quats.detach().contiguous(), "opacities": opacities.detach().contiguous(),
+             "sh": sh.detach().contiguous(),
+             "sh_degree": int(round(math.sqrt(sh.shape[1]))) - 1}
+        outs = renderer.render(g, cams, keep_state=True, overdraw=False, **opts)
+        ctx.renderer, ctx.g, ctx.gen = renderer, g, renderer.generation
+        ctx.shapes = [(o["rgb"].shape, o["trans"].shape) for o in outs]
+        return tuple(o["rgb"] for o in outs) + tuple(o["trans"] for o in outs)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        r = ctx.renderer
+        if r.generation != ctx.gen:
+            raise RuntimeError("another forward ran on this Renderer since this one; "
+                               "its backward state is gone")
+        V = len(ctx.shapes)
+        d_rgb = [gr if gr is not None else torch.zeros(sh[0], device=r.device)
+                 for gr, sh in zip(grads[:V], ctx.shapes)]
+        d_tr = list(grads[V:])
+        if all(t is None for t in d_tr):
+            d_tr = None
+        gr = r.backward(ctx.g, d_rgb, d_tr)
+        return (None, None, None, gr["means"], gr["scales"], gr["quats"], gr["opacities"],
+                gr["sh"])
+
+
+def render(renderer, cams, means, scales, quats, opacities, sh, **opts):
+    """Differentiable multi-view render; returns (list of rgb, list of trans)."""
+    out = RenderFunction.apply(renderer, list(cams), opts, means, scales, quats, opacities, sh)
+    V = len(cams)
+    return list(out[:V]), list(out[V:])

@@ -39,6 +39,26 @@ FLOPS_PER_PAIR = {0: 20, 1: 18, 2: 22, 3: 22}
 FP32_VALU_PEAK_TFLOPS = 78.6432
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of each composite kernel on this workload (16x16 tiles),
+# from FETCH_SIZE and WRITE_SIZE counter runs scaled by a copy kernel of known
+# size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
+# kernel sources with this digest and are reported as null once those change.
+TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_internal.h")
+TRAFFIC = {"digest": "31588bf2bd7b58bd82d2cd0697051e9e4ceb9348f561bc36f1012245ce5ad962",
+           "tile": "16x16",
+           "bytes": {0: 160910303, 1: 96811032, 2: 107176219, 3: 93414705}}
+
+
+def measured_traffic(model, tile):
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_02887_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["digest"] or tile != TRAFFIC["tile"]:
+        return None
+    return TRAFFIC["bytes"].get(model)
+
 
 def percentile(xs, q):
     xs = sorted(xs)
@@ -50,31 +70,41 @@ def percentile(xs, q):
 
 
 def cpu_baseline(scene, cam, n_pixels, seed=123):
-    """Time the CPU oracle on a random pixel sample of the frame, per model,
-    and extrapolate to the full frame (setup + per-pixel time x pixels)."""
+    """Time the CPU oracle (single thread) on a random pixel sample of the frame,
+    per model, and extrapolate to the full frame: the model-independent set-up
+    (projection, key replay) once, then per model a 1-pixel render (its
+    pruning lists) and an n-pixel render; per-pixel time = their difference
+    / (n - 1)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import keys as okeys
+    from oracle import project as oproject
     from oracle import render as orender
     rng = np.random.default_rng(seed)
     flat = rng.choice(cam.width * cam.height, n_pixels, replace=False)
     pix = np.stack([flat % cam.width, flat // cam.width], 1)
-    one = pix[:1]
     frame_s = []
     t_all = time.perf_counter()
-    for m in range(4):
+    with threadpool_limits(1):
         t0 = time.perf_counter()
-        orender.render(scene, cam, m, pixels=one)
-        t_setup = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        orender.render(scene, cam, m, pixels=pix)
-        t_s = time.perf_counter() - t0
-        per_px = max(t_s - t_setup, 0.0) / n_pixels
-        frame_s.append(t_setup + per_px * cam.width * cam.height)
+        proj = oproject.project(scene, cam)
+        geom = okeys.geometry(scene, cam)
+        t_common = time.perf_counter() - t0
+        for m in range(4):
+            t0 = time.perf_counter()
+            orender.render(scene, cam, m, pixels=pix[:1], proj=proj, geom=geom)
+            t1 = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            orender.render(scene, cam, m, pixels=pix, proj=proj, geom=geom)
+            tn = time.perf_counter() - t0
+            per_px = max(tn - t1, 0.0) / (n_pixels - 1)
+            frame_s.append(t_common + t1 + per_px * cam.width * cam.height)
     spent = time.perf_counter() - t_all
     mpix = 4 * cam.width * cam.height / sum(frame_s) / 1e6
     return {"value": mpix, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
             "sample": (f"{n_pixels} random pixels of the 1920x1080 frame per model "
-                       f"(4 models) plus one 1-pixel call per model for the setup "
-                       f"(projection, key replay, pruning lists); full-frame time = "
-                       f"setup + sample time x W*H/{n_pixels}; {spent:.1f} s of CPU"),
+                       f"(4 models), one thread; full-frame time = set-up (projection "
+                       f"and key replay of all 1M Gaussians, once) + per-model pruning "
+                       f"lists + per-pixel time x W*H; {spent:.1f} s of CPU"),
             "frame_seconds": {MODELS[m]: frame_s[m] for m in range(4)}}
 
 
@@ -85,7 +115,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--lds-batch", type=int, default=256)
-    ap.add_argument("--cpu-pixels", type=int, default=256)
+    ap.add_argument("--cpu-pixels", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device-to-device copy (untimed) so that "
@@ -108,10 +138,11 @@ def main():
         sys.exit(1)
     tw, th = (int(x) for x in args.tile.split("x"))
     if args.copy_calibration:
+        # an elementwise kernel that reads 256 MiB and writes 256 MiB
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     scene, cams = synth.scene_scale()
@@ -174,7 +205,7 @@ def main():
         roofline = {"bound": "alu", "kernel": f"composite<{MODELS[dm]}>",
                     "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-                    "traffic": None,
+                    "traffic": measured_traffic(dm, f"{tw}x{th}"),
                     "work_per_launch": {"composited_pairs": od_sum[dm],
                                         "flops_per_pair": FLOPS_PER_PAIR[dm]},
                     "avg_launch_ms": dms}

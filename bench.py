@@ -108,6 +108,143 @@ def cpu_baseline(scene, cam, n_pixels, seed=123):
             "frame_seconds": {MODELS[m]: frame_s[m] for m in range(4)}}
 
 
+def batched_views(R, torch, nxs, synth, steps, models=(0, 1, 2, 3)):
+    """Multi-view batch: 3M Gaussians (256-cluster means), 16 views of uneven
+    size.  Per model: one batched render of all views with the autotuned tile
+    shape and schedule, the same with the default tile/schedule, and one render
+    per view (16 calls), each timed over `steps` repetitions after a warm-up."""
+    scene, cams = synth.batched_scene()
+    g = nxs.scene_to_device(scene)
+    pix = sum(c.width * c.height for c in cams)
+    outs = [{"rgb": torch.empty((c.height, c.width, 3), device="cuda"),
+             "trans": torch.empty((c.height, c.width), device="cuda"), "overdraw": None}
+            for c in cams]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(steps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    res = {}
+    for m in models:
+        tune = R.autotune(g, cams, model=m, outputs=outs, reps=3)
+        t_tuned = timed(lambda: R.render(g, cams, model=m, tile=tune["tile"],
+                                         schedule=tune["schedule"], outputs=outs))
+        t_default = timed(lambda: R.render(g, cams, model=m, outputs=outs))
+        t_per_view = timed(lambda: [R.render(g, [c], model=m, tile=tune["tile"],
+                                             schedule=tune["schedule"], outputs=[o])
+                                    for c, o in zip(cams, outs)])
+        n_inst, _ = R.counts()
+        res[MODELS[m]] = {"batched_ms": t_tuned, "batched_default_ms": t_default,
+                          "per_view_ms": t_per_view, "mpix_per_s": pix / t_tuned / 1e3,
+                          "tuned": {"tile": "%dx%d" % tune["tile"],
+                                    "schedule": tune["schedule"]},
+                          "speedup_vs_per_view": t_per_view / t_tuned}
+    return {"workload": ("3,000,000 Gaussians (means from 256 clusters), SH degree 0, "
+                         "16 views of uneven size on a radius-15 orbit"),
+            "pixels": pix, "views": len(cams), "per_model": res}
+
+
+SERVE_SIZES = [(512, 512), (1280, 720), (1920, 1080)]
+
+
+def serving(args, torch, nxs, synth):
+    """Serving workload: four resident scenes (200k, 500k, 1M, 3M Gaussians);
+    each request picks a scene, an eye at radius U[3,6], azimuth U[0,2pi),
+    elevation U[-30,30] deg, a resolution from SERVE_SIZES and a model, all
+    uniformly.  First the saturation rate (a burst of requests all queued at
+    once), then Poisson arrivals at fractions of it; latency = arrival ->
+    result ready.  Prints one JSON line."""
+    rng = np.random.default_rng(50)
+    scenes = synth.serving_scenes()
+    S = nxs.Server(0, workspace_budget=args.serve_budget_gib << 30, max_batch_views=16)
+    ids = [S.add_scene(nxs.scene_to_device(sc)) for sc in scenes]
+    pool = {wh: [] for wh in SERVE_SIZES}
+
+    def draw():
+        w, h = SERVE_SIZES[rng.integers(len(SERVE_SIZES))]
+        r, az = rng.uniform(3, 6), rng.uniform(0, 2 * math.pi)
+        el = math.radians(rng.uniform(-30, 30))
+        eye = (r * math.cos(el) * math.sin(az), r * math.sin(el),
+               -r * math.cos(el) * math.cos(az))
+        return (int(rng.integers(len(scenes))), synth.look_at_camera(eye, width=w, height=h),
+                int(rng.integers(4)))
+
+    def out_for(cam):
+        free = pool[(cam.width, cam.height)]
+        if free:
+            return free.pop()
+        return {"rgb": torch.empty((cam.height, cam.width, 3), device="cuda"),
+                "trans": torch.empty((cam.height, cam.width), device="cuda"),
+                "overdraw": None}
+
+    def run(arrivals, reqs):
+        """Serve requests arriving at `arrivals` (seconds from now); returns
+        per-request latency (s), wall time and pixels served."""
+        t0 = time.perf_counter()
+        n, nxt, lat, pix = len(reqs), 0, [0.0] * len(reqs), 0
+        cams = {}
+        while nxt < n or S.pending:
+            now = time.perf_counter() - t0
+            while nxt < n and arrivals[nxt] <= now:
+                sc, cam, m = reqs[nxt]
+                S.submit(ids[sc], cam, nxt, outputs=out_for(cam), model=m)
+                cams[nxt] = cam
+                nxt += 1
+            if S.pending:
+                for tag, st, out in S.step():
+                    if st != 0:
+                        raise RuntimeError(f"request {tag} failed with status {st}")
+                    lat[tag] = time.perf_counter() - t0 - arrivals[tag]
+                    cam = cams.pop(tag)
+                    pix += cam.width * cam.height
+                    pool[(cam.width, cam.height)].append(out)
+            elif nxt < n:
+                time.sleep(max(0.0, min(arrivals[nxt] - now, 0.002)))
+        return lat, time.perf_counter() - t0, pix
+
+    # warm-up, then the saturation rate from a burst
+    run([0.0] * 32, [draw() for _ in range(32)])
+    burst = [draw() for _ in range(args.serve_burst)]
+    lat_b, wall_b, pix_b = run([0.0] * len(burst), burst)
+    rate_sat = len(burst) / wall_b
+    loads = []
+    for frac in (0.25, 0.5, 0.8, 1.0):
+        lam = frac * rate_sat
+        n = args.serve_warmup + args.serve_requests
+        arr = np.cumsum(rng.exponential(1.0 / lam, n))
+        reqs = [draw() for _ in range(n)]
+        lat, wall, pix = run(list(arr), reqs)
+        meas = lat[args.serve_warmup:]
+        loads.append({"load": frac, "rate_req_per_s": lam,
+                      "achieved_req_per_s": n / wall, "mpix_per_s": pix / wall / 1e6,
+                      "p50_ms": percentile(meas, 50) * 1e3, "p99_ms": percentile(meas, 99) * 1e3,
+                      "mean_ms": float(np.mean(meas)) * 1e3})
+        print(f"serving load {frac}: p50 {loads[-1]['p50_ms']:.2f} ms p99 "
+              f"{loads[-1]['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+    line = {"metric": "serving: Mpix/s at saturation; p50/p99 request latency under Poisson load",
+            "value": pix_b / wall_b / 1e6, "unit": "Mpix/s", "n_gpus": 1,
+            "steps": args.serve_requests, "warmup": args.serve_warmup,
+            "ms_per_step": wall_b / len(burst) * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": ("serving: resident scenes of 200k/500k/1M/3M Gaussians, "
+                                    "requests uniform over scene, pose, resolution "
+                                    "(512x512, 1280x720, 1920x1080) and the four models"),
+                       "workspace_budget_gib": args.serve_budget_gib, "max_batch_views": 16},
+            "saturation": {"requests": len(burst), "req_per_s": rate_sat,
+                           "p50_ms": percentile(lat_b, 50) * 1e3,
+                           "p99_ms": percentile(lat_b, 99) * 1e3},
+            "poisson": loads}
+    S.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[1])
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +254,16 @@ def main():
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--cpu-pixels", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 16-view batched workload")
+    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--workload", choices=("scene", "serving"), default="scene",
+                    help="scene: the 1M-Gaussian 1080p forward (default); serving: the "
+                         "continuous-batching server under Poisson load")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-burst", type=int, default=400)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device-to-device copy (untimed) so that "
                          "counter runs can scale FETCH_SIZE / WRITE_SIZE by a kernel "
@@ -136,6 +283,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "serving":
+        serving(args, torch, nxs, synth)
+        return
     tw, th = (int(x) for x in args.tile.split("x"))
     if args.copy_calibration:
         # an elementwise kernel that reads 256 MiB and writes 256 MiB
@@ -219,6 +369,10 @@ def main():
     for name in MODELS[1:]:
         per_model[name]["speedup_vs_exponential"] = exp_ms / per_model[name]["p50_ms"]
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_views(R, torch, nxs, synth, args.batched_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, cam, args.cpu_pixels)
@@ -237,6 +391,7 @@ def main():
         "per_model": per_model,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     R.close()
     print(json.dumps(line), flush=True)

@@ -44,7 +44,10 @@ typedef enum {
   NXS_EINVAL = -1,       /* bad argument; nothing was launched */
   NXS_ENOMEM = -2,       /* workspace allocation failed */
   NXS_EHIP = -3,         /* a HIP runtime call failed; see nxs_last_error */
-  NXS_ECAPACITY = -4,    /* instance count exceeds the 32-bit index range */
+  NXS_ECAPACITY = -4,    /* more than 2^32 - 1 tile instances, or more workspace
+                            than the context's limit allows (outputs undefined;
+                            retry with fewer views or after
+                            nxs_release_workspace) */
   NXS_EUNSUPPORTED = -5  /* feature not available in this build */
 } nxs_status;
 
@@ -123,7 +126,20 @@ typedef struct {
                              composite walks its tile in batches of 64 splats) */
   float param;            /* operator parameter of models 4..7 (c, gamma or v) */
   int32_t keep_state;     /* nonzero: keep what nxs_render_backward needs */
+  int32_t schedule;       /* nxs_schedule of the composite; 0 -> NXS_SCHED_TILES */
 } nxs_render_opts;
+
+/* How the composite's work is laid onto the GPU (results are bitwise the same
+ * under all three; only the time differs):
+ *   TILES   one work-group per tile, one wave per 8x8 block of it
+ *   BLOCKS  one single-wave work-group per 8x8 block
+ *   QUEUE   persistent single-wave work-groups taking blocks from one atomic
+ *           queue over all views' tiles, longest tile lists first */
+typedef enum {
+  NXS_SCHED_TILES = 1,
+  NXS_SCHED_BLOCKS = 2,
+  NXS_SCHED_QUEUE = 3
+} nxs_schedule;
 
 /* Per-view outputs (device pointers), row-major:
  *   rgb       [H, W, 3] float32   pixel value L0
@@ -182,6 +198,73 @@ nxs_status nxs_render_backward(nxs_context* ctx, const float* const* dL_drgb,
                                const float* const* dL_dtrans,
                                const nxs_gaussians_grad* grads, void* stream);
 
+/* Measured choice of tile shape and composite schedule for one workload. */
+typedef struct {
+  int32_t tile_w, tile_h;
+  int32_t schedule;       /* nxs_schedule */
+  float ms;               /* median render time of the choice when measured */
+} nxs_tuning;
+
+/* Autotuner: the tile shape (8x8, 16x16, 32x8) and composite schedule with the
+ * lowest median time of a whole nxs_render_forward on this workload.
+ * The result is cached per (GPU architecture, CU count, n, SH degree, model,
+ * number and sizes of the views): first in the context, then, if cache_path
+ * is not NULL, in that text file (one line per workload; read on a miss,
+ * appended after a sweep).  On a cache hit nothing is rendered.  On a miss
+ * every candidate is rendered once untimed and `reps` times (0 -> 5) timed
+ * with events on `stream`, writing `out` (the outputs are those of the last
+ * candidate) and synchronising the stream.  Other fields of `opts` are used
+ * as given; its tile and schedule fields are ignored.  Errors as for
+ * nxs_render_forward; an unreadable or unwritable cache file is ignored. */
+nxs_status nxs_autotune(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* cams,
+                        int32_t n_views, const nxs_render_opts* opts, const nxs_image* out,
+                        const char* cache_path, int32_t reps, nxs_tuning* result,
+                        void* stream);
+
+/* Workspace: the device memory a context keeps between renders (sort
+ * buffers, per-slot and per-instance records), grown on demand and never
+ * shrunk.  With a limit set (bytes; 0 = none), a render that would grow it past
+ * the limit returns NXS_ECAPACITY.  nxs_release_workspace synchronises the
+ * device and frees all of it (it also ends any kept backward state). */
+nxs_status nxs_set_workspace_limit(nxs_context* ctx, size_t bytes);
+nxs_status nxs_workspace_bytes(const nxs_context* ctx, size_t* bytes);
+nxs_status nxs_release_workspace(nxs_context* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Serving: resident scenes and continuous batching under a workspace budget.
+ * A server owns one context on `device` whose workspace limit is
+ * `workspace_budget` bytes (0 = none).  Scenes are caller-owned device arrays
+ * that must stay unchanged and alive while the server uses them.  Requests
+ * queue in submission order; each nxs_server_step serves the oldest pending
+ * request together with later pending requests for the same scene with
+ * identical options (up to max_batch_views, 0 -> 16, and while the estimated
+ * workspace fits the budget) in one multi-view render on `stream`, waits for
+ * it, and reports the completed requests' tags and statuses (NXS_OK, or the
+ * render's error for a request that fails on its own, e.g. NXS_ECAPACITY when
+ * one view alone exceeds the budget).  Results are bitwise those of rendering
+ * each request alone with the same options.  A server is used from one host
+ * thread.
+ * ------------------------------------------------------------------------- */
+typedef struct nxs_server nxs_server;
+
+nxs_status nxs_server_create(int device, size_t workspace_budget, int32_t max_batch_views,
+                             nxs_server** out);
+nxs_status nxs_server_destroy(nxs_server* server);
+/* The server's context (for inspection; do not render on it directly). */
+nxs_context* nxs_server_context(nxs_server* server);
+nxs_status nxs_server_add_scene(nxs_server* server, const nxs_gaussians* g,
+                                int32_t* scene_id);
+/* Queue one view of a scene; `out` (device images, caller-owned) is written
+ * when a step completes the request.  opts.keep_state must be 0. */
+nxs_status nxs_server_submit(nxs_server* server, int32_t scene_id, const nxs_camera* cam,
+                             const nxs_render_opts* opts, const nxs_image* out, int64_t tag);
+/* Serve one batch.  tags / status: host arrays of `capacity` entries; the
+ * first *n_done are filled.  Returns an error only if the stream fails. */
+nxs_status nxs_server_step(nxs_server* server, void* stream, int64_t* tags, int32_t* status,
+                           int32_t capacity, int32_t* n_done);
+int32_t nxs_server_pending(const nxs_server* server);
+const char* nxs_server_last_error(const nxs_server* server);
+
 /* Message for the last non-OK status returned on this context ("" if none).
  * The pointer stays valid until the next call on the context. */
 const char* nxs_last_error(const nxs_context* ctx);
@@ -202,7 +285,8 @@ const char* nxs_last_error(const nxs_context* ctx);
 nxs_status nxs_set_timing(nxs_context* ctx, int32_t enable);
 nxs_status nxs_inspect_stage_times(nxs_context* ctx, float* ms_host, int32_t n);
 
-/* Number of tile instances M and of global tiles of the last render. */
+/* Number of tile instances M and of global tiles of the last render; after a
+ * render that failed with NXS_ECAPACITY once M was known, the M it needed. */
 nxs_status nxs_inspect_counts(nxs_context* ctx, int64_t* n_instances,
                               int64_t* n_tiles);
 

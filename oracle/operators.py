@@ -172,7 +172,13 @@ def composite_sequence(alphas, op, emissions=None, background=None,
             continue
         p = p_unsaturated(op, a, tau, prod)
         p_raw[i] = p
-        if S + p >= 1.0:                 # splat i saturates: it is the k of eq. nexp_p
+        if op.kind == "exponential":
+            # sum p = 1 - prod(1 - alpha) exactly, so T is the product; it
+            # reaches 0 (saturation) only where some alpha is 1
+            S += p
+            T = prod * (1.0 - a)
+            done = T == 0.0
+        elif S + p >= 1.0:               # splat i saturates: it is the k of eq. nexp_p
             p = 1.0 - S
             S, T, done = 1.0, 0.0, True
         else:

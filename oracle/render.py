@@ -20,9 +20,10 @@ That list only prunes; it does not change any result.
 
 Each pixel also gets an `ambiguous` flag, set where float32 rounding on the
 GPU may legitimately take a different discrete decision than this FP64
-evaluation: some considered alpha within 1e-5 relative of alpha_min, or some
-composited step whose transmittance lands within 1e-6 of the cutoff (0 for
-saturation, t_eps for the exponential's termination).
+evaluation: some considered alpha within 1e-5 relative of alpha_min, some
+composited step of a running-sum operator whose transmittance lands within
+1e-6 of 0 (saturation), an exponential step landing within 1e-6 of t_eps
+(termination) or below 1e-30 (where a float32 product may flush to 0).
 """
 import math
 
@@ -35,6 +36,7 @@ from . import project as _project
 CELL = 16
 ALPHA_REL = 1e-5
 CUTOFF_ABS = 1e-6
+UNDERFLOW = 1e-30    # below this a float32 product of (1 - alpha) may flush to 0
 
 
 def _cell_lists(proj, vis_idx, alpha_min, width, height):
@@ -83,7 +85,12 @@ def composite_pixel(alphas, rgb, op, alpha_min, t_eps, background):
             continue
         # transmittance this step would leave before any clamp
         t_next = T[i] - p_raw[i]
-        if abs(t_next) <= CUTOFF_ABS:
+        # the running-sum operators decide saturation where T reaches 0; the
+        # exponential keeps T as a product, which reaches 0 only at alpha = 1
+        # or where float32 underflows
+        if op.kind != "exponential" and abs(t_next) <= CUTOFF_ABS:
+            amb = True
+        if op.kind == "exponential" and t_next < UNDERFLOW:
             amb = True
         if op.kind == "exponential" and t_eps and abs(t_next - t_eps) <= CUTOFF_ABS:
             amb = True

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -30,7 +31,12 @@ struct nxs_context {
   DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, ntiles, rect, prec;
   DevBuf scan_local, block_sums, counts;
   DevBuf inst_tile, inst_tile_alt, inst_val, inst_val_alt;
-  DevBuf crec, ranges, pstate, gslot;
+  DevBuf crec, ranges, pstate, gslot, order, queue;
+  int n_cu = 256;
+  std::string arch;
+  size_t ws_limit = 0;   // 0: no limit on the workspace
+  size_t ws_total = 0;   // bytes currently allocated for the workspace
+  std::map<std::string, nxs_tuning> tuned;   // autotuner results of this process
   Counters* host_counters = nullptr;  // pinned
   ViewDev* host_views = nullptr;      // pinned
   int host_views_cap = 0;
@@ -72,23 +78,35 @@ nxs_status fail(nxs_context* ctx, nxs_status st, const char* fmt, ...) {
       return fail(ctx, NXS_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
   } while (0)
 
+// Grow buffer b to at least `bytes` (with 25% headroom when the workspace
+// limit allows it); never shrinks.  Beyond the context's workspace limit the
+// call fails with NXS_ECAPACITY before freeing anything.
 nxs_status ensure(nxs_context* ctx, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return NXS_OK;
+  size_t want = bytes + bytes / 4;
+  want = (want + 255) & ~(size_t)255;
+  if (ctx->ws_limit) {
+    const size_t others = ctx->ws_total - b.cap;
+    if (others + want > ctx->ws_limit) want = (bytes + 255) & ~(size_t)255;
+    if (others + want > ctx->ws_limit)
+      return fail(ctx, NXS_ECAPACITY, "workspace limit: %zu bytes needed, %zu allowed",
+                  others + want, ctx->ws_limit);
+  }
   if (b.p) {
     hipError_t e = hipFree(b.p);  // hipFree waits for outstanding work on the device
+    ctx->ws_total -= b.cap;
     b.p = nullptr;
     b.cap = 0;
     if (e != hipSuccess) return fail(ctx, NXS_EHIP, "hipFree: %s", hipGetErrorString(e));
   }
-  size_t want = bytes + bytes / 4;
-  want = (want + 255) & ~(size_t)255;
   if (hipMalloc(&b.p, want) != hipSuccess) {
     (void)hipGetLastError();
     b.p = nullptr;
     return fail(ctx, NXS_ENOMEM, "hipMalloc(%zu bytes) failed", want);
   }
   b.cap = want;
+  ctx->ws_total += want;
   return NXS_OK;
 }
 
@@ -104,6 +122,50 @@ int bit_length(uint64_t x) {
 template <typename T>
 T* P(DevBuf& b) {
   return static_cast<T*>(b.p);
+}
+
+}  // namespace
+
+namespace {
+
+std::string tuning_key(const nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* cams,
+                       int32_t n_views, const nxs_render_opts* opts) {
+  char buf[160];
+  snprintf(buf, sizeof(buf), "%s|cu%d|n%d|sh%d|m%d|p%.6g|v%d", ctx->arch.c_str(), ctx->n_cu,
+           g->n, g->sh_degree, opts->model, (double)opts->param, n_views);
+  std::string k = buf;
+  for (int v = 0; v < n_views; ++v) {
+    snprintf(buf, sizeof(buf), "|%dx%d", cams[v].width, cams[v].height);
+    k += buf;
+  }
+  return k;
+}
+
+bool read_cache(const char* path, const std::string& key, nxs_tuning* t) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[4096];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    char k[4000];
+    nxs_tuning r{};
+    if (sscanf(line, "%3999s %d %d %d %f", k, &r.tile_w, &r.tile_h, &r.schedule, &r.ms) == 5 &&
+        key == k) {
+      *t = r;   // the last line for a key wins
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void append_cache(const char* path, const std::string& key, const nxs_tuning& t) {
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d %d %.5f\n", key.c_str(), t.tile_w, t.tile_h, t.schedule, (double)t.ms);
+  fclose(f);
 }
 
 }  // namespace
@@ -127,6 +189,11 @@ nxs_status nxs_create(nxs_context** out, int device) {
     delete ctx;
     return NXS_EHIP;
   }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    ctx->arch = prop.gcnArchName;
+  }
   *out = ctx;
   return NXS_OK;
 }
@@ -140,7 +207,7 @@ nxs_status nxs_destroy(nxs_context* ctx) {
                    &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
                    &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->crec,      &ctx->ranges,
-                   &ctx->pstate,     &ctx->gslot};
+                   &ctx->pstate,     &ctx->gslot,         &ctx->order,     &ctx->queue};
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
@@ -180,6 +247,9 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   int tw = opts->tile_w ? opts->tile_w : 16, th = opts->tile_h ? opts->tile_h : 16;
   if (!((tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 8)))
     return fail(ctx, NXS_EINVAL, "tile size %dx%d not supported (8x8, 16x16, 32x8)", tw, th);
+  const int sched = opts->schedule ? opts->schedule : NXS_SCHED_TILES;
+  if (sched < NXS_SCHED_TILES || sched > NXS_SCHED_QUEUE)
+    return fail(ctx, NXS_EINVAL, "schedule %d not supported (0..3)", opts->schedule);
   int batch = opts->lds_batch ? opts->lds_batch : 256;
   if (batch != 128 && batch != 256 && batch != 512)
     return fail(ctx, NXS_EINVAL, "lds_batch must be 0, 128, 256 or 512");
@@ -270,6 +340,10 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   HIP_TRY(hipMemcpyAsync(ctx->host_counters, dcount, sizeof(Counters), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const uint64_t M = ctx->host_counters->total;
+  // what this render needs, visible through nxs_inspect_counts even if it fails
+  ctx->last_m = (int64_t)M;
+  ctx->last_tiles = total_tiles;
+  ctx->last_inst_tile = ctx->last_inst_val = nullptr;
   if (M >= 0xFFFFFFFFull)
     return fail(ctx, NXS_ECAPACITY, "%llu tile instances exceed the 32-bit range",
                 (unsigned long long)M);
@@ -334,8 +408,15 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   cp.param = param;
   for (int k = 0; k < 3; ++k) cp.bg[k] = opts->background[k];
   cp.lds_batch = batch;
-  launch_composite(opts->model, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),
-                   P<float4>(ctx->crec), cp, pstate, s);
+  CompositeLaunch cl{sched, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),
+                     P<float4>(ctx->crec), nullptr, nullptr, ctx->n_cu};
+  if (sched == NXS_SCHED_QUEUE) {
+    if ((st = ensure(ctx, ctx->order, 4 * (size_t)total_tiles))) return st;
+    if ((st = ensure(ctx, ctx->queue, 4))) return st;
+    cl.order = P<uint32_t>(ctx->order);
+    cl.queue = P<uint32_t>(ctx->queue);
+  }
+  launch_composite(opts->model, cl, cp, pstate, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(7));
   HIP_TRY(hipEventRecord(ctx->done, s));
@@ -404,6 +485,107 @@ nxs_status nxs_render_backward(nxs_context* ctx, const float* const* dL_drgb,
   return NXS_OK;
 }
 
+nxs_status nxs_autotune(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* cams,
+                        int32_t n_views, const nxs_render_opts* opts, const nxs_image* out,
+                        const char* cache_path, int32_t reps, nxs_tuning* result,
+                        void* stream) {
+  if (!ctx) return NXS_EINVAL;
+  ctx->err.clear();
+  if (!g || !cams || !opts || !out || !result || n_views <= 0 || reps < 0)
+    return fail(ctx, NXS_EINVAL, "bad autotune argument");
+  const std::string key = tuning_key(ctx, g, cams, n_views, opts);
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) {
+    *result = it->second;
+    return NXS_OK;
+  }
+  nxs_tuning t{};
+  if (read_cache(cache_path, key, &t)) {
+    ctx->tuned[key] = t;
+    *result = t;
+    return NXS_OK;
+  }
+  if (reps == 0) reps = 5;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ctx, NXS_EHIP, "hipEventCreate failed");
+  }
+  const int shapes[3][2] = {{8, 8}, {16, 16}, {32, 8}};
+  nxs_tuning best{0, 0, 0, 0.0f};
+  nxs_status st = NXS_OK;
+  for (int sh = 0; sh < 3 && st == NXS_OK; ++sh) {
+    for (int sc = NXS_SCHED_TILES; sc <= NXS_SCHED_QUEUE && st == NXS_OK; ++sc) {
+      nxs_render_opts o = *opts;
+      o.tile_w = shapes[sh][0];
+      o.tile_h = shapes[sh][1];
+      o.schedule = sc;
+      o.keep_state = 0;
+      std::vector<float> ms;
+      for (int r = 0; r <= reps && st == NXS_OK; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) { st = NXS_EHIP; break; }
+        st = nxs_render_forward(ctx, g, cams, n_views, &o, out, stream);
+        if (st != NXS_OK) break;
+        float t_ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t_ms, e0, e1) != hipSuccess) {
+          st = fail(ctx, NXS_EHIP, "autotune timing failed");
+          break;
+        }
+        if (r > 0) ms.push_back(t_ms);   // the first render is a warm-up
+      }
+      if (st != NXS_OK) break;
+      std::sort(ms.begin(), ms.end());
+      const float med = ms[ms.size() / 2];
+      if (best.schedule == 0 || med < best.ms) best = {o.tile_w, o.tile_h, sc, med};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != NXS_OK) return st;
+  ctx->tuned[key] = best;
+  append_cache(cache_path, key, best);
+  *result = best;
+  return NXS_OK;
+}
+
+nxs_status nxs_set_workspace_limit(nxs_context* ctx, size_t bytes) {
+  if (!ctx) return NXS_EINVAL;
+  ctx->ws_limit = bytes;
+  return NXS_OK;
+}
+
+nxs_status nxs_release_workspace(nxs_context* ctx) {
+  if (!ctx) return NXS_EINVAL;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipDeviceSynchronize());
+  DevBuf* all[] = {&ctx->views,      &ctx->counters,      &ctx->partials,      &ctx->depth_key, &ctx->dsort_a, &ctx->dsort_b,
+                   &ctx->slot_a,     &ctx->slot_b,        &ctx->ntiles,    &ctx->rect,
+                   &ctx->prec,       &ctx->scan_local,
+                   &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
+                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->crec,      &ctx->ranges,
+                   &ctx->pstate,     &ctx->gslot,         &ctx->order,     &ctx->queue};
+  for (DevBuf* b : all) {
+    if (b->p) HIP_TRY(hipFree(b->p));
+    b->p = nullptr;
+    b->cap = 0;
+  }
+  ctx->ws_total = 0;
+  ctx->bwd_valid = false;
+  ctx->last_m = ctx->last_tiles = ctx->last_slots = 0;
+  ctx->last_inst_tile = ctx->last_inst_val = nullptr;
+  return NXS_OK;
+}
+
+nxs_status nxs_workspace_bytes(const nxs_context* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return NXS_EINVAL;
+  *bytes = ctx->ws_total;
+  return NXS_OK;
+}
+
 nxs_status nxs_set_timing(nxs_context* ctx, int32_t enable) {
   if (!ctx) return NXS_EINVAL;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -440,6 +622,7 @@ nxs_status nxs_inspect_instances(nxs_context* ctx, uint64_t* keys_host, int32_t*
     return NXS_EINVAL;
   if (capacity < ctx->last_m) return fail(ctx, NXS_EINVAL, "capacity below instance count");
   if (ctx->last_m == 0) return NXS_OK;
+  if (!ctx->last_inst_tile) return fail(ctx, NXS_EINVAL, "the last render did not complete");
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipEventSynchronize(ctx->done));
   std::vector<uint32_t> tile(ctx->last_m), val(ctx->last_m), dk(ctx->last_slots);

@@ -17,19 +17,31 @@
 //   after the first splat that leaves T < t_eps;
 //   L += E p, overdraw += 1 for every composited splat.
 // A wave leaves the tile when a ballot finds all its pixels stopped.
+//
+// Three schedules of the same per-block work, with bitwise-identical results:
+//   tile WGs     one work-group per tile, one wave per 8x8 block of it;
+//   block waves  one single-wave work-group per 8x8 block, so the dispatcher
+//                refills a wave slot as soon as any block finishes;
+//   persistent   a fixed grid of single-wave work-groups, each taking the next
+//                block from a global atomic queue over all views' tiles, in
+//                an order with the longest tile lists first (their blocks
+//                start early instead of forming the tail).
 #include "nxs_internal.h"
 #include "nxs_ops.h"
+
+#include <algorithm>
 
 namespace nxs {
 
 namespace {
 
+// One wave composites the 8x8 block `wid` of global tile `tile`.
 template <int MODEL, int TW, int TH, bool STATE>
-__global__ __launch_bounds__(TW* TH) void composite_kernel(
+__device__ __forceinline__ void composite_block(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const float4* __restrict__ crec, CompositeParams prm, float4* __restrict__ pstate) {
+    const float4* __restrict__ crec, const CompositeParams& prm, float4* __restrict__ pstate,
+    uint32_t tile, int wid, int lane) {
   static_assert(TW % 8 == 0 && TH % 8 == 0, "waves cover 8x8 blocks");
-  const uint32_t tile = blockIdx.x;
   int vi = 0;
   {
     int lo = 0, hi = n_views - 1;
@@ -42,8 +54,6 @@ __global__ __launch_bounds__(TW* TH) void composite_kernel(
   const ViewDev& v = views[vi];
   const int lt = (int)(tile - (uint32_t)v.tile_off);
   const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
   const int bx = (wid % (TW / 8)) * 8, by = (wid / (TW / 8)) * 8;   // wave's 8x8 block
   const int lx = bx + (lane & 7), ly = by + (lane >> 3);
   const int px = tx * TW + lx, py = ty * TH + ly;
@@ -141,39 +151,133 @@ __global__ __launch_bounds__(TW* TH) void composite_kernel(
   }
 }
 
+constexpr int kBlocksPerTile(int tw, int th) { return (tw / 8) * (th / 8); }
+
+template <int MODEL, int TW, int TH, bool STATE>
+__global__ __launch_bounds__(TW* TH) void composite_tiles_kernel(
+    const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
+    const float4* __restrict__ crec, CompositeParams prm, float4* __restrict__ pstate) {
+  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, crec, prm, pstate, blockIdx.x,
+                                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                                        threadIdx.x & 63);
+}
+
+template <int MODEL, int TW, int TH, bool STATE>
+__global__ __launch_bounds__(64) void composite_blocks_kernel(
+    const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
+    const float4* __restrict__ crec, CompositeParams prm, float4* __restrict__ pstate) {
+  constexpr int B = kBlocksPerTile(TW, TH);
+  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, crec, prm, pstate,
+                                        blockIdx.x / B, (int)(blockIdx.x % B), threadIdx.x);
+}
+
+// Work item k of the queue is block (k mod B) of tile order[k / B].
+template <int MODEL, int TW, int TH, bool STATE>
+__global__ __launch_bounds__(64) void composite_queue_kernel(
+    const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
+    const float4* __restrict__ crec, CompositeParams prm, float4* __restrict__ pstate,
+    const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* __restrict__ queue) {
+  constexpr int B = kBlocksPerTile(TW, TH);
+  const int lane = threadIdx.x;
+  for (;;) {
+    uint32_t k = 0;
+    if (lane == 0) k = atomicAdd(queue, 1u);
+    k = __builtin_amdgcn_readfirstlane(k);   // lane 0's ticket, wave-uniform
+    if (k >= n_items) break;        // every wave ends once the queue is drained
+    composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, crec, prm, pstate,
+                                          order[k / B], (int)(k % B), lane);
+  }
+}
+
+// Tiles in order of decreasing list length, bucketed by floor(log2(length)):
+// a single work-group counts the buckets in LDS, scans them (longest first) and
+// scatters the tile ids.  Order within a bucket is whatever the LDS atomics
+// give; it only changes which wave runs a block, not any result.
+constexpr int kOrderThreads = 1024;
+constexpr int kBuckets = 33;
+
+__global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(
+    const uint2* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ order,
+    uint32_t* __restrict__ queue) {
+  __shared__ uint32_t cnt[kBuckets];
+  __shared__ uint32_t pos[kBuckets];
+  const uint32_t t = threadIdx.x;
+  if (t < kBuckets) cnt[t] = 0;
+  if (t == 0) *queue = 0u;          // the queue of the composite that follows
+  __syncthreads();
+  for (uint32_t i = t; i < n_tiles; i += kOrderThreads) {
+    const uint2 r = ranges[i];
+    const uint32_t len = r.y - r.x;
+    const int b = len ? 32 - __clz(len) : 0;      // 0 for empty, else 1 + floor(log2)
+    atomicAdd(&cnt[b], 1u);
+  }
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    for (int b = kBuckets - 1; b >= 0; --b) {
+      pos[b] = run;
+      run += cnt[b];
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < n_tiles; i += kOrderThreads) {
+    const uint2 r = ranges[i];
+    const uint32_t len = r.y - r.x;
+    const int b = len ? 32 - __clz(len) : 0;
+    order[atomicAdd(&pos[b], 1u)] = i;
+  }
+}
+
+template <int MODEL, int TW, int TH, bool STATE>
+void launch_s(const CompositeLaunch& L, const CompositeParams& p, float4* pstate,
+              hipStream_t s) {
+  constexpr int B = kBlocksPerTile(TW, TH);
+  if (L.schedule == NXS_SCHED_TILES) {
+    hipLaunchKernelGGL((composite_tiles_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)L.n_tiles),
+                       dim3(TW * TH), 0, s, L.views, L.n_views, L.ranges, L.crec, p, pstate);
+  } else if (L.schedule == NXS_SCHED_BLOCKS) {
+    hipLaunchKernelGGL((composite_blocks_kernel<MODEL, TW, TH, STATE>),
+                       dim3((unsigned)(L.n_tiles * B)), dim3(64), 0, s, L.views, L.n_views,
+                       L.ranges, L.crec, p, pstate);
+  } else {
+    hipLaunchKernelGGL(order_tiles_kernel, dim3(1), dim3(kOrderThreads), 0, s, L.ranges,
+                       (uint32_t)L.n_tiles, L.order, L.queue);
+    const int64_t items = L.n_tiles * B;
+    const int64_t grid = std::min<int64_t>(items, (int64_t)L.n_cu * kQueueWavesPerCU);
+    hipLaunchKernelGGL((composite_queue_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)grid),
+                       dim3(64), 0, s, L.views, L.n_views, L.ranges, L.crec, p, pstate,
+                       L.order, (uint32_t)items, L.queue);
+  }
+}
+
 template <int MODEL, int TW, int TH>
-void launch_t(int64_t n_tiles, const ViewDev* views, int n_views, const uint2* ranges,
-              const float4* crec, const CompositeParams& p, float4* pstate, hipStream_t s) {
+void launch_t(const CompositeLaunch& L, const CompositeParams& p, float4* pstate,
+              hipStream_t s) {
   if (pstate)
-    hipLaunchKernelGGL((composite_kernel<MODEL, TW, TH, true>), dim3((unsigned)n_tiles),
-                       dim3(TW * TH), 0, s, views, n_views, ranges, crec, p, pstate);
+    launch_s<MODEL, TW, TH, true>(L, p, pstate, s);
   else
-    hipLaunchKernelGGL((composite_kernel<MODEL, TW, TH, false>), dim3((unsigned)n_tiles),
-                       dim3(TW * TH), 0, s, views, n_views, ranges, crec, p, pstate);
+    launch_s<MODEL, TW, TH, false>(L, p, pstate, s);
 }
 
 template <int MODEL>
-void launch_m(int tile_w, int tile_h, int64_t n_tiles, const ViewDev* views, int n_views,
-              const uint2* ranges, const float4* crec, const CompositeParams& p,
-              float4* pstate, hipStream_t s) {
-  if (tile_w == 8 && tile_h == 8)
-    launch_t<MODEL, 8, 8>(n_tiles, views, n_views, ranges, crec, p, pstate, s);
-  else if (tile_w == 32 && tile_h == 8)
-    launch_t<MODEL, 32, 8>(n_tiles, views, n_views, ranges, crec, p, pstate, s);
+void launch_m(const CompositeLaunch& L, const CompositeParams& p, float4* pstate,
+              hipStream_t s) {
+  if (L.tile_w == 8 && L.tile_h == 8)
+    launch_t<MODEL, 8, 8>(L, p, pstate, s);
+  else if (L.tile_w == 32 && L.tile_h == 8)
+    launch_t<MODEL, 32, 8>(L, p, pstate, s);
   else
-    launch_t<MODEL, 16, 16>(n_tiles, views, n_views, ranges, crec, p, pstate, s);
+    launch_t<MODEL, 16, 16>(L, p, pstate, s);
 }
 
 }  // namespace
 
-void launch_composite(int model, int tile_w, int tile_h, int64_t n_tiles,
-                      const ViewDev* views, int n_views, const uint2* ranges,
-                      const float4* crec, const CompositeParams& p, float4* pstate,
-                      hipStream_t s) {
-  if (n_tiles <= 0) return;
+void launch_composite(int model, const CompositeLaunch& L, const CompositeParams& p,
+                      float4* pstate, hipStream_t s) {
+  if (L.n_tiles <= 0) return;
   switch (model) {
 #define NXS_M(M) \
-  case M: launch_m<M>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, pstate, s); break;
+  case M: launch_m<M>(L, p, pstate, s); break;
     NXS_M(0) NXS_M(1) NXS_M(2) NXS_M(3) NXS_M(4) NXS_M(5) NXS_M(6) NXS_M(7)
 #undef NXS_M
     default: break;

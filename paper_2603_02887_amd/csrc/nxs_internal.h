@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "nxs.h"
+
 namespace nxs {
 
 // Per-view parameters, one entry per view in a device table.
@@ -105,10 +107,24 @@ struct CompositeParams {
 //   (L0, L1, L2, T_final), (E_k, tau_k), (U, 0) with E_k the saturating splat's
 //   emission (background if none), tau_k the optical depth before it and
 //   U = sum_{j<k} E_j alpha_j.
-void launch_composite(int model, int tile_w, int tile_h, int64_t n_tiles,
-                      const ViewDev* views, int n_views, const uint2* ranges,
-                      const float4* crec, const CompositeParams& p, float4* pstate,
-                      hipStream_t s);
+// Composite launch geometry.  schedule: NXS_SCHED_TILES, NXS_SCHED_BLOCKS or
+// NXS_SCHED_QUEUE (which also needs `order` [n_tiles] and the 4-byte `queue`
+// counter as scratch, and the CU count to size its grid).
+struct CompositeLaunch {
+  int schedule;
+  int tile_w, tile_h;
+  int64_t n_tiles;
+  const ViewDev* views;
+  int n_views;
+  const uint2* ranges;
+  const float4* crec;
+  uint32_t* order;
+  uint32_t* queue;
+  int n_cu;
+};
+constexpr int kQueueWavesPerCU = 32;
+void launch_composite(int model, const CompositeLaunch& L, const CompositeParams& p,
+                      float4* pstate, hipStream_t s);
 
 // Path-replay backward of the composite (models 0..4): per-slot gradients
 // gslot[9 * slot + f] for f = dLoss/d(opacity, u, v, conic A, B, C, r, g, b),

@@ -20,9 +20,17 @@ MODEL_IDS = {"exponential": 0, "linear": 1, "sublinear": 2, "superlinear": 3,
 STATUS = {0: "NXS_OK", -1: "NXS_EINVAL", -2: "NXS_ENOMEM", -3: "NXS_EHIP",
           -4: "NXS_ECAPACITY", -5: "NXS_EUNSUPPORTED"}
 SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_render_backward",
+           "nxs_autotune", "nxs_set_workspace_limit", "nxs_workspace_bytes",
+           "nxs_release_workspace",
+           "nxs_server_create", "nxs_server_destroy", "nxs_server_context",
+           "nxs_server_add_scene", "nxs_server_submit", "nxs_server_step",
+           "nxs_server_pending", "nxs_server_last_error",
            "nxs_last_error",
-           "nxs_set_timing", "nxs_inspect_stage_times", "nxs_inspect_counts", "nxs_inspect_instances", "nxs_inspect_ranges",
-           "nxs_inspect_projection"]
+           "nxs_set_timing", "nxs_inspect_stage_times", "nxs_inspect_counts",
+           "nxs_inspect_instances", "nxs_inspect_ranges", "nxs_inspect_projection"]
+# entry points that do not return an nxs_status
+_NOT_STATUS = {"nxs_last_error": ctypes.c_char_p, "nxs_server_last_error": ctypes.c_char_p,
+               "nxs_server_context": c_void_p, "nxs_server_pending": c_int32}
 
 
 class NxsError(RuntimeError):
@@ -46,7 +54,16 @@ class Camera(ctypes.Structure):
 class RenderOpts(ctypes.Structure):
     _fields_ = [("model", c_int32), ("background", c_float * 3), ("alpha_min", c_float),
                 ("t_eps", c_float), ("tile_w", c_int32), ("tile_h", c_int32),
-                ("lds_batch", c_int32), ("param", c_float), ("keep_state", c_int32)]
+                ("lds_batch", c_int32), ("param", c_float), ("keep_state", c_int32),
+                ("schedule", c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("schedule", c_int32),
+                ("ms", c_float)]
+
+
+SCHEDULES = {"tiles": 1, "blocks": 2, "queue": 3}
 
 
 class Image(ctypes.Structure):
@@ -75,6 +92,23 @@ def lib():
                                          POINTER(RenderOpts), POINTER(Image), c_void_p]
         L.nxs_render_backward.argtypes = [c_void_p, c_void_p, c_void_p,
                                           POINTER(GaussiansGrad), c_void_p]
+        L.nxs_autotune.argtypes = [c_void_p, POINTER(Gaussians), POINTER(Camera), c_int32,
+                                   POINTER(RenderOpts), POINTER(Image), ctypes.c_char_p,
+                                   c_int32, POINTER(Tuning), c_void_p]
+        L.nxs_set_workspace_limit.argtypes = [c_void_p, ctypes.c_size_t]
+        L.nxs_workspace_bytes.argtypes = [c_void_p, POINTER(ctypes.c_size_t)]
+        L.nxs_release_workspace.argtypes = [c_void_p]
+        L.nxs_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, c_int32,
+                                        POINTER(c_void_p)]
+        L.nxs_server_destroy.argtypes = [c_void_p]
+        L.nxs_server_context.argtypes = [c_void_p]
+        L.nxs_server_add_scene.argtypes = [c_void_p, POINTER(Gaussians), POINTER(c_int32)]
+        L.nxs_server_submit.argtypes = [c_void_p, c_int32, POINTER(Camera), POINTER(RenderOpts),
+                                        POINTER(Image), c_int64]
+        L.nxs_server_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                      POINTER(c_int32)]
+        L.nxs_server_pending.argtypes = [c_void_p]
+        L.nxs_server_last_error.argtypes = [c_void_p]
         L.nxs_last_error.argtypes = [c_void_p]
         L.nxs_last_error.restype = ctypes.c_char_p
         L.nxs_set_timing.argtypes = [c_void_p, c_int32]
@@ -84,7 +118,9 @@ def lib():
         L.nxs_inspect_ranges.argtypes = [c_void_p, c_void_p, c_int64]
         L.nxs_inspect_projection.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int64]
         for name in SYMBOLS:
-            if name not in ("nxs_last_error",):
+            if name in _NOT_STATUS:
+                getattr(L, name).restype = _NOT_STATUS[name]
+            else:
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -121,6 +157,64 @@ def make_camera(cam):
     return c
 
 
+def _make_gaussians(g):
+    n = int(g["means"].shape[0])
+    gs = Gaussians()
+    gs.n, gs.sh_degree = n, int(g["sh_degree"])
+    if n:
+        gs.means = _f32(g["means"], "means").data_ptr()
+        gs.scales = _f32(g["scales"], "scales").data_ptr()
+        gs.quats = _f32(g["quats"], "quats").data_ptr()
+        gs.opacities = _f32(g["opacities"], "opacities").data_ptr()
+        gs.sh = _f32(g["sh"], "sh").data_ptr()
+        K = (gs.sh_degree + 1) ** 2
+        if tuple(g["sh"].shape[1:]) != (K, 3) or tuple(g["means"].shape[1:]) != (3,):
+            raise ValueError("bad Gaussian array shapes")
+    return gs
+
+
+def _make_outputs(device, cams, outputs, overdraw):
+    if outputs is not None:
+        return outputs
+    outputs = []
+    for c in cams:
+        H, W = int(c.height), int(c.width)
+        outputs.append({
+            "rgb": torch.empty((H, W, 3), dtype=torch.float32, device=device),
+            "trans": torch.empty((H, W), dtype=torch.float32, device=device),
+            "overdraw": (torch.empty((H, W), dtype=torch.int32, device=device)
+                         if overdraw else None)})
+    return outputs
+
+
+def _make_image(o):
+    img = Image()
+    img.rgb = _f32(o["rgb"], "rgb").data_ptr()
+    img.trans = _f32(o["trans"], "trans").data_ptr()
+    od = o.get("overdraw")
+    img.overdraw = od.data_ptr() if od is not None else None
+    return img
+
+
+def _make_opts(model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0, t_eps=0.0, tile=(16, 16),
+               lds_batch=0, param=0.0, keep_state=False, schedule=0):
+    if isinstance(model, str):
+        model = MODEL_IDS[model]
+    if isinstance(schedule, str):
+        schedule = SCHEDULES[schedule]
+    opts = RenderOpts()
+    opts.model = int(model)
+    for k in range(3):
+        opts.background[k] = float(background[k])
+    opts.alpha_min, opts.t_eps = float(alpha_min), float(t_eps)
+    opts.tile_w, opts.tile_h = int(tile[0]), int(tile[1])
+    opts.lds_batch = int(lds_batch)
+    opts.param = float(param)
+    opts.keep_state = int(bool(keep_state))
+    opts.schedule = int(schedule)
+    return opts
+
+
 class Renderer:
     """A library context on one GPU; render() enqueues on the current stream."""
 
@@ -150,52 +244,26 @@ class Renderer:
             msg = self._L.nxs_last_error(self._ctx)
             raise NxsError(st, msg.decode() if msg else "")
 
+    def _marshal(self, g, cams, model, background, alpha_min, t_eps, tile, lds_batch,
+                 outputs, overdraw, param, keep_state, schedule):
+        gs = _make_gaussians(g)
+        V = len(cams)
+        carr = (Camera * V)(*[make_camera(c) for c in cams])
+        outputs = _make_outputs(self.device, cams, outputs, overdraw)
+        imgs = (Image * V)(*[_make_image(o) for o in outputs])
+        opts = _make_opts(model, background, alpha_min, t_eps, tile, lds_batch, param,
+                          keep_state, schedule)
+        return gs, carr, V, imgs, opts, outputs
+
     def render(self, g, cams, model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0,
                t_eps=0.0, tile=(16, 16), lds_batch=0, outputs=None, overdraw=True,
-               stream=None, param=0.0, keep_state=False):
+               stream=None, param=0.0, keep_state=False, schedule=0):
         """Render the Gaussians `g` (dict of GPU tensors, see scene_to_device) in
         every camera of `cams`.  Returns a list of dicts {rgb [H,W,3], trans [H,W],
         overdraw [H,W] int32} (or fills `outputs`, a list of such dicts)."""
-        if isinstance(model, str):
-            model = MODEL_IDS[model]
-        n = int(g["means"].shape[0])
-        gs = Gaussians()
-        gs.n, gs.sh_degree = n, int(g["sh_degree"])
-        if n:
-            gs.means = _f32(g["means"], "means").data_ptr()
-            gs.scales = _f32(g["scales"], "scales").data_ptr()
-            gs.quats = _f32(g["quats"], "quats").data_ptr()
-            gs.opacities = _f32(g["opacities"], "opacities").data_ptr()
-            gs.sh = _f32(g["sh"], "sh").data_ptr()
-            K = (gs.sh_degree + 1) ** 2
-            if tuple(g["sh"].shape[1:]) != (K, 3) or tuple(g["means"].shape[1:]) != (3,):
-                raise ValueError("bad Gaussian array shapes")
-        V = len(cams)
-        carr = (Camera * V)(*[make_camera(c) for c in cams])
-        if outputs is None:
-            outputs = []
-            for c in cams:
-                H, W = int(c.height), int(c.width)
-                outputs.append({
-                    "rgb": torch.empty((H, W, 3), dtype=torch.float32, device=self.device),
-                    "trans": torch.empty((H, W), dtype=torch.float32, device=self.device),
-                    "overdraw": (torch.empty((H, W), dtype=torch.int32, device=self.device)
-                                 if overdraw else None)})
-        imgs = (Image * V)()
-        for k, o in enumerate(outputs):
-            imgs[k].rgb = _f32(o["rgb"], "rgb").data_ptr()
-            imgs[k].trans = _f32(o["trans"], "trans").data_ptr()
-            od = o.get("overdraw")
-            imgs[k].overdraw = od.data_ptr() if od is not None else None
-        opts = RenderOpts()
-        opts.model = int(model)
-        for k in range(3):
-            opts.background[k] = float(background[k])
-        opts.alpha_min, opts.t_eps = float(alpha_min), float(t_eps)
-        opts.tile_w, opts.tile_h = int(tile[0]), int(tile[1])
-        opts.lds_batch = int(lds_batch)
-        opts.param = float(param)
-        opts.keep_state = int(bool(keep_state))
+        gs, carr, V, imgs, opts, outputs = self._marshal(
+            g, cams, model, background, alpha_min, t_eps, tile, lds_batch, outputs, overdraw,
+            param, keep_state, schedule)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         st = self._L.nxs_render_forward(self._ctx, byref(gs), carr, V, byref(opts), imgs,
@@ -204,6 +272,24 @@ class Renderer:
         self._last_shapes = [(int(c.height), int(c.width)) for c in cams]
         self._check(st)
         return outputs
+
+    def autotune(self, g, cams, model=0, cache_path=None, reps=5, outputs=None, stream=None,
+                 background=(0.0, 0.0, 0.0), alpha_min=0.0, t_eps=0.0, param=0.0):
+        """Measured best tile shape and composite schedule for this workload
+        (see nxs_autotune).  Returns {"tile": (w, h), "schedule": name, "ms": t}."""
+        gs, carr, V, imgs, opts, outputs = self._marshal(
+            g, cams, model, background, alpha_min, t_eps, (16, 16), 0, outputs, True, param,
+            False, 0)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        res = Tuning()
+        path = None if cache_path is None else str(cache_path).encode()
+        st = self._L.nxs_autotune(self._ctx, byref(gs), carr, V, byref(opts), imgs, path,
+                                  int(reps), byref(res), c_void_p(stream.cuda_stream))
+        self.generation += 1          # a sweep renders, which ends any kept state
+        self._check(st)
+        name = {v: k for k, v in SCHEDULES.items()}[res.schedule]
+        return {"tile": (res.tile_w, res.tile_h), "schedule": name, "ms": float(res.ms)}
 
     def backward(self, g, dL_drgb, dL_dtrans=None, stream=None):
         """Gradients of the Gaussians (dict of tensors shaped like `g`) from the
@@ -286,6 +372,81 @@ class Renderer:
         self._check(self._L.nxs_inspect_projection(self._ctx, int(view), d.ctypes.data,
                                                    r.ctypes.data, max(n, 1)))
         return d[:n], r[:4 * n].reshape(n, 4)
+
+
+class Server:
+    """Continuous-batching render server over resident scenes (nxs_server_*).
+
+    add_scene(g) keeps a scene's device arrays alive; submit() queues one view
+    and returns its output images (written once a step completes the
+    request); step() serves one batch and returns [(tag, status, outputs)]."""
+
+    def __init__(self, device=0, workspace_budget=0, max_batch_views=16):
+        self._L = lib()
+        self._s = c_void_p()
+        st = self._L.nxs_server_create(int(device), int(workspace_budget), int(max_batch_views),
+                                       byref(self._s))
+        if st != 0:
+            raise NxsError(st, "nxs_server_create failed")
+        self.device = torch.device("cuda", int(device))
+        self._scenes = []
+        self._inflight = {}
+        self._cap = 64
+        self._tags = (c_int64 * self._cap)()
+        self._status = (c_int32 * self._cap)()
+
+    def close(self):
+        if self._s:
+            self._L.nxs_server_destroy(self._s)
+            self._s = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            msg = self._L.nxs_server_last_error(self._s)
+            raise NxsError(st, msg.decode() if msg else "")
+
+    def add_scene(self, g):
+        sid = c_int32()
+        self._check(self._L.nxs_server_add_scene(self._s, byref(_make_gaussians(g)), byref(sid)))
+        self._scenes.append(g)
+        return sid.value
+
+    def submit(self, scene, cam, tag, outputs=None, overdraw=False, **opts):
+        tag = int(tag)
+        if tag in self._inflight:
+            raise ValueError(f"tag {tag} is already pending")
+        out = _make_outputs(self.device, [cam], None if outputs is None else [outputs],
+                            overdraw)[0]
+        img = _make_image(out)
+        self._check(self._L.nxs_server_submit(self._s, int(scene), byref(make_camera(cam)),
+                                              byref(_make_opts(**opts)), byref(img), tag))
+        self._inflight[tag] = out
+        return out
+
+    @property
+    def pending(self):
+        return int(self._L.nxs_server_pending(self._s))
+
+    def step(self, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        n = c_int32()
+        self._check(self._L.nxs_server_step(self._s, c_void_p(stream.cuda_stream), self._tags,
+                                            self._status, self._cap, byref(n)))
+        return [(int(self._tags[k]), int(self._status[k]), self._inflight.pop(int(self._tags[k])))
+                for k in range(n.value)]
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        ctx = self._L.nxs_server_context(self._s)
+        self._check(self._L.nxs_workspace_bytes(ctx, byref(b)))
+        return int(b.value)
 
 
 class RenderFunction(torch.autograd.Function):

@@ -120,7 +120,8 @@ typedef struct {
                              0 -> 1e-3 */
   float t_eps;            /* exponential (and Vicini's exponential part): stop
                              after the first splat that leaves T < t_eps;
-                             0 -> 1e-4, < 0 -> never */
+                             0 -> 1e-4, < 0 -> only once T falls below the
+                             smallest normal float32 (1.2e-38) */
   int32_t tile_w, tile_h; /* 8x8, 16x16 or 32x8; 0 -> 16x16 */
   int32_t lds_batch;      /* accepted for compatibility: 0, 128, 256, 512 (the
                              composite walks its tile in batches of 64 splats) */
@@ -185,7 +186,9 @@ typedef struct {
  *   dL_drgb   [n_views] host array of device [H,W,3] upstream gradients
  *   dL_dtrans [n_views] host array of device [H,W] gradients, or NULL (the
  *             array itself, or any entry, may be NULL for "zero")
- *   grads     device outputs, overwritten (sum over all views)
+ *   grads     device outputs, overwritten (sum over all views); per-Gaussian
+ *             sums are accumulated with float atomics, so repeated calls agree
+ *             to float32 rounding, not bitwise
  * Each tile's splats are re-walked front to back, rebuilding every pixel's
  * state from the start with the same float32 decisions as the forward;
  * nothing is stored per splat, only 12 floats per pixel.  The Gaussians and

@@ -404,7 +404,11 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   }
   CompositeParams cp;
   cp.log2_alpha_min = (float)std::log2((double)alpha_min);
-  cp.t_eps = (opts->model == NXS_EXPONENTIAL || opts->model == NXS_VICINI) ? t_eps : 0.0f;
+  // the exponential parts stop once T < cp.t_eps; "never" is the smallest
+  // normal float, below which the float32 product would underflow
+  cp.t_eps = (opts->model == NXS_EXPONENTIAL || opts->model == NXS_VICINI)
+                 ? (t_eps > 0.0f ? t_eps : 1.17549435e-38f)
+                 : 0.0f;
   cp.param = param;
   for (int k = 0; k < 3; ++k) cp.bg[k] = opts->background[k];
   cp.lds_batch = batch;

@@ -67,9 +67,9 @@ __device__ __forceinline__ void composite_block(
   const float param = prm.param;
   Op<MODEL> op;
 
+  if (!inside) op.stop();
   float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f;
   int od = 0;
-  bool done = !inside;
   // backward state (linear and quadratic): E_k, tau_k, U
   constexpr bool kSat = STATE && MODEL >= 1 && MODEL <= 4;
   float ek0 = prm.bg[0], ek1 = prm.bg[1], ek2 = prm.bg[2], tau_s = 0.0f;
@@ -77,62 +77,53 @@ __device__ __forceinline__ void composite_block(
 
   // Batches of 64 splats: lane j reads the block bits of splat (base + j)
   // (one coalesced load); a ballot gives the wave a bitmap of the splats whose
-  // footprint reaches its 8x8 block.  Those are visited in order, each one's
-  // fields read with scalar loads into SGPRs (no per-lane copies, no LDS).
+  // footprint reaches its 8x8 block.  Those are visited in order, one per
+  // iteration, each one's fields read with scalar loads into SGPRs (no
+  // per-lane copies, no LDS).  The per-pixel update is branch-free: a lane
+  // whose alpha is below alpha_min, or which has stopped, composites a = 0,
+  // which leaves every operator's state unchanged, so the loop carries no
+  // per-lane control flow and little scalar bookkeeping.
   const float* crf = reinterpret_cast<const float*>(crec);
-  bool all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
+  bool all_done = __builtin_amdgcn_ballot_w64(!op.stopped(t_eps)) == 0;
   for (uint32_t base = rg.x; base < rg.y && !all_done; base += 64) {
     const uint32_t j = base + (uint32_t)lane;
     const uint32_t bits = j < rg.y ? __float_as_uint(crf[12 * (size_t)j + 9]) : 0u;
     uint64_t rel = __builtin_amdgcn_ballot_w64((bits & wbit) != 0);
-    if (rel == 0) continue;
-    // up to four relevant splats per step: their scalar loads are all issued
-    // before the first is composited, so the load latency overlaps the work
-    do {
-      uint32_t kk[4];
-      int cnt = 0;
+    const float* bp = crf + 12 * (size_t)base;
+    while (rel != 0) {
+      const uint32_t b = (uint32_t)__builtin_ctzll(rel);
+      rel ^= 1ull << b;
+      const float* r = bp + 12 * b;
+      float c[9];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bool have = rel != 0;
-        kk[q] = have ? base + (uint32_t)__builtin_ctzll(rel) : kk[0];
-        rel = have ? rel & (rel - 1) : 0ull;
-        cnt += have ? 1 : 0;
+      for (int f = 0; f < 9; ++f) c[f] = r[f];
+      const float dx = fx - c[0], dy = fy - c[1];
+      const float e = fmaf(dx, fmaf(c[2], dx, c[3] * dy), fmaf(c[4] * dy, dy, c[5]));
+      const bool valid = (e >= amin) && !op.stopped(t_eps);
+      const float a = valid ? __builtin_amdgcn_exp2f(e) : 0.0f;
+      const float s_before = op.S;
+      const float p = op.step(a, param, t_eps);
+      if (kSat) {
+        // the saturating splat's emission, and the sums over the splats before it
+        const bool sat_now = op.S >= 1.0f && s_before < 1.0f;
+        ek0 = sat_now ? c[6] : ek0;
+        ek1 = sat_now ? c[7] : ek1;
+        ek2 = sat_now ? c[8] : ek2;
+        const float a_pre = op.S >= 1.0f ? 0.0f : a;
+        u0 = fmaf(c[6], a_pre, u0);
+        u1 = fmaf(c[7], a_pre, u1);
+        u2 = fmaf(c[8], a_pre, u2);
+        tau_s += a_pre;
       }
-      float cur[4][9];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int f = 0; f < 9; ++f) cur[q][f] = crf[12 * (size_t)kk[q] + f];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q < cnt && !done) {
-          const float dx = fx - cur[q][0], dy = fy - cur[q][1];
-          const float e =
-              fmaf(dx, fmaf(cur[q][2], dx, cur[q][3] * dy), fmaf(cur[q][4] * dy, dy, cur[q][5]));
-          if (e >= amin) {
-            const float a = __builtin_amdgcn_exp2f(e);
-            const float p = op.step(a, param, t_eps, done);
-            if (kSat) {
-              if (done) {
-                ek0 = cur[q][6];
-                ek1 = cur[q][7];
-                ek2 = cur[q][8];
-              } else {
-                u0 = fmaf(cur[q][6], a, u0);
-                u1 = fmaf(cur[q][7], a, u1);
-                u2 = fmaf(cur[q][8], a, u2);
-                tau_s += a;
-              }
-            }
-            L0 = fmaf(cur[q][6], p, L0);
-            L1 = fmaf(cur[q][7], p, L1);
-            L2 = fmaf(cur[q][8], p, L2);
-            ++od;
-          }
-        }
+      L0 = fmaf(c[6], p, L0);
+      L1 = fmaf(c[7], p, L1);
+      L2 = fmaf(c[8], p, L2);
+      od += valid ? 1 : 0;
+      if (__builtin_amdgcn_ballot_w64(!op.stopped(t_eps)) == 0) {
+        all_done = true;
+        break;
       }
-      all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
-    } while (rel != 0 && !all_done);
+    }
   }
   if (inside) {
     const float Tf = op.transmittance(param);

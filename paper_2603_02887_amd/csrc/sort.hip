@@ -417,17 +417,42 @@ __global__ __launch_bounds__(256) void ranges_gather_kernel(
   const uint32_t hx = __float_as_uint(r2.w);
   const float rx = __half2float(__ushort_as_half((unsigned short)(hx & 0xFFFFu)));
   const float ry = __half2float(__ushort_as_half((unsigned short)(hx >> 16)));
-  // which 8x8 pixel blocks of the tile (bit by * (tile_w / 8) + bx) the box
-  // reaches, judged at pixel centres; the composite's waves skip the others
+  // which 8x8 pixel blocks of the tile (bit by * (tile_w / 8) + bx) the
+  // footprint reaches, judged at pixel centres; the composite's waves skip the
+  // others.  A block passes the box test, then the exact one: the largest
+  // exponent e = lo + A' dx^2 + B' dx dy + C' dy^2 over the rectangle spanned
+  // by its pixel centres must reach log2(alpha_min) (with a margin of 2e-3 in
+  // log2 units, so float32 rounding here can only keep a block, never drop one
+  // that some pixel needs).
+  const float qa = -r1.x, qb = -r1.y, qc = -r1.z;    // Q = -(e - lo) >= 0
+  const float qlim = r1.w - log2_alpha_min + 2e-3f;  // e >= log2(alpha_min) <=> Q <= qlim
+  const float ia = 0.5f / qa, ic = 0.5f / qc;
   uint32_t mask = 0;
   const int nbx = tile_w >> 3, nby = tile_h >> 3;
   for (int by = 0; by < nby; ++by) {
     const float y0 = (float)(8 * by) + 0.5f, y1 = (float)(8 * by) + 7.5f;
     if (dv - ry > y1 || dv + ry < y0) continue;
+    const float ylo = y0 - dv, yhi = y1 - dv;          // dy range over the block
     for (int bx = 0; bx < nbx; ++bx) {
       const float x0 = (float)(8 * bx) + 0.5f, x1 = (float)(8 * bx) + 7.5f;
       if (du - rx > x1 || du + rx < x0) continue;
-      mask |= 1u << (by * nbx + bx);
+      const float xlo = x0 - du, xhi = x1 - du;        // dx range over the block
+      float qmin = 0.0f;
+      if (!(xlo <= 0.0f && xhi >= 0.0f && ylo <= 0.0f && yhi >= 0.0f)) {
+        // the centre is outside: the minimum lies on an edge of the rectangle
+        qmin = __builtin_inff();
+        const float xs[2] = {xlo, xhi}, ys[2] = {ylo, yhi};
+#pragma unroll
+        for (int e2 = 0; e2 < 2; ++e2) {
+          const float X = xs[e2];
+          const float y = fminf(fmaxf(-qb * X * ic, ylo), yhi);
+          qmin = fminf(qmin, X * (qa * X + qb * y) + qc * y * y);
+          const float Y = ys[e2];
+          const float x = fminf(fmaxf(-qb * Y * ia, xlo), xhi);
+          qmin = fminf(qmin, Y * (qc * Y + qb * x) + qa * x * x);
+        }
+      }
+      if (qmin <= qlim) mask |= 1u << (by * nbx + bx);
     }
   }
   crec[3 * j + 0] = make_float4(du, dv, r1.x, r1.y);

@@ -127,8 +127,11 @@ def test_autograd_function_matches_direct_backward(R):
     R.render(g, cams, model=3, keep_state=True)
     direct = R.backward(g, w, wt)
     torch.cuda.synchronize()
+    # per-Gaussian sums are accumulated with float atomics in whatever order
+    # the waves finish, so two runs agree to float32 rounding, not bitwise
     for k, leaf in leaves.items():
-        assert torch.allclose(leaf.grad, direct[k], rtol=1e-5, atol=1e-6), k
+        scale = float(direct[k].abs().max())
+        assert torch.allclose(leaf.grad, direct[k], rtol=1e-4, atol=1e-5 * scale), k
 
 
 def test_autograd_rejects_stale_state(R):

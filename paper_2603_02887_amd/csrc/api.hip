@@ -349,8 +349,10 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
                 (unsigned long long)M);
 
   // ---- instance buffers ---------------------------------------------------------
+  const int dbits = bit_length(ctx->host_counters->dmin ^ ctx->host_counters->dmax);
+  const int tbits = bit_length((uint64_t)(total_tiles - 1));
   const int64_t sort_n = std::max<int64_t>(S, (int64_t)M);
-  if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_size(sort_n))) ||
+  if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_words(sort_n))) ||
       (st = ensure(ctx, ctx->inst_tile, 4 * M)) || (st = ensure(ctx, ctx->inst_tile_alt, 4 * M)) ||
       (st = ensure(ctx, ctx->inst_val, 4 * M)) || (st = ensure(ctx, ctx->inst_val_alt, 4 * M)) ||
       (st = ensure(ctx, ctx->crec, 48 * M)) || (st = ensure(ctx, ctx->ranges, 8 * total_tiles)))
@@ -362,28 +364,21 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   launch_fill_u32(P<uint32_t>(ctx->ranges), 2 * total_tiles, 0u, s);
   if (M > 0) {
     // 1. depth sort of the slots on the bits that vary among visible ones
-    const uint32_t dmin = ctx->host_counters->dmin, dmax = ctx->host_counters->dmax;
-    const int dbits = bit_length(dmin ^ dmax);
-    uint32_t* ka = P<uint32_t>(ctx->dsort_a);
-    uint32_t* kb = P<uint32_t>(ctx->dsort_b);
-    uint32_t* slots = P<uint32_t>(ctx->slot_a);
-    uint32_t* slots_alt = P<uint32_t>(ctx->slot_b);
-    // values are the slots 0..S-1; the sort permutes a copy of the depth keys
-    launch_iota_copy(P<uint32_t>(ctx->depth_key), ka, slots, S, s);
-    int where = radix_sort_pairs(ka, slots, kb, slots_alt, S, dbits,
-                                 P<uint32_t>(ctx->counts), s);
-    uint32_t* sorted_slots = where ? slots_alt : slots;
+    //    (values: the slots 0..S-1)
+    const int wd = radix_sort(P<uint32_t>(ctx->depth_key), nullptr, P<uint32_t>(ctx->dsort_a),
+                              P<uint32_t>(ctx->slot_a), P<uint32_t>(ctx->dsort_b),
+                              P<uint32_t>(ctx->slot_b), S, dbits, P<uint32_t>(ctx->counts), s);
+    uint32_t* sorted_slots = wd ? P<uint32_t>(ctx->slot_b) : P<uint32_t>(ctx->slot_a);
     HIP_TRY(mark(3));
     // 2. emission in depth order
     launch_emit(sorted_slots, S, g->n, proj, dviews, P<uint32_t>(ctx->scan_local),
                 P<uint32_t>(ctx->block_sums), (uint32_t)M, inst_tile, inst_val, s);
     HIP_TRY(mark(4));
     // 3. stable sort by global tile
-    const int tbits = bit_length((uint64_t)(total_tiles - 1));
-    int w2 = radix_sort_pairs(inst_tile, inst_val, P<uint32_t>(ctx->inst_tile_alt),
-                              P<uint32_t>(ctx->inst_val_alt), (int64_t)M, tbits,
-                              P<uint32_t>(ctx->counts), s);
-    if (w2) {
+    const int wt = radix_sort(inst_tile, inst_val, P<uint32_t>(ctx->inst_tile_alt),
+                              P<uint32_t>(ctx->inst_val_alt), inst_tile, inst_val, (int64_t)M,
+                              tbits, P<uint32_t>(ctx->counts), s);
+    if (wt == 0) {
       inst_tile = P<uint32_t>(ctx->inst_tile_alt);
       inst_val = P<uint32_t>(ctx->inst_val_alt);
     }

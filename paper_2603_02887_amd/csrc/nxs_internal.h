@@ -64,11 +64,16 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
 
 // Stable LSD radix sort of (u32 key, u32 value) pairs on key bits [0, nbits).
 // Returns 0 if the result is in (keys, vals), 1 if in (keys_alt, vals_alt).
-// `counts` needs radix_counts_size(n) u32 entries.
-size_t radix_counts_size(int64_t n);
-int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
-                     uint32_t* vals_alt, int64_t n, int nbits, uint32_t* counts,
-                     hipStream_t s);
+// Stable LSD radix sort (reduce-then-scan, 8-bit digits): sorts (keys_in,
+// vals_in) by the low nbits of the keys (at least one pass), ping-ponging
+// through (k0, v0) and (k1, v1); returns which pair holds the result (0 or 1).
+// vals_in == nullptr: values are the input positions.  `counts` needs
+// radix_counts_words(n) u32.
+size_t radix_counts_words(int64_t n);
+int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
+               uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
+               hipStream_t s);
+
 
 // Exclusive scan of ntiles in sorted-slot order and emission of instances.
 size_t scan_blocks_size(int64_t n);
@@ -77,9 +82,8 @@ void launch_emit(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
                  uint32_t* block_sums, uint32_t total, uint32_t* inst_tile,
                  uint32_t* inst_val, hipStream_t s);
 
-// dst[i] = src[i], idx[i] = i.
-void launch_iota_copy(const uint32_t* src, uint32_t* dst, uint32_t* idx, int64_t n,
-                      hipStream_t s);
+
+
 
 // Tile ranges and gather of the composite records in sorted order.
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s);

@@ -1,0 +1,262 @@
+// Stable LSD radix sort of (u32 key, u32 value) pairs, reduce-then-scan.
+//
+// Digits of up to 8 bits (as few passes as that allows, widths balanced) over
+// chunks of 1,024 keys (small chunks: many work-groups, short per-group
+// latency, which is what bounds these passes at 1-3 million keys).  Each pass
+// is three kernels:
+//   count    per chunk and digit                counts[d * nchunks + c]
+//            (one LDS add per distinct digit per wave round: lanes with equal
+//            digits are matched by ballots first)
+//   scan     per digit over chunks (one work-group per digit) -> exclusive
+//            offsets in place, digit totals
+//   scatter  per chunk: stable local ranks via wave ballots, a reorder by
+//            digit in LDS, then the digit runs written out.
+// Work-groups are dealt to the 8 XCDs round-robin; chunk c goes to the
+// work-group that puts a contiguous range of chunks on each XCD.  A digit's
+// runs from consecutive chunks are adjacent in the output, so the partial
+// cache lines at their seams are merged in one XCD's L2 instead of reaching
+// HBM as several partial writes.  No kernel waits on another work-group.
+#include "nxs_internal.h"
+
+#include <algorithm>
+
+namespace nxs {
+
+namespace {
+
+constexpr int kRThreads = 256;
+constexpr int kRWaves = kRThreads / 64;
+constexpr int kRItems = 4;
+constexpr int kRChunk = kRThreads * kRItems;   // 1,024 keys
+constexpr int kRPerWave = kRChunk / kRWaves;   // 256 keys, 4 rounds of 64
+constexpr int kRBins = 256;                    // digits of up to 8 bits
+constexpr uint32_t kRXcds = 8;
+
+__device__ __forceinline__ uint32_t chunk_of(uint32_t b, uint32_t per) {
+  return (b % kRXcds) * per + b / kRXcds;
+}
+
+// lanes of the wave whose digit equals this lane's (valid lanes only)
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, int width, bool valid) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < width; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+__global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* __restrict__ keys,
+                                                      int64_t n, int shift, int width,
+                                                      uint32_t nchunks, uint32_t per,
+                                                      uint32_t* __restrict__ counts) {
+  __shared__ uint32_t h[kRBins];
+  const uint32_t c = chunk_of(blockIdx.x, per);
+  if (c >= nchunks) return;                    // the whole work-group
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  h[t] = 0;
+  __syncthreads();
+  const uint32_t mask = (1u << width) - 1u;
+  const int64_t base = (int64_t)c * kRChunk;
+  const int chunk_n = (int)min((int64_t)kRChunk, n - base);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t k[kRItems];
+#pragma unroll
+  for (int r = 0; r < kRItems; ++r) {
+    const int li = wid * kRPerWave + r * 64 + lane;
+    k[r] = li < chunk_n ? keys[base + li] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kRItems; ++r) {
+    const int li = wid * kRPerWave + r * 64 + lane;
+    const bool valid = li < chunk_n;
+    const uint32_t d = (k[r] >> shift) & mask;
+    const uint64_t peers = digit_peers(d, width, valid);
+    if (valid && (peers & lt_mask) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+  }
+  __syncthreads();
+  if (t <= (int)mask) counts[(int64_t)t * nchunks + c] = h[t];
+}
+
+__device__ __forceinline__ uint32_t rx_block_scan(uint32_t x, uint32_t* s_tmp, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_tmp[wid] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kRWaves; ++w) {
+    const uint32_t v = s_tmp[w];
+    if (w < wid) off += v;
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - x;
+}
+
+// One work-group per digit: exclusive scan of counts[d][0..nchunks) in place.
+__global__ __launch_bounds__(kRThreads) void rx_scan(uint32_t* __restrict__ counts,
+                                                     uint32_t nchunks,
+                                                     uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_tmp[kRWaves];
+  uint32_t* row = counts + (int64_t)blockIdx.x * nchunks;
+  uint32_t running = 0;
+  for (uint32_t b = 0; b < nchunks; b += kRThreads * 4) {
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t i = b + threadIdx.x * 4 + q;
+      v[q] = i < nchunks ? row[i] : 0u;
+      sum += v[q];
+    }
+    uint32_t tot;
+    uint32_t ex = rx_block_scan(sum, s_tmp, &tot) + running;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t i = b + threadIdx.x * 4 + q;
+      if (i < nchunks) row[i] = ex;
+      ex += v[q];
+    }
+    running += tot;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = running;
+}
+
+// vals_in == nullptr: the values are the input positions.
+__global__ __launch_bounds__(kRThreads) void rx_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n, int shift,
+    int width, uint32_t nchunks, uint32_t per, const uint32_t* __restrict__ counts,
+    const uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_key[kRChunk];
+  __shared__ uint32_t s_val[kRChunk];
+  __shared__ uint32_t s_wave[kRWaves][kRBins];
+  __shared__ uint32_t s_gbase[kRBins];
+  __shared__ uint32_t s_lbase[kRBins];
+  __shared__ uint32_t s_tmp[kRWaves];
+
+  const uint32_t c = chunk_of(blockIdx.x, per);
+  if (c >= nchunks) return;                    // the whole work-group
+  const int t = threadIdx.x;
+  const int lane = t & 63, wid = t >> 6;
+  for (int w = 0; w < kRWaves; ++w) s_wave[w][t] = 0;
+  const uint32_t mask = (1u << width) - 1u;
+  const int nd = 1 << width;
+  const int64_t base = (int64_t)c * kRChunk;
+  const int chunk_n = (int)min((int64_t)kRChunk, n - base);
+
+  uint32_t k_reg[kRItems], v_reg[kRItems];
+#pragma unroll
+  for (int r = 0; r < kRItems; ++r) {
+    const int li = wid * kRPerWave + r * 64 + lane;
+    k_reg[r] = 0u;
+    v_reg[r] = 0u;
+    if (li < chunk_n) {
+      k_reg[r] = keys_in[base + li];
+      v_reg[r] = vals_in ? vals_in[base + li] : (uint32_t)(base + li);
+    }
+  }
+  // global start of this chunk's run of digit t: keys of smaller digits plus
+  // keys of digit t in earlier chunks
+  {
+    const uint32_t tot = t < nd ? totals[t] : 0u;
+    const uint32_t off = t < nd ? counts[(int64_t)t * nchunks + c] : 0u;
+    uint32_t all;
+    const uint32_t ex = rx_block_scan(tot, s_tmp, &all);
+    s_gbase[t] = ex + off;
+  }
+  __syncthreads();
+  // per-wave ranks: keys of the same digit earlier in this wave's part
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t rank[kRItems], dig[kRItems];
+#pragma unroll
+  for (int r = 0; r < kRItems; ++r) {
+    const int li = wid * kRPerWave + r * 64 + lane;
+    const bool valid = li < chunk_n;
+    const uint32_t d = valid ? (k_reg[r] >> shift) & mask : 0u;
+    const uint64_t peers = digit_peers(d, width, valid);
+    dig[r] = d;
+    rank[r] = 0;
+    if (valid) {
+      const uint32_t before = s_wave[wid][d];   // the same for every peer
+      const uint32_t pos = (uint32_t)__popcll(peers & lt_mask);
+      rank[r] = before + pos;
+      if (pos == 0) s_wave[wid][d] = before + (uint32_t)__popcll(peers);
+    }
+  }
+  __syncthreads();
+  // local start of each digit's run in the chunk
+  {
+    uint32_t cnt = 0;
+    for (int w = 0; w < kRWaves; ++w) cnt += s_wave[w][t];
+    uint32_t all;
+    s_lbase[t] = rx_block_scan(t < nd ? cnt : 0u, s_tmp, &all);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRItems; ++r) {
+    const int li = wid * kRPerWave + r * 64 + lane;
+    if (li < chunk_n) {
+      const uint32_t d = dig[r];
+      uint32_t off = s_lbase[d] + rank[r];
+      for (int w = 0; w < wid; ++w) off += s_wave[w][d];
+      s_key[off] = k_reg[r];
+      s_val[off] = v_reg[r];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < chunk_n; i += kRThreads) {
+    const uint32_t k = s_key[i];
+    const uint32_t d = (k >> shift) & mask;
+    const uint32_t g = s_gbase[d] + (uint32_t)i - s_lbase[d];
+    keys_out[g] = k;
+    vals_out[g] = s_val[i];
+  }
+}
+
+}  // namespace
+
+size_t radix_counts_words(int64_t n) {
+  const int64_t nchunks = std::max<int64_t>((n + kRChunk - 1) / kRChunk, 1);
+  return (size_t)nchunks * kRBins + kRBins;
+}
+
+int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
+               uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
+               hipStream_t s) {
+  if (n <= 0) return 0;
+  nbits = std::max(nbits, 1);
+  const uint32_t nchunks = (uint32_t)((n + kRChunk - 1) / kRChunk);
+  const uint32_t per = (nchunks + kRXcds - 1) / kRXcds;
+  const unsigned grid = per * kRXcds;
+  uint32_t* totals = counts + (size_t)nchunks * kRBins;
+  const int passes = (nbits + 7) / 8;
+  const uint32_t* kin = keys_in;
+  const uint32_t* vin = vals_in;
+  int cur = -1, shift = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int width = (nbits - shift + (passes - p) - 1) / (passes - p);
+    uint32_t* kout = (cur == 0) ? k1 : k0;
+    uint32_t* vout = (cur == 0) ? v1 : v0;
+    hipLaunchKernelGGL(rx_count, dim3(grid), dim3(kRThreads), 0, s, kin, n, shift, width,
+                       nchunks, per, counts);
+    hipLaunchKernelGGL(rx_scan, dim3(1u << width), dim3(kRThreads), 0, s, counts, nchunks,
+                       totals);
+    hipLaunchKernelGGL(rx_scatter, dim3(grid), dim3(kRThreads), 0, s, kin, vin, kout, vout, n,
+                       shift, width, nchunks, per, counts, totals);
+    kin = kout;
+    vin = vout;
+    cur = (cur == 0) ? 1 : 0;
+    shift += width;
+  }
+  return cur;
+}
+
+}  // namespace nxs

@@ -1,6 +1,6 @@
-// Sorting and binning: stable LSD radix sort of (u32 key, u32 value) pairs,
-// the scan + emission of tile instances, tile ranges and the gather of the
-// composite records into sorted order.
+// Binning: the scan + emission of tile instances, tile ranges and the gather
+// of the composite records into sorted order (the radix sort itself is in
+// radix.hip).
 //
 // Front-to-back order inside each tile (Sec. 3: splats sorted by depth) is
 // obtained in two sorts instead of one wide one:
@@ -11,14 +11,6 @@
 // single sort on the 64-bit key (tile << 32 | depth bits) with ties by index,
 // while moving 32-bit keys over fewer bits.
 //
-// Radix sort: reduce-then-scan with digits of up to 9 bits (as few passes as
-// that allows, widths balanced) and 2048 keys per work-group chunk.
-//   count   per chunk and digit            counts[d * nchunks + c]
-//   scan    per digit over chunks (one WG per digit) -> exclusive offsets,
-//           digit totals
-//   scatter per chunk: digit bases from the totals, stable local ranks via
-//           wave ballots, a local reorder in LDS, then coalesced stores.
-// No kernel waits on another work-group, so no launch can deadlock.
 #include <hip/hip_fp16.h>
 
 #include "nxs_internal.h"
@@ -27,42 +19,7 @@ namespace nxs {
 
 namespace {
 
-constexpr int kSortBlock = 256;
 constexpr uint32_t kXcds = 8;   // accelerator complex dies of an MI355X
-constexpr int kItems = 8;
-constexpr int kChunk = kSortBlock * kItems;  // 2048 keys per work-group
-constexpr int kRadixBits = 9;                // digits of up to 9 bits
-constexpr int kRadix = 1 << kRadixBits;
-constexpr int kPer = kRadix / kSortBlock;    // digits per thread in digit-wide loops
-
-__device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift, uint32_t mask) {
-  return (k >> shift) & mask;
-}
-
-__global__ __launch_bounds__(kSortBlock) void rs_count(const uint32_t* __restrict__ keys,
-                                                       int64_t n, int shift, uint32_t mask,
-                                                       int nchunks,
-                                                       uint32_t* __restrict__ counts) {
-  __shared__ uint32_t hist[kRadix];
-  const uint32_t nd = mask + 1;
-  for (uint32_t d = threadIdx.x; d < nd; d += kSortBlock) hist[d] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kChunk;
-  uint32_t k[kItems];
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int64_t idx = base + r * kSortBlock + threadIdx.x;
-    k[r] = idx < n ? keys[idx] : 0xFFFFFFFFu;
-  }
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int64_t idx = base + r * kSortBlock + threadIdx.x;
-    if (idx < n) atomicAdd(&hist[digit_of(k[r], shift, mask)], 1u);
-  }
-  __syncthreads();
-  for (uint32_t d = threadIdx.x; d < nd; d += kSortBlock)
-    counts[(int64_t)d * nchunks + blockIdx.x] = hist[d];
-}
 
 // Block-wide exclusive scan of one value per thread (256 threads).
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s_tmp,
@@ -78,7 +35,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
   __syncthreads();
   uint32_t wave_off = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < kSortBlock / 64; ++w) {
+  for (int w = 0; w < 4; ++w) {
     uint32_t v = s_tmp[w];
     if (w < wid) wave_off += v;
     tot += v;
@@ -86,154 +43,6 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
   __syncthreads();
   *total = tot;
   return wave_off + incl - x;
-}
-
-// One WG per digit: exclusive scan of counts[d][0..nchunks) in place.
-__global__ __launch_bounds__(kSortBlock) void rs_scan_digit(uint32_t* __restrict__ counts,
-                                                            int nchunks,
-                                                            uint32_t* __restrict__ totals) {
-  __shared__ uint32_t s_tmp[kSortBlock / 64];
-  uint32_t* row = counts + (int64_t)blockIdx.x * nchunks;
-  uint32_t running = 0;
-  for (int b = 0; b < nchunks; b += kSortBlock * 4) {
-    uint32_t v[4];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      int idx = b + threadIdx.x * 4 + k;
-      v[k] = idx < nchunks ? row[idx] : 0u;
-      sum += v[k];
-    }
-    uint32_t tot;
-    uint32_t ex = block_exclusive_scan(sum, s_tmp, &tot) + running;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      int idx = b + threadIdx.x * 4 + k;
-      if (idx < nchunks) row[idx] = ex;
-      ex += v[k];
-    }
-    running += tot;
-  }
-  if (threadIdx.x == 0) totals[blockIdx.x] = running;
-}
-
-// Stable scatter of one 2048-key chunk.  Each wave ranks its own contiguous
-// quarter of the chunk (8 rounds of 64 keys) by matching digits with one
-// ballot per digit bit, keeping its running digit counts in its own LDS row,
-// so the rounds need no barriers.  The waves' counts then give every key its
-// place in the chunk; the chunk is reordered by digit in LDS and written out
-// in runs (coalesced).
-__global__ __launch_bounds__(kSortBlock) void rs_scatter(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n,
-    int shift, int width, int nchunks, const uint32_t* __restrict__ counts,
-    const uint32_t* __restrict__ totals) {
-  constexpr int kWaves = kSortBlock / 64;
-  constexpr int kPerWave = kChunk / kWaves;   // 512 keys, 8 rounds of 64
-  __shared__ uint32_t s_key[kChunk];
-  __shared__ uint32_t s_val[kChunk];
-  __shared__ uint32_t s_gbase[kRadix];   // global position of this chunk's digit run
-  __shared__ uint32_t s_lbase[kRadix];   // local (in-chunk) start of the digit run
-  __shared__ uint32_t s_wave[kWaves][kRadix];
-  __shared__ uint32_t s_tmp[kWaves];
-
-  const int t = threadIdx.x;
-  const int c = blockIdx.x;
-  const int lane = t & 63, wid = t >> 6;
-  const uint32_t mask = (1u << width) - 1u;
-  const int nd = 1 << width;
-  const int64_t base = (int64_t)c * kChunk;
-  const int chunk_n = (int)min((int64_t)kChunk, n - base);
-
-  uint32_t k_reg[kItems], v_reg[kItems];
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int li = wid * kPerWave + r * 64 + lane;
-    if (li < chunk_n) {
-      k_reg[r] = keys_in[base + li];
-      v_reg[r] = vals_in[base + li];
-    }
-  }
-  // digit bases: exclusive scans over digits (kPer consecutive digits per thread)
-  {
-    uint32_t tot_d[kPer], loc_d[kPer], off_d[kPer];
-    uint32_t st = 0, sl = 0;
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int d = t * kPer + q;
-      if (d < nd) {
-        tot_d[q] = totals[d];
-        off_d[q] = counts[(int64_t)d * nchunks + c];
-        const uint32_t next =
-            (c + 1 < nchunks) ? counts[(int64_t)d * nchunks + c + 1] : tot_d[q];
-        loc_d[q] = next - off_d[q];
-      } else {
-        tot_d[q] = loc_d[q] = off_d[q] = 0;
-      }
-      st += tot_d[q];
-      sl += loc_d[q];
-    }
-    uint32_t dummy;
-    uint32_t ex_t = block_exclusive_scan(st, s_tmp, &dummy);
-    uint32_t ex_l = block_exclusive_scan(sl, s_tmp, &dummy);
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int d = t * kPer + q;
-      s_gbase[d] = ex_t + off_d[q];
-      s_lbase[d] = ex_l;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) s_wave[w][d] = 0;
-      ex_t += tot_d[q];
-      ex_l += loc_d[q];
-    }
-  }
-  __syncthreads();
-
-  // per-wave ranking: rank[r] = keys of the same digit earlier in this wave's quarter
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t rank[kItems], dig[kItems];
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int li = wid * kPerWave + r * 64 + lane;
-    const bool valid = li < chunk_n;
-    const uint32_t d = valid ? digit_of(k_reg[r], shift, mask) : 0u;
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < width; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    dig[r] = d;
-    rank[r] = 0;
-    if (valid) {
-      const uint32_t before = s_wave[wid][d];   // same value for every peer
-      const uint32_t pos = (uint32_t)__popcll(peers & lt_mask);
-      rank[r] = before + pos;
-      if (pos == 0) s_wave[wid][d] = before + (uint32_t)__popcll(peers);
-    }
-  }
-  __syncthreads();
-  // place every key: digit start in the chunk + keys of that digit in earlier waves
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const int li = wid * kPerWave + r * 64 + lane;
-    if (li < chunk_n) {
-      const uint32_t d = dig[r];
-      uint32_t off = s_lbase[d] + rank[r];
-      for (int w = 0; w < wid; ++w) off += s_wave[w][d];
-      s_key[off] = k_reg[r];
-      s_val[off] = v_reg[r];
-    }
-  }
-  __syncthreads();
-  // coalesced write-out of the locally sorted chunk
-  for (int i = t; i < chunk_n; i += kSortBlock) {
-    const uint32_t k = s_key[i];
-    const uint32_t d = digit_of(k, shift, mask);
-    const uint32_t g = s_gbase[d] + (uint32_t)i - s_lbase[d];
-    keys_out[g] = k;
-    vals_out[g] = s_val[i];
-  }
 }
 
 // ---------------------------------------------------------------- scan + emit
@@ -365,14 +174,6 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
 
 // ----------------------------------------------------- ranges + gather
 
-__global__ void iota_copy_kernel(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
-                                 uint32_t* __restrict__ idx, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    dst[i] = src[i];
-    idx[i] = (uint32_t)i;
-  }
-}
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -462,39 +263,6 @@ __global__ __launch_bounds__(256) void ranges_gather_kernel(
 
 }  // namespace
 
-size_t radix_counts_size(int64_t n) {
-  const int64_t nchunks = (n + kChunk - 1) / kChunk;
-  return (size_t)(nchunks > 0 ? nchunks : 1) * kRadix + kRadix;
-}
-
-int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
-                     uint32_t* vals_alt, int64_t n, int nbits, uint32_t* counts,
-                     hipStream_t s) {
-  if (n <= 1 || nbits <= 0) return 0;
-  const int nchunks = (int)((n + kChunk - 1) / kChunk);
-  uint32_t* totals = counts + (int64_t)nchunks * kRadix;
-  // as few passes as digits of <= kRadixBits allow, widths as even as possible
-  const int passes = (nbits + kRadixBits - 1) / kRadixBits;
-  int cur = 0, shift = 0;
-  for (int p = 0; p < passes; ++p) {
-    const int width = (nbits - shift + (passes - p) - 1) / (passes - p);
-    const uint32_t mask = (1u << width) - 1u;
-    uint32_t* kin = cur ? keys_alt : keys;
-    uint32_t* vin = cur ? vals_alt : vals;
-    uint32_t* kout = cur ? keys : keys_alt;
-    uint32_t* vout = cur ? vals : vals_alt;
-    hipLaunchKernelGGL(rs_count, dim3(nchunks), dim3(kSortBlock), 0, s, kin, n, shift,
-                       mask, nchunks, counts);
-    hipLaunchKernelGGL(rs_scan_digit, dim3(1u << width), dim3(kSortBlock), 0, s, counts,
-                       nchunks, totals);
-    hipLaunchKernelGGL(rs_scatter, dim3(nchunks), dim3(kSortBlock), 0, s, kin, vin, kout,
-                       vout, n, shift, width, nchunks, counts, totals);
-    cur ^= 1;
-    shift += width;
-  }
-  return cur;
-}
-
 size_t scan_blocks_size(int64_t n) {
   return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1;
 }
@@ -515,12 +283,6 @@ void launch_emit(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
                      total, inst_tile, inst_val);
 }
 
-void launch_iota_copy(const uint32_t* src, uint32_t* dst, uint32_t* idx, int64_t n,
-                      hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(iota_copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                     src, dst, idx, n);
-}
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {
   if (n <= 0) return;

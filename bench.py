@@ -44,9 +44,9 @@ HBM_PEAK_GBS = 8000.0
 # size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
 # kernel sources with this digest and are reported as null once those change.
 TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_internal.h")
-TRAFFIC = {"digest": "31588bf2bd7b58bd82d2cd0697051e9e4ceb9348f561bc36f1012245ce5ad962",
+TRAFFIC = {"digest": "84decaceaa050874cd0f4e93e4cd2450590702167d63a62f123f9f17118425cf",
            "tile": "16x16",
-           "bytes": {0: 160910303, 1: 96811032, 2: 107176219, 3: 93414705}}
+           "bytes": {0: 158396922, 1: 96983881, 2: 106946674, 3: 93593283}}
 
 
 def measured_traffic(model, tile):
@@ -245,6 +245,57 @@ def serving(args, torch, nxs, synth):
     print(json.dumps(line), flush=True)
 
 
+def differentiation(R, torch, nxs, synth, steps, models=(0, 1, 2, 3)):
+    """Differentiation workload: 500k Gaussians (uniform-cube generator), 8
+    views on a radius-6 orbit at 1280x720, per-pixel L1 loss against a render
+    of the same scene with means jittered by N(0, 0.01) and opacity logits by
+    N(0, 0.1).  One step = forward keeping state + path-replay backward for
+    means, scales, rotations, opacities and SH, all 8 views, timed with
+    events on the render stream."""
+    scene, cams = synth.diff_scene()
+    rng = np.random.default_rng(33)
+    tgt = synth.Scene(scene.means + rng.normal(0, 0.01, scene.means.shape).astype(np.float32),
+                      scene.scales, scene.quats,
+                      (1.0 / (1.0 + np.exp(-(np.log(scene.opacities / (1 - scene.opacities))
+                                             + rng.normal(0, 0.1, scene.n))))).astype(np.float32),
+                      scene.sh, scene.sh_degree)
+    g, gt = nxs.scene_to_device(scene), nxs.scene_to_device(tgt)
+    pix = sum(c.width * c.height for c in cams)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    res = {}
+    for m in models:
+        target = R.render(gt, cams, model=m, overdraw=False)
+        outs = [{"rgb": torch.empty_like(t["rgb"]), "trans": torch.empty_like(t["trans"]),
+                 "overdraw": None} for t in target]
+
+        def step():
+            R.render(g, cams, model=m, keep_state=True, outputs=outs)
+            ev[1].record()
+            d_rgb = [torch.sign(o["rgb"] - t["rgb"]) / (3.0 * pix) for o, t in zip(outs, target)]
+            return R.backward(g, d_rgb)
+
+        step()
+        torch.cuda.synchronize()
+        fwd, tot = [], []
+        for _ in range(steps):
+            ev[0].record()
+            gr = step()
+            ev[2].record()
+            torch.cuda.synchronize()
+            fwd.append(ev[0].elapsed_time(ev[1]))
+            tot.append(ev[0].elapsed_time(ev[2]))
+        loss = sum(float((o["rgb"] - t["rgb"]).abs().sum()) for o, t in zip(outs, target)) / (3 * pix)
+        res[MODELS[m]] = {"forward_ms": float(np.median(fwd)),
+                          "forward_backward_ms": float(np.median(tot)),
+                          "backward_ms": float(np.median(tot) - np.median(fwd)),
+                          "mpix_per_s_fwd_bwd": pix / float(np.median(tot)) / 1e3,
+                          "l1_loss": loss,
+                          "grad_norm_means": float(gr["means"].norm())}
+    return {"workload": ("500,000 Gaussians (uniform cube), SH degree 0, 8 views on a radius-6 "
+                         "orbit at 1280x720, L1 loss against a jittered-scene render"),
+            "pixels": pix, "views": len(cams), "per_model": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[1])
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +308,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 16-view batched workload")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--no-diff", action="store_true",
+                    help="skip the 8-view forward + backward workload")
+    ap.add_argument("--diff-steps", type=int, default=5)
     ap.add_argument("--workload", choices=("scene", "serving"), default="scene",
                     help="scene: the 1M-Gaussian 1080p forward (default); serving: the "
                          "continuous-batching server under Poisson load")
@@ -373,6 +427,10 @@ def main():
     if not args.no_batched:
         batched = batched_views(R, torch, nxs, synth, args.batched_steps)
 
+    diff = None
+    if not args.no_diff:
+        diff = differentiation(R, torch, nxs, synth, args.diff_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, cam, args.cpu_pixels)
@@ -392,6 +450,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "differentiation": diff,
     }
     R.close()
     print(json.dumps(line), flush=True)

@@ -163,7 +163,8 @@ def serving(args, torch, nxs, synth):
     result ready.  Prints one JSON line."""
     rng = np.random.default_rng(50)
     scenes = synth.serving_scenes()
-    S = nxs.Server(0, workspace_budget=args.serve_budget_gib << 30, max_batch_views=16)
+    S = nxs.Server(0, workspace_budget=args.serve_budget_gib << 30, max_batch_views=16,
+                   n_slots=args.serve_slots)
     ids = [S.add_scene(nxs.scene_to_device(sc)) for sc in scenes]
     pool = {wh: [] for wh in SERVE_SIZES}
 
@@ -190,23 +191,26 @@ def serving(args, torch, nxs, synth):
         t0 = time.perf_counter()
         n, nxt, lat, pix = len(reqs), 0, [0.0] * len(reqs), 0
         cams = {}
-        while nxt < n or S.pending:
+        while nxt < n or S.pending or S.in_flight:
             now = time.perf_counter() - t0
             while nxt < n and arrivals[nxt] <= now:
                 sc, cam, m = reqs[nxt]
                 S.submit(ids[sc], cam, nxt, outputs=out_for(cam), model=m)
                 cams[nxt] = cam
                 nxt += 1
-            if S.pending:
-                for tag, st, out in S.step():
-                    if st != 0:
-                        raise RuntimeError(f"request {tag} failed with status {st}")
-                    lat[tag] = time.perf_counter() - t0 - arrivals[tag]
-                    cam = cams.pop(tag)
-                    pix += cam.width * cam.height
-                    pool[(cam.width, cam.height)].append(out)
-            elif nxt < n:
-                time.sleep(max(0.0, min(arrivals[nxt] - now, 0.002)))
+            # block only when every slot is busy and requests wait for one;
+            # otherwise poll, so that new arrivals are admitted promptly
+            res = S.step(wait=S.pending > 0)
+            t_done = time.perf_counter() - t0
+            for tag, st, out in res:
+                if st != 0:
+                    raise RuntimeError(f"request {tag} failed with status {st}")
+                lat[tag] = t_done - arrivals[tag]
+                cam = cams.pop(tag)
+                pix += cam.width * cam.height
+                pool[(cam.width, cam.height)].append(out)
+            if not res and not S.pending and nxt < n:
+                time.sleep(max(0.0, min(arrivals[nxt] - (time.perf_counter() - t0), 2e-4)))
         return lat, time.perf_counter() - t0, pix
 
     # warm-up, then the saturation rate from a burst
@@ -236,7 +240,8 @@ def serving(args, torch, nxs, synth):
             "config": {"workload": ("serving: resident scenes of 200k/500k/1M/3M Gaussians, "
                                     "requests uniform over scene, pose, resolution "
                                     "(512x512, 1280x720, 1920x1080) and the four models"),
-                       "workspace_budget_gib": args.serve_budget_gib, "max_batch_views": 16},
+                       "workspace_budget_gib": args.serve_budget_gib, "max_batch_views": 16,
+                       "slots": args.serve_slots},
             "saturation": {"requests": len(burst), "req_per_s": rate_sat,
                            "p50_ms": percentile(lat_b, 50) * 1e3,
                            "p99_ms": percentile(lat_b, 99) * 1e3},
@@ -318,6 +323,7 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-burst", type=int, default=400)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device-to-device copy (untimed) so that "
                          "counter runs can scale FETCH_SIZE / WRITE_SIZE by a kernel "

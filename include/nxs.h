@@ -234,38 +234,48 @@ nxs_status nxs_workspace_bytes(const nxs_context* ctx, size_t* bytes);
 nxs_status nxs_release_workspace(nxs_context* ctx);
 
 /* ---------------------------------------------------------------------------
- * Serving: resident scenes and continuous batching under a workspace budget.
- * A server owns one context on `device` whose workspace limit is
- * `workspace_budget` bytes (0 = none).  Scenes are caller-owned device arrays
- * that must stay unchanged and alive while the server uses them.  Requests
- * queue in submission order; each nxs_server_step serves the oldest pending
- * request together with later pending requests for the same scene with
- * identical options (up to max_batch_views, 0 -> 16, and while the estimated
- * workspace fits the budget) in one multi-view render on `stream`, waits for
- * it, and reports the completed requests' tags and statuses (NXS_OK, or the
- * render's error for a request that fails on its own, e.g. NXS_ECAPACITY when
- * one view alone exceeds the budget).  Results are bitwise those of rendering
- * each request alone with the same options.  A server is used from one host
- * thread.
+ * Serving: resident scenes, continuous batching under a workspace budget, and
+ * several batches in flight.  A server has n_slots slots (0 -> 2, at most 16),
+ * each a context on `device` with its own stream and workspace_budget /
+ * n_slots bytes of workspace (budget 0 = no limit).  Scenes are caller-owned
+ * device arrays that must stay unchanged and alive while the server uses them.
+ * Requests queue in submission order.  A batch is the oldest pending request
+ * together with later pending requests for the same scene with identical
+ * options (up to max_batch_views, 0 -> 16, while the estimated workspace fits a
+ * slot's share), rendered as one multi-view nxs_render_forward.
+ * nxs_server_step collects the batches that have finished, starts a batch on
+ * every free slot, and returns: batches on different slots overlap on the
+ * device, and requests submitted meanwhile join later batches.  Results are
+ * bitwise those of rendering each request alone with the same options.  A
+ * request whose options are invalid, or that alone exceeds a slot's workspace
+ * (NXS_ECAPACITY), is completed with that status without blocking the others.
+ * A server is used from one host thread; outputs of a request may be read once
+ * a step has reported it.
  * ------------------------------------------------------------------------- */
 typedef struct nxs_server nxs_server;
 
 nxs_status nxs_server_create(int device, size_t workspace_budget, int32_t max_batch_views,
-                             nxs_server** out);
+                             int32_t n_slots, nxs_server** out);
+/* Waits for every batch in flight, then frees the server. */
 nxs_status nxs_server_destroy(nxs_server* server);
-/* The server's context (for inspection; do not render on it directly). */
-nxs_context* nxs_server_context(nxs_server* server);
 nxs_status nxs_server_add_scene(nxs_server* server, const nxs_gaussians* g,
                                 int32_t* scene_id);
 /* Queue one view of a scene; `out` (device images, caller-owned) is written
- * when a step completes the request.  opts.keep_state must be 0. */
+ * before a step reports the request.  opts.keep_state must be 0. */
 nxs_status nxs_server_submit(nxs_server* server, int32_t scene_id, const nxs_camera* cam,
                              const nxs_render_opts* opts, const nxs_image* out, int64_t tag);
-/* Serve one batch.  tags / status: host arrays of `capacity` entries; the
- * first *n_done are filled.  Returns an error only if the stream fails. */
-nxs_status nxs_server_step(nxs_server* server, void* stream, int64_t* tags, int32_t* status,
+/* One scheduling step.  tags / status: host arrays of `capacity` entries
+ * (capacity >= max_batch_views + n_slots); the first *n_done are filled with
+ * completed requests, oldest batch first.  wait != 0: if nothing has completed,
+ * block until the oldest batch in flight does.  Returns an error only if a
+ * stream fails. */
+nxs_status nxs_server_step(nxs_server* server, int32_t wait, int64_t* tags, int32_t* status,
                            int32_t capacity, int32_t* n_done);
+/* Requests queued and not yet started; requests in flight on the slots. */
 int32_t nxs_server_pending(const nxs_server* server);
+int32_t nxs_server_in_flight(const nxs_server* server);
+/* Workspace currently held by all slots (bytes). */
+nxs_status nxs_server_workspace_bytes(const nxs_server* server, size_t* bytes);
 const char* nxs_server_last_error(const nxs_server* server);
 
 /* Message for the last non-OK status returned on this context ("" if none).

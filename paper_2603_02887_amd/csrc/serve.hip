@@ -1,19 +1,28 @@
-// Serving loop: resident scenes, continuous batching under a workspace budget.
+// Serving loop: resident scenes, continuous batching under a workspace budget,
+// several batches in flight at once.
 //
 // Requests (scene, camera, render options, caller-owned output images) queue in
-// arrival order.  Each step serves the oldest pending request together with the
-// later pending requests that can share its render: same scene and identical
-// options, so that one multi-view nxs_render_forward covers them all (one
-// projection pass over the scene for all their cameras, one sort, one composite
-// launch).  A batch grows in arrival order while its estimated workspace stays
-// within the budget; the estimate uses the instances per pixel that the
-// scene's last render produced.  The context's workspace limit is the budget,
-// so a batch whose estimate was too low fails with NXS_ECAPACITY instead of
-// growing past it: the step then frees the workspace and retries, and if that
-// fails too, serves the first half of the batch; a single request that cannot
-// fit is completed with that status.  Requests that arrive while a batch renders
-// join a later batch.  Every step synchronises its stream before returning the
-// tags it completed.
+// arrival order.  A batch is the oldest pending request together with the later
+// pending requests that can share its render: same scene and identical options,
+// so that one multi-view nxs_render_forward covers them all (one projection pass
+// over the scene for all their cameras, one sort, one composite launch).  A batch
+// grows in arrival order while its estimated workspace stays within a slot's
+// share of the budget; the estimate uses the instance density that the scene's
+// earlier renders produced.
+//
+// The server has n_slots slots, each a context with its own stream and a share
+// of the budget as its workspace limit.  A step first collects the batches whose
+// completion events have fired, then starts a batch on every free slot while
+// requests are pending, and returns without waiting (unless asked to wait for at
+// least one completion).  So batches on different slots overlap on the device:
+// one slot's projection runs while another's sort or composite does, and
+// requests that arrive meanwhile are admitted as slots free up.
+//
+// A batch whose estimate was too low fails with NXS_ECAPACITY before allocating
+// past the limit: the step reads the instance count the attempt needed,
+// re-estimates and starts the prefix that fits (after one release of a
+// fragmented workspace); a single request that cannot fit on its own, or one
+// with invalid options, is completed with its error without blocking the queue.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,7 +48,16 @@ struct Request {
 
 struct Scene {
   nxs_gaussians g;
-  double inst_per_px;   // instances per output pixel of the last render (estimate)
+  double inst_per_px;   // instances per output pixel of recent renders (estimate)
+};
+
+struct Slot {
+  nxs_context* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  uint64_t seq = 0;              // start order, to report older batches first
+  std::vector<int64_t> tags;     // requests in flight on this slot
 };
 
 bool same_batch(const Request& a, const Request& b) {
@@ -60,14 +78,21 @@ double workspace_estimate(const Scene& sc, const std::vector<const Request*>& ba
   return 88.0 * slots + 68.0 * inst + 12.0 * tiles + (1 << 20);
 }
 
+double pixels_of(const std::vector<const Request*>& batch) {
+  double px = 0.0;
+  for (const Request* r : batch) px += (double)r->cam.width * r->cam.height;
+  return px;
+}
+
 }  // namespace
 
 struct nxs_server {
-  nxs_context* ctx = nullptr;
-  size_t budget = 0;
+  size_t budget = 0;           // per slot
   int32_t max_views = 16;
+  std::vector<Slot> slots;
   std::vector<Scene> scenes;
   std::deque<Request> pending;
+  uint64_t seq = 0;
   std::string err;
 };
 
@@ -83,36 +108,141 @@ nxs_status sfail(nxs_server* s, nxs_status st, const char* fmt, ...) {
   return st;
 }
 
+void destroy_slots(nxs_server* s) {
+  for (Slot& sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.ctx) nxs_destroy(sl.ctx);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  s->slots.clear();
+}
+
+// Start the oldest pending request's batch on slot `sl`.  A request that fails
+// on its own is completed at once into (tags, status).  Returns false if the
+// slot's stream failed.
+bool start_batch(nxs_server* s, Slot& sl, std::vector<int64_t>& tags,
+                 std::vector<int32_t>& status) {
+  Scene& sc = s->scenes[s->pending.front().scene];
+  std::vector<size_t> idx{0};
+  std::vector<const Request*> batch{&s->pending.front()};
+  for (size_t i = 1; i < s->pending.size() && (int32_t)batch.size() < s->max_views; ++i) {
+    if (!same_batch(s->pending.front(), s->pending[i])) continue;
+    batch.push_back(&s->pending[i]);
+    if ((s->budget && workspace_estimate(sc, batch) > (double)s->budget) ||
+        sc.inst_per_px * pixels_of(batch) >= 4.0e9) {
+      batch.pop_back();
+      break;
+    }
+    idx.push_back(i);
+  }
+
+  nxs_status st = NXS_OK;
+  bool released = false;
+  for (;;) {
+    const int32_t V = (int32_t)idx.size();
+    std::vector<nxs_camera> cams(V);
+    std::vector<nxs_image> outs(V);
+    std::vector<const Request*> cur;
+    for (int32_t v = 0; v < V; ++v) {
+      cams[v] = s->pending[idx[v]].cam;
+      outs[v] = s->pending[idx[v]].out;
+      cur.push_back(&s->pending[idx[v]]);
+    }
+    const double pixels = pixels_of(cur);
+    st = nxs_render_forward(sl.ctx, &sc.g, cams.data(), V, &s->pending[idx[0]].opts,
+                            outs.data(), sl.stream);
+    int64_t m = 0, t = 0;
+    nxs_inspect_counts(sl.ctx, &m, &t);
+    if (st == NXS_OK) {
+      // follow the scene's instance density, decaying slowly towards lighter views
+      if (pixels > 0.0) sc.inst_per_px = std::max((double)m / pixels, 0.9 * sc.inst_per_px);
+      if (hipEventRecord(sl.done, sl.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        s->err = "event record failed";
+        return false;
+      }
+      break;
+    }
+    if (V == 1 && (st != NXS_ECAPACITY || released)) break;   // complete it with the error
+    if (st != NXS_ECAPACITY) {
+      idx.resize(1);             // some request of the batch is bad: the oldest alone
+      continue;
+    }
+    // the render needed m instances: re-estimate and keep the prefix that fits
+    if (m > 0 && pixels > 0.0)
+      sc.inst_per_px = std::max(sc.inst_per_px, 1.05 * (double)m / pixels);
+    size_t keep = 1;
+    while (keep < idx.size()) {
+      std::vector<const Request*> pre;
+      for (size_t k = 0; k <= keep; ++k) pre.push_back(&s->pending[idx[k]]);
+      if ((s->budget && workspace_estimate(sc, pre) > (double)s->budget) ||
+          sc.inst_per_px * pixels_of(pre) >= 4.0e9)
+        break;
+      ++keep;
+    }
+    if (keep < idx.size()) {
+      idx.resize(keep);          // serve the older part now, the rest later
+    } else if (!released) {      // it should fit: the workspace is fragmented by
+      released = true;           // earlier batches, so start afresh
+      nxs_release_workspace(sl.ctx);
+    } else {
+      idx.resize((V + 1) / 2);
+    }
+  }
+  if (st == NXS_OK) {
+    sl.busy = true;
+    sl.seq = s->seq++;
+    sl.tags.clear();
+    for (size_t k : idx) sl.tags.push_back(s->pending[k].tag);
+  } else {
+    tags.push_back(s->pending[idx[0]].tag);   // failed on its own: complete it now
+    status.push_back(st);
+    s->err = nxs_last_error(sl.ctx);
+  }
+  for (size_t k = idx.size(); k-- > 0;) s->pending.erase(s->pending.begin() + (long)idx[k]);
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
 
 nxs_status nxs_server_create(int device, size_t workspace_budget, int32_t max_batch_views,
-                             nxs_server** out) {
-  if (!out || max_batch_views < 0) return NXS_EINVAL;
+                             int32_t n_slots, nxs_server** out) {
+  if (!out || max_batch_views < 0 || n_slots < 0 || n_slots > 16) return NXS_EINVAL;
   *out = nullptr;
   nxs_server* s = new (std::nothrow) nxs_server();
   if (!s) return NXS_ENOMEM;
-  nxs_status st = nxs_create(&s->ctx, device);
-  if (st != NXS_OK) {
-    delete s;
-    return st;
-  }
-  s->budget = workspace_budget;
+  const int32_t k = n_slots ? n_slots : 2;
+  s->budget = workspace_budget / (size_t)k;
   s->max_views = max_batch_views ? max_batch_views : 16;
-  nxs_set_workspace_limit(s->ctx, workspace_budget);
+  s->slots.resize(k);
+  for (Slot& sl : s->slots) {
+    nxs_status st = nxs_create(&sl.ctx, device);
+    if (st == NXS_OK &&
+        (hipSetDevice(device) != hipSuccess ||
+         hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess))
+      st = NXS_EHIP;
+    if (st != NXS_OK) {
+      (void)hipGetLastError();
+      destroy_slots(s);
+      delete s;
+      return st;
+    }
+    nxs_set_workspace_limit(sl.ctx, s->budget);
+  }
   *out = s;
   return NXS_OK;
 }
 
 nxs_status nxs_server_destroy(nxs_server* s) {
   if (!s) return NXS_EINVAL;
-  nxs_destroy(s->ctx);
+  destroy_slots(s);
   delete s;
   return NXS_OK;
 }
-
-nxs_context* nxs_server_context(nxs_server* s) { return s ? s->ctx : nullptr; }
 
 nxs_status nxs_server_add_scene(nxs_server* s, const nxs_gaussians* g, int32_t* scene_id) {
   if (!s || !g || !scene_id) return NXS_EINVAL;
@@ -139,93 +269,79 @@ nxs_status nxs_server_submit(nxs_server* s, int32_t scene_id, const nxs_camera* 
 
 int32_t nxs_server_pending(const nxs_server* s) { return s ? (int32_t)s->pending.size() : 0; }
 
-nxs_status nxs_server_step(nxs_server* s, void* stream, int64_t* tags, int32_t* status,
+int32_t nxs_server_in_flight(const nxs_server* s) {
+  if (!s) return 0;
+  int32_t n = 0;
+  for (const Slot& sl : s->slots)
+    if (sl.busy) n += (int32_t)sl.tags.size();
+  return n;
+}
+
+nxs_status nxs_server_workspace_bytes(const nxs_server* s, size_t* bytes) {
+  if (!s || !bytes) return NXS_EINVAL;
+  size_t total = 0;
+  for (const Slot& sl : s->slots) {
+    size_t b = 0;
+    nxs_workspace_bytes(sl.ctx, &b);
+    total += b;
+  }
+  *bytes = total;
+  return NXS_OK;
+}
+
+nxs_status nxs_server_step(nxs_server* s, int32_t wait, int64_t* tags, int32_t* status,
                            int32_t capacity, int32_t* n_done) {
-  if (!s || !n_done || (capacity > 0 && (!tags || !status))) return NXS_EINVAL;
+  if (!s || !n_done || capacity < 1 || !tags || !status) return NXS_EINVAL;
   s->err.clear();
+  if (capacity < s->max_views + (int32_t)s->slots.size())
+    return sfail(s, NXS_EINVAL, "capacity must be at least max_batch_views + n_slots");
   *n_done = 0;
-  if (s->pending.empty()) return NXS_OK;
-  if (capacity < 1) return sfail(s, NXS_EINVAL, "capacity must be >= 1");
-  const int32_t limit = std::min(s->max_views, capacity);
-  Scene& sc = s->scenes[s->pending.front().scene];
-
-  // oldest request, then later compatible ones while the estimate fits
-  std::vector<size_t> idx{0};
-  std::vector<const Request*> batch{&s->pending.front()};
-  for (size_t i = 1; i < s->pending.size() && (int32_t)batch.size() < limit; ++i) {
-    if (!same_batch(s->pending.front(), s->pending[i])) continue;
-    batch.push_back(&s->pending[i]);
-    double px = 0.0;
-    for (const Request* r : batch) px += (double)r->cam.width * r->cam.height;
-    if ((s->budget && workspace_estimate(sc, batch) > (double)s->budget) ||
-        sc.inst_per_px * px >= 4.0e9) {
-      batch.pop_back();
-      break;
-    }
-    idx.push_back(i);
-  }
-
-  hipStream_t strm = (hipStream_t)stream;
-  nxs_status st = NXS_OK;
-  bool released = false;
-  for (;;) {
-    const int32_t V = (int32_t)idx.size();
-    std::vector<nxs_camera> cams(V);
-    std::vector<nxs_image> outs(V);
-    double pixels = 0.0;
-    for (int32_t v = 0; v < V; ++v) {
-      cams[v] = s->pending[idx[v]].cam;
-      outs[v] = s->pending[idx[v]].out;
-      pixels += (double)cams[v].width * cams[v].height;
-    }
-    st = nxs_render_forward(s->ctx, &sc.g, cams.data(), V, &s->pending[idx[0]].opts,
-                            outs.data(), stream);
-    int64_t m = 0, t = 0;
-    nxs_inspect_counts(s->ctx, &m, &t);
-    if (st == NXS_OK) {
-      // follow the scene's instance density, decaying slowly towards lighter views
-      if (pixels > 0.0) sc.inst_per_px = std::max((double)m / pixels, 0.9 * sc.inst_per_px);
-      if (hipStreamSynchronize(strm) != hipSuccess) {
+  std::vector<int64_t> t_out;
+  std::vector<int32_t> s_out;
+  // finished batches, oldest first, as far as `capacity` allows; with `block`,
+  // wait for the oldest one in flight
+  auto collect = [&](bool block) -> bool {
+    for (;;) {
+      Slot* best = nullptr;
+      for (Slot& sl : s->slots)
+        if (sl.busy && (!best || sl.seq < best->seq)) best = &sl;
+      if (!best) return true;
+      if (t_out.size() + best->tags.size() > (size_t)capacity) return true;
+      const hipError_t q = block ? hipEventSynchronize(best->done) : hipEventQuery(best->done);
+      if (q == hipErrorNotReady) return true;
+      if (q != hipSuccess) {
         (void)hipGetLastError();
-        return sfail(s, NXS_EHIP, "stream synchronisation failed");
+        return false;
       }
-      break;
+      block = false;
+      t_out.insert(t_out.end(), best->tags.begin(), best->tags.end());
+      s_out.insert(s_out.end(), best->tags.size(), (int32_t)NXS_OK);
+      best->busy = false;
     }
-    if (V == 1 && (st != NXS_ECAPACITY || released)) break;   // complete it with the error
-    if (st != NXS_ECAPACITY) {
-      idx.resize(1);             // some request of the batch is bad: the oldest alone
-      continue;
+  };
+  // 1. batches that have finished
+  if (!collect(false)) return sfail(s, NXS_EHIP, "a render stream failed");
+  // 2. start batches on the free slots (each start completes at most one
+  //    request at once, so keep room for it)
+  auto start_all = [&]() -> bool {
+    for (Slot& sl : s->slots) {
+      if (sl.busy || s->pending.empty()) continue;
+      if (t_out.size() >= (size_t)capacity) break;
+      if (!start_batch(s, sl, t_out, s_out)) return false;
     }
-    // the render needed m instances: re-estimate and keep the prefix that fits
-    if (m > 0 && pixels > 0.0)
-      sc.inst_per_px = std::max(sc.inst_per_px, 1.05 * (double)m / pixels);
-    size_t keep = 1;
-    while (keep < idx.size()) {
-      std::vector<const Request*> pre;
-      for (size_t k = 0; k <= keep; ++k) pre.push_back(&s->pending[idx[k]]);
-      if (workspace_estimate(sc, pre) > (double)s->budget && s->budget) break;
-      double px = 0.0;
-      for (const Request* r : pre) px += (double)r->cam.width * r->cam.height;
-      if (sc.inst_per_px * px >= 4.0e9) break;   // the 32-bit instance range
-      ++keep;
-    }
-    if (keep < idx.size()) {
-      idx.resize(keep);          // serve the older part now, the rest later
-    } else if (!released) {      // it should fit: the workspace is fragmented by
-      released = true;           // earlier batches, so start afresh
-      nxs_release_workspace(s->ctx);
-    } else {
-      idx.resize((V + 1) / 2);
-    }
+    return true;
+  };
+  if (!start_all()) return sfail(s, NXS_EHIP, "%s", s->err.c_str());
+  // 3. optionally wait for the oldest batch in flight, then refill its slot
+  if (wait && t_out.empty()) {
+    if (!collect(true)) return sfail(s, NXS_EHIP, "a render stream failed");
+    if (!start_all()) return sfail(s, NXS_EHIP, "%s", s->err.c_str());
   }
-  // complete the served requests (or the single one that failed), in order
-  for (size_t k = 0; k < idx.size(); ++k) {
-    tags[k] = s->pending[idx[k]].tag;
-    status[k] = st;
+  for (size_t k = 0; k < t_out.size(); ++k) {
+    tags[k] = t_out[k];
+    status[k] = s_out[k];
   }
-  *n_done = (int32_t)idx.size();
-  if (st != NXS_OK) s->err = nxs_last_error(s->ctx);
-  for (size_t k = idx.size(); k-- > 0;) s->pending.erase(s->pending.begin() + (long)idx[k]);
+  *n_done = (int32_t)t_out.size();
   return NXS_OK;
 }
 

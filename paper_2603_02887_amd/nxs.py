@@ -22,15 +22,15 @@ STATUS = {0: "NXS_OK", -1: "NXS_EINVAL", -2: "NXS_ENOMEM", -3: "NXS_EHIP",
 SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_render_backward",
            "nxs_autotune", "nxs_set_workspace_limit", "nxs_workspace_bytes",
            "nxs_release_workspace",
-           "nxs_server_create", "nxs_server_destroy", "nxs_server_context",
-           "nxs_server_add_scene", "nxs_server_submit", "nxs_server_step",
-           "nxs_server_pending", "nxs_server_last_error",
+           "nxs_server_create", "nxs_server_destroy", "nxs_server_add_scene",
+           "nxs_server_submit", "nxs_server_step", "nxs_server_pending",
+           "nxs_server_in_flight", "nxs_server_workspace_bytes", "nxs_server_last_error",
            "nxs_last_error",
            "nxs_set_timing", "nxs_inspect_stage_times", "nxs_inspect_counts",
            "nxs_inspect_instances", "nxs_inspect_ranges", "nxs_inspect_projection"]
 # entry points that do not return an nxs_status
 _NOT_STATUS = {"nxs_last_error": ctypes.c_char_p, "nxs_server_last_error": ctypes.c_char_p,
-               "nxs_server_context": c_void_p, "nxs_server_pending": c_int32}
+               "nxs_server_pending": c_int32, "nxs_server_in_flight": c_int32}
 
 
 class NxsError(RuntimeError):
@@ -98,14 +98,15 @@ def lib():
         L.nxs_set_workspace_limit.argtypes = [c_void_p, ctypes.c_size_t]
         L.nxs_workspace_bytes.argtypes = [c_void_p, POINTER(ctypes.c_size_t)]
         L.nxs_release_workspace.argtypes = [c_void_p]
-        L.nxs_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, c_int32,
+        L.nxs_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, c_int32, c_int32,
                                         POINTER(c_void_p)]
         L.nxs_server_destroy.argtypes = [c_void_p]
-        L.nxs_server_context.argtypes = [c_void_p]
+        L.nxs_server_in_flight.argtypes = [c_void_p]
+        L.nxs_server_workspace_bytes.argtypes = [c_void_p, POINTER(ctypes.c_size_t)]
         L.nxs_server_add_scene.argtypes = [c_void_p, POINTER(Gaussians), POINTER(c_int32)]
         L.nxs_server_submit.argtypes = [c_void_p, c_int32, POINTER(Camera), POINTER(RenderOpts),
                                         POINTER(Image), c_int64]
-        L.nxs_server_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+        L.nxs_server_step.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int32,
                                       POINTER(c_int32)]
         L.nxs_server_pending.argtypes = [c_void_p]
         L.nxs_server_last_error.argtypes = [c_void_p]
@@ -375,23 +376,24 @@ class Renderer:
 
 
 class Server:
-    """Continuous-batching render server over resident scenes (nxs_server_*).
+    """Continuous-batching render server over resident scenes (nxs_server_*),
+    with `n_slots` batches in flight at once.
 
     add_scene(g) keeps a scene's device arrays alive; submit() queues one view
-    and returns its output images (written once a step completes the
-    request); step() serves one batch and returns [(tag, status, outputs)]."""
+    and returns its output images (written before a step reports the request);
+    step(wait) serves and returns [(tag, status, outputs)]."""
 
-    def __init__(self, device=0, workspace_budget=0, max_batch_views=16):
+    def __init__(self, device=0, workspace_budget=0, max_batch_views=16, n_slots=2):
         self._L = lib()
         self._s = c_void_p()
         st = self._L.nxs_server_create(int(device), int(workspace_budget), int(max_batch_views),
-                                       byref(self._s))
+                                       int(n_slots), byref(self._s))
         if st != 0:
             raise NxsError(st, "nxs_server_create failed")
         self.device = torch.device("cuda", int(device))
         self._scenes = []
         self._inflight = {}
-        self._cap = 64
+        self._cap = int(max_batch_views or 16) + int(n_slots or 2) + 8
         self._tags = (c_int64 * self._cap)()
         self._status = (c_int32 * self._cap)()
 
@@ -431,21 +433,31 @@ class Server:
 
     @property
     def pending(self):
+        """Requests queued and not yet started."""
         return int(self._L.nxs_server_pending(self._s))
 
-    def step(self, stream=None):
-        if stream is None:
-            stream = torch.cuda.current_stream(self.device)
+    @property
+    def in_flight(self):
+        """Requests started on a slot and not yet reported."""
+        return int(self._L.nxs_server_in_flight(self._s))
+
+    def step(self, wait=True):
         n = c_int32()
-        self._check(self._L.nxs_server_step(self._s, c_void_p(stream.cuda_stream), self._tags,
-                                            self._status, self._cap, byref(n)))
+        self._check(self._L.nxs_server_step(self._s, int(bool(wait)), self._tags, self._status,
+                                            self._cap, byref(n)))
         return [(int(self._tags[k]), int(self._status[k]), self._inflight.pop(int(self._tags[k])))
                 for k in range(n.value)]
 
+    def drain(self):
+        """Step until nothing is pending or in flight; returns all completions."""
+        done = []
+        while self.pending or self.in_flight:
+            done += self.step(wait=True)
+        return done
+
     def workspace_bytes(self):
         b = ctypes.c_size_t()
-        ctx = self._L.nxs_server_context(self._s)
-        self._check(self._L.nxs_workspace_bytes(ctx, byref(b)))
+        self._check(self._L.nxs_server_workspace_bytes(self._s, byref(b)))
         return int(b.value)
 
 

@@ -173,3 +173,77 @@ def test_backward_culled_and_empty(R):
     torch.cuda.synchronize()
     for k, v in out.items():
         assert torch.count_nonzero(v) == 0, k
+
+
+# ------------------------------------------------ the differentiation workload
+
+def _diff_workload():
+    sc, cams = synth.diff_scene()
+    rng = np.random.default_rng(33)
+    logit = np.log(sc.opacities / (1 - sc.opacities)) + rng.normal(0, 0.1, sc.n)
+    tgt = synth.Scene(sc.means + rng.normal(0, 0.01, sc.means.shape).astype(np.float32),
+                      sc.scales, sc.quats, (1 / (1 + np.exp(-logit))).astype(np.float32),
+                      sc.sh, sc.sh_degree)
+    return sc, tgt, cams
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("model,op,n_focus", [(3, O.SUPERLINEAR, 16), (0, O.EXPONENTIAL, 8)])
+def test_gradients_at_workload_size(R, model, op, n_focus):
+    """500,000 Gaussians, 8 views at 1280x720, per-pixel L1 loss against a
+    render of the jittered scene: gradients of random parameters (4 per
+    Gaussian, over visible Gaussians drawn among those with footprints under 4 px in
+    every view) against FP64 central differences (tests/fd_local.py)."""
+    from oracle import project as P
+    from paper_2603_02887_amd import nxs
+    from tests import fd_local
+    sc, tgt, cams = _diff_workload()
+    g, gt = nxs.scene_to_device(sc), nxs.scene_to_device(tgt)
+    target = R.render(gt, cams, model=model, overdraw=False)
+    out = R.render(g, cams, model=model, overdraw=False)
+    torch.cuda.synchronize()
+    pix = sum(c.width * c.height for c in cams)
+    w = [(torch.sign(o["rgb"] - t["rgb"]) / (3.0 * pix)).double().cpu().numpy()
+         for o, t in zip(out, target)]
+    # candidates: in some view, footprint under 4 px in all views
+    smax, seen = np.zeros(sc.n), np.zeros(sc.n, bool)
+    for c in cams:
+        pr = P.project(sc, c)
+        s_ = np.sqrt(np.maximum(pr["cov2d"][:, 0], pr["cov2d"][:, 2]))
+        inimg = (pr["z"] > 0.1) & (pr["uv"][:, 0] > -20) & (pr["uv"][:, 0] < c.width + 20) & \
+                (pr["uv"][:, 1] > -20) & (pr["uv"][:, 1] < c.height + 20)
+        smax = np.where(inimg, np.maximum(smax, s_), smax)
+        seen |= inimg
+    # ... and visible: a nonzero opacity gradient (most Gaussians are hidden)
+    R.render(g, cams, model=model, overdraw=False, keep_state=True)
+    G0 = R.backward(g, [torch.from_numpy(a).float().cuda() for a in w])
+    torch.cuda.synchronize()
+    live = G0["opacities"].abs().cpu().numpy() > 0
+    rng = np.random.default_rng(77 + model)
+    focus = rng.choice(np.nonzero(seen & (smax < 4.0) & live)[0], n_focus, replace=False)
+    L = fd_local.LocalLoss(sc, cams, op, focus)
+    L.mask_weights(w)
+    R.render(g, cams, model=model, overdraw=False, keep_state=True)
+    G = R.backward(g, [torch.from_numpy(a).float().cuda() for a in w])
+    torch.cuda.synchronize()
+    G = {k: v.double().cpu().numpy() for k, v in G.items()}
+    params = fd.params_of(sc)
+    fields = [("means", (0,)), ("means", (1,)), ("means", (2,)), ("scales", (0,)),
+              ("scales", (2,)), ("quats", (1,)), ("quats", (3,)), ("opacities", ()),
+              ("sh", (0, 0)), ("sh", (0, 2))]
+    got, want = [], []
+    for i in focus:
+        for f in rng.choice(len(fields), 4, replace=False):
+            field, sub = fields[f]
+            idx = (int(i),) + sub
+            h = H_STEP * (abs(params[field][idx]) if field == "scales" else 1.0)
+            want.append(L.grad_element(params, w, field, idx, h))
+            got.append(G[field][idx])
+    got, want = np.array(got), np.array(want)
+    scale = np.abs(want).max()
+    tol = 2e-3 * np.abs(want) + 2e-4 * scale
+    bad = np.nonzero(np.abs(got - want) > tol)[0]
+    print("params", len(got), "worst/tol", float(np.max(np.abs(got - want) / tol)),
+          "nonzero", int(np.count_nonzero(want)))
+    assert bad.size == 0, (bad, got[bad], want[bad])
+    assert np.count_nonzero(want) >= len(want) // 2     # the check is not vacuous

@@ -57,14 +57,14 @@ def _alone(R, g, req):
 def test_mix_equals_alone(R):
     from paper_2603_02887_amd import nxs
     scenes = [nxs.scene_to_device(s) for s in _scenes()]
-    S = nxs.Server(0, workspace_budget=0, max_batch_views=16)
+    S = nxs.Server(0, workspace_budget=0, max_batch_views=16, n_slots=2)
     ids = [S.add_scene(g) for g in scenes]
     reqs = _requests(48, len(scenes), seed=1)
     for q in reqs[:30]:
         S.submit(ids[q["scene"]], q["cam"], q["tag"], model=q["model"])
     done, steps, batch_sizes = {}, 0, []
-    while S.pending:
-        res = S.step()
+    while S.pending or S.in_flight:
+        res = S.step(wait=True)
         steps += 1
         batch_sizes.append(len(res))
         for tag, st, out in res:
@@ -88,15 +88,15 @@ def test_budget_splits_and_rejects(R):
     big = synth.random_scene(65, 400_000, sh_degree=0)
     gs, gb = nxs.scene_to_device(small), nxs.scene_to_device(big)
     budget = 12 << 20             # 12 MiB: a 400k-Gaussian render alone needs ~35 MB
-    S = nxs.Server(0, workspace_budget=budget, max_batch_views=64)
+    S = nxs.Server(0, workspace_budget=budget, max_batch_views=64, n_slots=2)
     i_small, i_big = S.add_scene(gs), S.add_scene(gb)
     reqs = [q for q in _requests(40, 1, seed=2)]
     for q in reqs:
         S.submit(i_small, q["cam"], q["tag"], model=q["model"])
     S.submit(i_big, reqs[0]["cam"], 7, model=0)
     results, steps = {}, 0
-    while S.pending:
-        for tag, st, out in S.step():
+    while S.pending or S.in_flight:
+        for tag, st, out in S.step(wait=True):
             results[tag] = (st, out)
         steps += 1
         assert S.workspace_bytes() <= budget
@@ -120,10 +120,30 @@ def test_submit_errors(R):
         S.submit(sid, cam, 2, keep_state=True)
     S.submit(sid, cam, 3, model=9)                   # invalid model: fails alone
     S.submit(sid, cam, 4, model=1)
-    got = {}
-    while S.pending:
-        for tag, st, _ in S.step():
-            got[tag] = st
+    got = {tag: st for tag, st, _ in S.drain()}
     assert got == {3: -1, 4: 0}
     assert S.step() == []
+    S.close()
+
+
+def test_batches_overlap_on_the_device(R):
+    """Two slots: requests for two scenes start as two batches in one step,
+    both in flight before either is collected; results equal renders alone."""
+    from paper_2603_02887_amd import nxs
+    scenes = [nxs.scene_to_device(s) for s in _scenes()[:2]]
+    S = nxs.Server(0, n_slots=2)
+    ids = [S.add_scene(g) for g in scenes]
+    reqs = _requests(12, 2, seed=4)
+    for q in reqs:
+        S.submit(ids[q["scene"]], q["cam"], q["tag"], model=0)
+    first = S.step(wait=False)
+    started = len(reqs) - S.pending - len(first)
+    assert S.in_flight == started
+    # both slots took a batch: more requests started than the larger batch holds
+    per_scene = max(sum(q["scene"] == k for q in reqs) for k in range(2))
+    assert started + len(first) > per_scene or S.pending == 0
+    done = {tag: out for tag, st, out in first + S.drain()}
+    for q in reqs:
+        q["model"] = 0
+        assert torch.equal(done[q["tag"]]["rgb"], _alone(R, scenes[q["scene"]], q)["rgb"])
     S.close()

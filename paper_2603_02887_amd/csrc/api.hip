@@ -41,6 +41,7 @@ struct nxs_context {
   ViewDev* host_views = nullptr;      // pinned
   int host_views_cap = 0;
   hipEvent_t done = nullptr;           // recorded at the end of each render
+  hipEvent_t counted = nullptr;        // the instance count has reached the host
   bool has_done = false;
   // optional per-stage timing (hipEvents on the render's stream)
   bool timing = false;
@@ -94,7 +95,10 @@ nxs_status ensure(nxs_context* ctx, DevBuf& b, size_t bytes) {
                   others + want, ctx->ws_limit);
   }
   if (b.p) {
-    hipError_t e = hipFree(b.p);  // hipFree waits for outstanding work on the device
+    // kernels enqueued earlier (this render's included) may still use the
+    // buffer: wait for the device before freeing it (growth is rare)
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipFree(b.p);
     ctx->ws_total -= b.cap;
     b.p = nullptr;
     b.cap = 0;
@@ -184,7 +188,8 @@ nxs_status nxs_create(nxs_context** out, int device) {
   if (hipSetDevice(device) != hipSuccess ||
       hipHostMalloc((void**)&ctx->host_counters, sizeof(Counters), hipHostMallocDefault) !=
           hipSuccess ||
-      hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->counted, hipEventDisableTiming) != hipSuccess) {
     if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
     delete ctx;
     return NXS_EHIP;
@@ -213,6 +218,7 @@ nxs_status nxs_destroy(nxs_context* ctx) {
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
   if (ctx->host_views) (void)hipHostFree(ctx->host_views);
   if (ctx->done) (void)hipEventDestroy(ctx->done);
+  if (ctx->counted) (void)hipEventDestroy(ctx->counted);
   for (int k = 0; k < 8; ++k)
     if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
   delete ctx;
@@ -337,8 +343,35 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
                  P<uint4>(ctx->partials), dcount, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(1));
+  // The instance count M is read by the host only where it sizes buffers and
+  // grids: the depth sort (its digits planned on the device) and the emission
+  // (total read on the device, writes bounded by the current capacity) are
+  // enqueued first, so the GPU keeps working while the host waits.
   HIP_TRY(hipMemcpyAsync(ctx->host_counters, dcount, sizeof(Counters), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipEventRecord(ctx->counted, s));
+  if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_words(S))) ||
+      (st = ensure(ctx, ctx->ranges, 8 * total_tiles)))
+    return st;
+  HIP_TRY(mark(2));
+  launch_fill_u32(P<uint32_t>(ctx->ranges), 2 * total_tiles, 0u, s);
+  // 1. depth sort of the slots (values: the slots 0..S-1)
+  const int wd = radix_sort_planned(P<uint32_t>(ctx->depth_key), nullptr,
+                                    P<uint32_t>(ctx->dsort_a), P<uint32_t>(ctx->slot_a),
+                                    P<uint32_t>(ctx->dsort_b), P<uint32_t>(ctx->slot_b), S,
+                                    dcount->plan, P<uint32_t>(ctx->counts), s);
+  uint32_t* sorted_slots = wd ? P<uint32_t>(ctx->slot_b) : P<uint32_t>(ctx->slot_a);
+  HIP_TRY(mark(3));
+  // 2. emission in depth order, into the buffers as they are
+  launch_emit_scan(sorted_slots, S, proj, P<uint32_t>(ctx->scan_local),
+                   P<uint32_t>(ctx->block_sums), s);
+  const size_t cap = std::min(ctx->inst_tile.cap, ctx->inst_val.cap) / 4;
+  const uint32_t cap32 = (uint32_t)std::min<size_t>(cap, 0xFFFFFFFFu);
+  if (cap32 > 0)
+    launch_emit_write(sorted_slots, S, g->n, proj, dviews, P<uint32_t>(ctx->scan_local),
+                      P<uint32_t>(ctx->block_sums), &dcount->total, cap32,
+                      P<uint32_t>(ctx->inst_tile), P<uint32_t>(ctx->inst_val), s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventSynchronize(ctx->counted));
   const uint64_t M = ctx->host_counters->total;
   // what this render needs, visible through nxs_inspect_counts even if it fails
   ctx->last_m = (int64_t)M;
@@ -348,32 +381,21 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
     return fail(ctx, NXS_ECAPACITY, "%llu tile instances exceed the 32-bit range",
                 (unsigned long long)M);
 
-  // ---- instance buffers ---------------------------------------------------------
-  const int dbits = bit_length(ctx->host_counters->dmin ^ ctx->host_counters->dmax);
+  // ---- instance buffers (growing them waits for the work above) ------------------
   const int tbits = bit_length((uint64_t)(total_tiles - 1));
-  const int64_t sort_n = std::max<int64_t>(S, (int64_t)M);
-  if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_words(sort_n))) ||
+  if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_words(std::max<int64_t>(S, M)))) ||
       (st = ensure(ctx, ctx->inst_tile, 4 * M)) || (st = ensure(ctx, ctx->inst_tile_alt, 4 * M)) ||
       (st = ensure(ctx, ctx->inst_val, 4 * M)) || (st = ensure(ctx, ctx->inst_val_alt, 4 * M)) ||
-      (st = ensure(ctx, ctx->crec, 48 * M)) || (st = ensure(ctx, ctx->ranges, 8 * total_tiles)))
+      (st = ensure(ctx, ctx->crec, 48 * M)))
     return st;
-
   uint32_t* inst_tile = P<uint32_t>(ctx->inst_tile);
   uint32_t* inst_val = P<uint32_t>(ctx->inst_val);
-  HIP_TRY(mark(2));
-  launch_fill_u32(P<uint32_t>(ctx->ranges), 2 * total_tiles, 0u, s);
+  if (M > cap32)   // the emission above did not fit: emit again into the grown buffers
+    launch_emit_write(sorted_slots, S, g->n, proj, dviews, P<uint32_t>(ctx->scan_local),
+                      P<uint32_t>(ctx->block_sums), &dcount->total, (uint32_t)M, inst_tile,
+                      inst_val, s);
+  HIP_TRY(mark(4));
   if (M > 0) {
-    // 1. depth sort of the slots on the bits that vary among visible ones
-    //    (values: the slots 0..S-1)
-    const int wd = radix_sort(P<uint32_t>(ctx->depth_key), nullptr, P<uint32_t>(ctx->dsort_a),
-                              P<uint32_t>(ctx->slot_a), P<uint32_t>(ctx->dsort_b),
-                              P<uint32_t>(ctx->slot_b), S, dbits, P<uint32_t>(ctx->counts), s);
-    uint32_t* sorted_slots = wd ? P<uint32_t>(ctx->slot_b) : P<uint32_t>(ctx->slot_a);
-    HIP_TRY(mark(3));
-    // 2. emission in depth order
-    launch_emit(sorted_slots, S, g->n, proj, dviews, P<uint32_t>(ctx->scan_local),
-                P<uint32_t>(ctx->block_sums), (uint32_t)M, inst_tile, inst_val, s);
-    HIP_TRY(mark(4));
     // 3. stable sort by global tile
     const int wt = radix_sort(inst_tile, inst_val, P<uint32_t>(ctx->inst_tile_alt),
                               P<uint32_t>(ctx->inst_val_alt), inst_tile, inst_val, (int64_t)M,
@@ -388,7 +410,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
                          (float)std::log2((double)alpha_min), P<uint2>(ctx->ranges),
                          P<float4>(ctx->crec), s);
   } else {
-    for (int k = 3; k <= 5; ++k) HIP_TRY(mark(k));
+    HIP_TRY(mark(5));
   }
   HIP_TRY(mark(6));
   // 5. composite (also writes the background where no splat lands)

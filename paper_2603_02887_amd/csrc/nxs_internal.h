@@ -52,6 +52,8 @@ struct ProjDev {
 struct Counters {
   unsigned long long total;
   uint32_t dmin, dmax;
+  // the depth sort's digits (shift | width << 8 per pass), from dmin ^ dmax
+  uint32_t plan[4];
 };
 
 // ---- launchers (all enqueue on `s`) ------------------------------------------
@@ -70,6 +72,13 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
 // vals_in == nullptr: values are the input positions.  `counts` needs
 // radix_counts_words(n) u32.
 size_t radix_counts_words(int64_t n);
+// The same sort with its digits read from device memory: plan[p] = shift |
+// width << 8 for kPlanPasses passes (a pass of width 0 copies).  Enough for
+// keys of up to 32 varying bits.
+constexpr int kPlanPasses = 4;
+int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
+                       uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
+                       const uint32_t* plan, uint32_t* counts, hipStream_t s);
 int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
                hipStream_t s);
@@ -77,10 +86,15 @@ int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
 
 // Exclusive scan of ntiles in sorted-slot order and emission of instances.
 size_t scan_blocks_size(int64_t n);
-void launch_emit(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
-                 const ProjDev& proj, const ViewDev* views, uint32_t* scan_local,
-                 uint32_t* block_sums, uint32_t total, uint32_t* inst_tile,
-                 uint32_t* inst_val, hipStream_t s);
+void launch_emit_scan(const uint32_t* sorted_slots, int64_t n_slots, const ProjDev& proj,
+                      uint32_t* scan_local, uint32_t* block_sums, hipStream_t s);
+// Writes the instances of the depth-sorted slots; the total is read from
+// `total_dev`; instances at positions >= capacity are not written.
+void launch_emit_write(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
+                       const ProjDev& proj, const ViewDev* views, const uint32_t* scan_local,
+                       const uint32_t* block_sums, const unsigned long long* total_dev,
+                       uint32_t capacity, uint32_t* inst_tile, uint32_t* inst_val,
+                       hipStream_t s);
 
 
 

@@ -363,6 +363,16 @@ __global__ __launch_bounds__(1024) void reduce_counters_kernel(const uint4* __re
     c->total = tot;
     c->dmin = mn;
     c->dmax = mx;
+    // the depth sort needs the bits that vary among visible depths, in
+    // kPlanPasses balanced digits
+    const uint32_t diff = mn <= mx ? (mn ^ mx) : 0u;
+    const int nbits = diff ? 32 - __clz((int)diff) : 0;
+    int shift = 0;
+    for (int p = 0; p < kPlanPasses; ++p) {
+      const int w = (nbits - shift + (kPlanPasses - p) - 1) / (kPlanPasses - p);
+      c->plan[p] = (uint32_t)shift | ((uint32_t)w << 8);
+      shift += w;
+    }
   }
 }
 

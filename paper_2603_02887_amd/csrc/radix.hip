@@ -47,11 +47,25 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, int width, bool vali
   return peers;
 }
 
+// A pass's digit is (key >> shift) & (2^width - 1); with `plan` the pair comes
+// from device memory (plan[pass] = shift | width << 8), so a sort can be
+// enqueued before the host knows how many bits vary.
+__device__ __forceinline__ void pass_digit(const uint32_t* plan, int pass, int& shift,
+                                           int& width) {
+  if (plan) {
+    const uint32_t w = plan[pass];
+    shift = (int)(w & 0xFFu);
+    width = (int)((w >> 8) & 0xFFu);
+  }
+}
+
 __global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* __restrict__ keys,
                                                       int64_t n, int shift, int width,
-                                                      uint32_t nchunks, uint32_t per,
+                                                      const uint32_t* __restrict__ plan,
+                                                      int pass, uint32_t nchunks, uint32_t per,
                                                       uint32_t* __restrict__ counts) {
   __shared__ uint32_t h[kRBins];
+  pass_digit(plan, pass, shift, width);
   const uint32_t c = chunk_of(blockIdx.x, per);
   if (c >= nchunks) return;                    // the whole work-group
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -104,8 +118,13 @@ __device__ __forceinline__ uint32_t rx_block_scan(uint32_t x, uint32_t* s_tmp, u
 // One work-group per digit: exclusive scan of counts[d][0..nchunks) in place.
 __global__ __launch_bounds__(kRThreads) void rx_scan(uint32_t* __restrict__ counts,
                                                      uint32_t nchunks,
-                                                     uint32_t* __restrict__ totals) {
+                                                     uint32_t* __restrict__ totals,
+                                                     const uint32_t* __restrict__ plan,
+                                                     int pass) {
   __shared__ uint32_t s_tmp[kRWaves];
+  int shift = 0, width = 8;
+  pass_digit(plan, pass, shift, width);
+  if (blockIdx.x >= (1u << width)) return;    // the whole work-group
   uint32_t* row = counts + (int64_t)blockIdx.x * nchunks;
   uint32_t running = 0;
   for (uint32_t b = 0; b < nchunks; b += kRThreads * 4) {
@@ -133,8 +152,8 @@ __global__ __launch_bounds__(kRThreads) void rx_scan(uint32_t* __restrict__ coun
 __global__ __launch_bounds__(kRThreads) void rx_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n, int shift,
-    int width, uint32_t nchunks, uint32_t per, const uint32_t* __restrict__ counts,
-    const uint32_t* __restrict__ totals) {
+    int width, const uint32_t* __restrict__ plan, int pass, uint32_t nchunks, uint32_t per,
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals) {
   __shared__ uint32_t s_key[kRChunk];
   __shared__ uint32_t s_val[kRChunk];
   __shared__ uint32_t s_wave[kRWaves][kRBins];
@@ -142,6 +161,7 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
   __shared__ uint32_t s_lbase[kRBins];
   __shared__ uint32_t s_tmp[kRWaves];
 
+  pass_digit(plan, pass, shift, width);
   const uint32_t c = chunk_of(blockIdx.x, per);
   if (c >= nchunks) return;                    // the whole work-group
   const int t = threadIdx.x;
@@ -228,35 +248,59 @@ size_t radix_counts_words(int64_t n) {
   return (size_t)nchunks * kRBins + kRBins;
 }
 
+namespace {
+
+int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
+               uint32_t* k1, uint32_t* v1, int64_t n, int passes, const int* shifts,
+               const int* widths, const uint32_t* plan, uint32_t* counts, hipStream_t s) {
+  const uint32_t nchunks = (uint32_t)((n + kRChunk - 1) / kRChunk);
+  const uint32_t per = (nchunks + kRXcds - 1) / kRXcds;
+  const unsigned grid = per * kRXcds;
+  uint32_t* totals = counts + (size_t)nchunks * kRBins;
+  const uint32_t* kin = keys_in;
+  const uint32_t* vin = vals_in;
+  int cur = -1;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = shifts ? shifts[p] : 0, width = widths ? widths[p] : 8;
+    uint32_t* kout = (cur == 0) ? k1 : k0;
+    uint32_t* vout = (cur == 0) ? v1 : v0;
+    hipLaunchKernelGGL(rx_count, dim3(grid), dim3(kRThreads), 0, s, kin, n, shift, width, plan,
+                       p, nchunks, per, counts);
+    hipLaunchKernelGGL(rx_scan, dim3(plan ? kRBins : (1u << width)), dim3(kRThreads), 0, s,
+                       counts, nchunks, totals, plan, p);
+    hipLaunchKernelGGL(rx_scatter, dim3(grid), dim3(kRThreads), 0, s, kin, vin, kout, vout, n,
+                       shift, width, plan, p, nchunks, per, counts, totals);
+    kin = kout;
+    vin = vout;
+    cur = (cur == 0) ? 1 : 0;
+  }
+  return cur;
+}
+
+}  // namespace
+
 int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
                hipStream_t s) {
   if (n <= 0) return 0;
   nbits = std::max(nbits, 1);
-  const uint32_t nchunks = (uint32_t)((n + kRChunk - 1) / kRChunk);
-  const uint32_t per = (nchunks + kRXcds - 1) / kRXcds;
-  const unsigned grid = per * kRXcds;
-  uint32_t* totals = counts + (size_t)nchunks * kRBins;
   const int passes = (nbits + 7) / 8;
-  const uint32_t* kin = keys_in;
-  const uint32_t* vin = vals_in;
-  int cur = -1, shift = 0;
+  int shifts[4], widths[4], shift = 0;
   for (int p = 0; p < passes; ++p) {
-    const int width = (nbits - shift + (passes - p) - 1) / (passes - p);
-    uint32_t* kout = (cur == 0) ? k1 : k0;
-    uint32_t* vout = (cur == 0) ? v1 : v0;
-    hipLaunchKernelGGL(rx_count, dim3(grid), dim3(kRThreads), 0, s, kin, n, shift, width,
-                       nchunks, per, counts);
-    hipLaunchKernelGGL(rx_scan, dim3(1u << width), dim3(kRThreads), 0, s, counts, nchunks,
-                       totals);
-    hipLaunchKernelGGL(rx_scatter, dim3(grid), dim3(kRThreads), 0, s, kin, vin, kout, vout, n,
-                       shift, width, nchunks, per, counts, totals);
-    kin = kout;
-    vin = vout;
-    cur = (cur == 0) ? 1 : 0;
-    shift += width;
+    widths[p] = (nbits - shift + (passes - p) - 1) / (passes - p);
+    shifts[p] = shift;
+    shift += widths[p];
   }
-  return cur;
+  return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, passes, shifts, widths, nullptr,
+                    counts, s);
+}
+
+int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
+                       uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
+                       const uint32_t* plan, uint32_t* counts, hipStream_t s) {
+  if (n <= 0) return 0;
+  return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, kPlanPasses, nullptr, nullptr, plan,
+                    counts, s);
 }
 
 }  // namespace nxs

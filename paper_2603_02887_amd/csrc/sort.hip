@@ -109,7 +109,8 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
     const uint32_t* __restrict__ sorted_slots, int64_t n, int32_t n_gauss, int n_views,
     const uint2* __restrict__ rect, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ local, const uint32_t* __restrict__ block_off,
-    uint32_t total, uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_val) {
+    const unsigned long long* __restrict__ total_dev, uint32_t capacity,
+    uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_val) {
   __shared__ uint32_t s_off[kScanChunk + 1];
   __shared__ uint32_t s_slot[kScanChunk];
   __shared__ uint32_t s_tile0[kScanChunk];   // global tile of the rectangle's first tile
@@ -117,6 +118,10 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
   const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
   const int cnt = (int)min((int64_t)kScanChunk, n - b0);
   const uint32_t out0 = block_off[blockIdx.x];
+  // the instance total comes from the projection's counters on the device, so
+  // the emission can be enqueued before the host has read it; writes beyond
+  // `capacity` are dropped (the host grows the buffers and emits again)
+  const uint32_t total = (uint32_t)min(*total_dev, 0xFFFFFFFFull);
   const uint32_t out1 = (b0 + kScanChunk < n) ? block_off[blockIdx.x + 1] : total;
   // loads first (all independent), then the LDS tables
   constexpr int kPerT = kScanChunk / kScanBlock;
@@ -167,8 +172,10 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
     uint32_t row = (uint32_t)((float)l * __frcp_rn((float)w));
     if (row * w > l) --row;
     if ((row + 1) * w <= l) ++row;
-    inst_tile[out0 + q] = s_tile0[lo] + row * tiles_x + (l - row * w);
-    inst_val[out0 + q] = s_slot[lo];
+    if (out0 + q < capacity) {
+      inst_tile[out0 + q] = s_tile0[lo] + row * tiles_x + (l - row * w);
+      inst_val[out0 + q] = s_slot[lo];
+    }
   }
 }
 
@@ -267,22 +274,28 @@ size_t scan_blocks_size(int64_t n) {
   return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1;
 }
 
-void launch_emit(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
-                 const ProjDev& proj, const ViewDev* views, uint32_t* scan_local,
-                 uint32_t* block_sums, uint32_t total, uint32_t* inst_tile,
-                 uint32_t* inst_val, hipStream_t s) {
+void launch_emit_scan(const uint32_t* sorted_slots, int64_t n_slots, const ProjDev& proj,
+                      uint32_t* scan_local, uint32_t* block_sums, hipStream_t s) {
   if (n_slots <= 0) return;
   const int nblocks = (int)((n_slots + kScanChunk - 1) / kScanChunk);
   hipLaunchKernelGGL(scan_local_kernel, dim3(nblocks), dim3(kScanBlock), 0, s,
                      sorted_slots, n_slots, proj.ntiles, scan_local, block_sums);
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanBlock), 0, s, block_sums,
                      nblocks);
+}
+
+void launch_emit_write(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
+                       const ProjDev& proj, const ViewDev* views, const uint32_t* scan_local,
+                       const uint32_t* block_sums, const unsigned long long* total_dev,
+                       uint32_t capacity, uint32_t* inst_tile, uint32_t* inst_val,
+                       hipStream_t s) {
+  if (n_slots <= 0) return;
+  const int nblocks = (int)((n_slots + kScanChunk - 1) / kScanChunk);
   const int n_views = (int)(n_slots / n_gauss);
   hipLaunchKernelGGL(emit_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, sorted_slots,
                      n_slots, n_gauss, n_views, proj.rect, views, scan_local, block_sums,
-                     total, inst_tile, inst_val);
+                     total_dev, capacity, inst_tile, inst_val);
 }
-
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {
   if (n <= 0) return;

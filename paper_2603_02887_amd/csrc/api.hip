@@ -28,7 +28,7 @@ struct nxs_context {
   std::string err;
   // workspace
   DevBuf views, counters, partials;
-  DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, ntiles, rect, prec;
+  DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, tinfo, nt_sorted, rect_sorted, prec;
   DevBuf scan_local, block_sums, counts;
   DevBuf inst_tile, inst_tile_alt, inst_val, inst_val_alt;
   DevBuf crec, ranges, pstate, gslot, order, queue;
@@ -208,7 +208,7 @@ nxs_status nxs_destroy(nxs_context* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   DevBuf* all[] = {&ctx->views,      &ctx->counters,      &ctx->partials,      &ctx->depth_key, &ctx->dsort_a, &ctx->dsort_b,
-                   &ctx->slot_a,     &ctx->slot_b,        &ctx->ntiles,    &ctx->rect,
+                   &ctx->slot_a,     &ctx->slot_b,        &ctx->tinfo,     &ctx->nt_sorted,     &ctx->rect_sorted,
                    &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
                    &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->crec,      &ctx->ranges,
@@ -324,12 +324,12 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   if ((st = ensure(ctx, ctx->depth_key, 4 * S)) || (st = ensure(ctx, ctx->dsort_a, 4 * S)) ||
       (st = ensure(ctx, ctx->dsort_b, 4 * S)) ||
       (st = ensure(ctx, ctx->slot_a, 4 * S)) || (st = ensure(ctx, ctx->slot_b, 4 * S)) ||
-      (st = ensure(ctx, ctx->ntiles, 4 * S)) || (st = ensure(ctx, ctx->rect, 8 * S)) ||
+      (st = ensure(ctx, ctx->tinfo, 16 * S)) || (st = ensure(ctx, ctx->nt_sorted, 4 * S)) ||
+      (st = ensure(ctx, ctx->rect_sorted, 8 * S)) ||
       (st = ensure(ctx, ctx->prec, 48 * S)) || (st = ensure(ctx, ctx->scan_local, 4 * S)) ||
       (st = ensure(ctx, ctx->block_sums, 4 * scan_blocks_size(S))))
     return st;
-  ProjDev proj{P<uint32_t>(ctx->depth_key), P<uint32_t>(ctx->ntiles), P<uint2>(ctx->rect),
-               P<float4>(ctx->prec)};
+  ProjDev proj{P<uint32_t>(ctx->depth_key), P<uint4>(ctx->tinfo), P<float4>(ctx->prec)};
   GaussDev gd{g->means, g->scales, g->quats, g->opacities, g->sh, g->n, g->sh_degree};
   Counters* dcount = P<Counters>(ctx->counters);
   const float kappa2 = (float)(2.0 * std::log(1.0 / (double)alpha_min));
@@ -355,20 +355,23 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   HIP_TRY(mark(2));
   launch_fill_u32(P<uint32_t>(ctx->ranges), 2 * total_tiles, 0u, s);
   // 1. depth sort of the slots (values: the slots 0..S-1)
+  //    (its last pass also lays out the slots' tile counts and rectangles in
+  //    that order, so that the emission reads them coalesced)
   const int wd = radix_sort_planned(P<uint32_t>(ctx->depth_key), nullptr,
                                     P<uint32_t>(ctx->dsort_a), P<uint32_t>(ctx->slot_a),
                                     P<uint32_t>(ctx->dsort_b), P<uint32_t>(ctx->slot_b), S,
-                                    dcount->plan, P<uint32_t>(ctx->counts), s);
+                                    dcount->plan, P<uint32_t>(ctx->counts), proj.tinfo,
+                                    P<uint32_t>(ctx->nt_sorted), P<uint2>(ctx->rect_sorted), s);
   uint32_t* sorted_slots = wd ? P<uint32_t>(ctx->slot_b) : P<uint32_t>(ctx->slot_a);
   HIP_TRY(mark(3));
   // 2. emission in depth order, into the buffers as they are
-  launch_emit_scan(sorted_slots, S, proj, P<uint32_t>(ctx->scan_local),
+  launch_emit_scan(P<uint32_t>(ctx->nt_sorted), S, P<uint32_t>(ctx->scan_local),
                    P<uint32_t>(ctx->block_sums), s);
   const size_t cap = std::min(ctx->inst_tile.cap, ctx->inst_val.cap) / 4;
   const uint32_t cap32 = (uint32_t)std::min<size_t>(cap, 0xFFFFFFFFu);
   if (cap32 > 0)
-    launch_emit_write(sorted_slots, S, g->n, proj, dviews, P<uint32_t>(ctx->scan_local),
-                      P<uint32_t>(ctx->block_sums), &dcount->total, cap32,
+    launch_emit_write(sorted_slots, P<uint2>(ctx->rect_sorted), S, g->n, dviews,
+                      P<uint32_t>(ctx->scan_local), P<uint32_t>(ctx->block_sums), cap32,
                       P<uint32_t>(ctx->inst_tile), P<uint32_t>(ctx->inst_val), s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventSynchronize(ctx->counted));
@@ -391,9 +394,9 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   uint32_t* inst_tile = P<uint32_t>(ctx->inst_tile);
   uint32_t* inst_val = P<uint32_t>(ctx->inst_val);
   if (M > cap32)   // the emission above did not fit: emit again into the grown buffers
-    launch_emit_write(sorted_slots, S, g->n, proj, dviews, P<uint32_t>(ctx->scan_local),
-                      P<uint32_t>(ctx->block_sums), &dcount->total, (uint32_t)M, inst_tile,
-                      inst_val, s);
+    launch_emit_write(sorted_slots, P<uint2>(ctx->rect_sorted), S, g->n, dviews,
+                      P<uint32_t>(ctx->scan_local), P<uint32_t>(ctx->block_sums), (uint32_t)M,
+                      inst_tile, inst_val, s);
   HIP_TRY(mark(4));
   if (M > 0) {
     // 3. stable sort by global tile
@@ -584,7 +587,7 @@ nxs_status nxs_release_workspace(nxs_context* ctx) {
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipDeviceSynchronize());
   DevBuf* all[] = {&ctx->views,      &ctx->counters,      &ctx->partials,      &ctx->depth_key, &ctx->dsort_a, &ctx->dsort_b,
-                   &ctx->slot_a,     &ctx->slot_b,        &ctx->ntiles,    &ctx->rect,
+                   &ctx->slot_a,     &ctx->slot_b,        &ctx->tinfo,     &ctx->nt_sorted,     &ctx->rect_sorted,
                    &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
                    &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->crec,      &ctx->ranges,
@@ -675,10 +678,11 @@ nxs_status nxs_inspect_projection(nxs_context* ctx, int32_t view, uint32_t* dept
   if (n == 0) return NXS_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipEventSynchronize(ctx->done));
-  std::vector<uint2> rect(n);
+  std::vector<uint4> rect(n);
   HIP_TRY(hipMemcpy(depth_bits_host, (uint32_t*)ctx->depth_key.p + view * n, 4 * n,
                     hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(rect.data(), (uint2*)ctx->rect.p + view * n, 8 * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(rect.data(), (uint4*)ctx->tinfo.p + view * n, 16 * n,
+                    hipMemcpyDeviceToHost));
   for (int64_t i = 0; i < n; ++i) {
     if (rect[i].x == 0xFFFFFFFFu) {
       depth_bits_host[i] = 0;

@@ -39,8 +39,9 @@ struct GaussDev {
 // Per projected slot (slot = view * n + gaussian) arrays written by the projection.
 struct ProjDev {
   uint32_t* depth_key;      // float32 depth bits; 0xFFFFFFFF when culled
-  uint32_t* ntiles;         // covered tiles, 0 when culled
-  uint2* rect;              // (tx0 | tx1 << 16, ty0 | ty1 << 16)
+  // tile record (tx0 | tx1 << 16, ty0 | ty1 << 16, covered tiles, 0); the
+  // rectangle is all ones and the count 0 when culled
+  uint4* tinfo;
   // 3 float4 per slot:
   //   (u_hi, u_lo, v_hi, v_lo)  image-plane centre as float hi + lo parts
   //   (A', B', C', log2 aleph)  log2(alpha) = log2 aleph + A' dx^2 + B' dx dy + C' dy^2
@@ -76,9 +77,12 @@ size_t radix_counts_words(int64_t n);
 // width << 8 for kPlanPasses passes (a pass of width 0 copies).  Enough for
 // keys of up to 32 varying bits.
 constexpr int kPlanPasses = 4;
+// Its last pass also writes, in sorted order, each value's tile count and
+// rectangle from `tinfo` (indexed by value) into nt_out / rect_out.
 int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
                        uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
-                       const uint32_t* plan, uint32_t* counts, hipStream_t s);
+                       const uint32_t* plan, uint32_t* counts, const uint4* tinfo,
+                       uint32_t* nt_out, uint2* rect_out, hipStream_t s);
 int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
                hipStream_t s);
@@ -86,15 +90,17 @@ int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
 
 // Exclusive scan of ntiles in sorted-slot order and emission of instances.
 size_t scan_blocks_size(int64_t n);
-void launch_emit_scan(const uint32_t* sorted_slots, int64_t n_slots, const ProjDev& proj,
-                      uint32_t* scan_local, uint32_t* block_sums, hipStream_t s);
-// Writes the instances of the depth-sorted slots; the total is read from
-// `total_dev`; instances at positions >= capacity are not written.
-void launch_emit_write(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
-                       const ProjDev& proj, const ViewDev* views, const uint32_t* scan_local,
-                       const uint32_t* block_sums, const unsigned long long* total_dev,
-                       uint32_t capacity, uint32_t* inst_tile, uint32_t* inst_val,
-                       hipStream_t s);
+// Exclusive scan of the depth-sorted tile counts, per block of 1,024 slots
+// (block totals in block_sums; scanned across blocks here only when there
+// are more blocks than the emission sums itself).
+void launch_emit_scan(const uint32_t* nt_sorted, int64_t n_slots, uint32_t* scan_local,
+                      uint32_t* block_sums, hipStream_t s);
+// Writes the instances of the depth-sorted slots (rectangles in rect_sorted);
+// instances at positions >= capacity are not written.
+void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted, int64_t n_slots,
+                       int32_t n_gauss, const ViewDev* views, const uint32_t* scan_local,
+                       const uint32_t* block_sums, uint32_t capacity, uint32_t* inst_tile,
+                       uint32_t* inst_val, hipStream_t s);
 
 
 

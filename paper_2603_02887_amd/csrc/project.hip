@@ -301,8 +301,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
       rec[2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(hx | (hy << 16)));
     }
     out.depth_key[slot] = kg.depth_bits;
-    out.ntiles[slot] = nt;
-    out.rect[slot] = rect;
+    out.tinfo[slot] = make_uint4(rect.x, rect.y, nt, 0u);
     nt_sum += nt;
   }
   // block reductions: instance total and visible depth-bit range

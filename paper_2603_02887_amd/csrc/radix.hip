@@ -153,7 +153,9 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n, int shift,
     int width, const uint32_t* __restrict__ plan, int pass, uint32_t nchunks, uint32_t per,
-    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals) {
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
+    const uint4* __restrict__ tinfo, uint32_t* __restrict__ nt_out,
+    uint2* __restrict__ rect_out) {
   __shared__ uint32_t s_key[kRChunk];
   __shared__ uint32_t s_val[kRChunk];
   __shared__ uint32_t s_wave[kRWaves][kRBins];
@@ -238,6 +240,11 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     const uint32_t g = s_gbase[d] + (uint32_t)i - s_lbase[d];
     keys_out[g] = k;
     vals_out[g] = s_val[i];
+    if (tinfo) {   // the slot's tile record, now in sorted order
+      const uint4 ti = tinfo[s_val[i]];
+      nt_out[g] = ti.z;
+      rect_out[g] = make_uint2(ti.x, ti.y);
+    }
   }
 }
 
@@ -252,7 +259,8 @@ namespace {
 
 int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int passes, const int* shifts,
-               const int* widths, const uint32_t* plan, uint32_t* counts, hipStream_t s) {
+               const int* widths, const uint32_t* plan, uint32_t* counts, const uint4* tinfo,
+               uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
   const uint32_t nchunks = (uint32_t)((n + kRChunk - 1) / kRChunk);
   const uint32_t per = (nchunks + kRXcds - 1) / kRXcds;
   const unsigned grid = per * kRXcds;
@@ -268,8 +276,10 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
                        p, nchunks, per, counts);
     hipLaunchKernelGGL(rx_scan, dim3(plan ? kRBins : (1u << width)), dim3(kRThreads), 0, s,
                        counts, nchunks, totals, plan, p);
+    const bool last = p == passes - 1;
     hipLaunchKernelGGL(rx_scatter, dim3(grid), dim3(kRThreads), 0, s, kin, vin, kout, vout, n,
-                       shift, width, plan, p, nchunks, per, counts, totals);
+                       shift, width, plan, p, nchunks, per, counts, totals,
+                       last ? tinfo : nullptr, nt_out, rect_out);
     kin = kout;
     vin = vout;
     cur = (cur == 0) ? 1 : 0;
@@ -292,15 +302,16 @@ int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
     shift += widths[p];
   }
   return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, passes, shifts, widths, nullptr,
-                    counts, s);
+                    counts, nullptr, nullptr, nullptr, s);
 }
 
 int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
                        uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
-                       const uint32_t* plan, uint32_t* counts, hipStream_t s) {
+                       const uint32_t* plan, uint32_t* counts, const uint4* tinfo,
+                       uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
   if (n <= 0) return 0;
   return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, kPlanPasses, nullptr, nullptr, plan,
-                    counts, s);
+                    counts, tinfo, nt_out, rect_out, s);
 }
 
 }  // namespace nxs

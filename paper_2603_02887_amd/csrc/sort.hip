@@ -53,8 +53,7 @@ constexpr int kScanChunk = kScanBlock * kScanItems;
 
 // Block-local exclusive scan of ntiles in sorted-slot order.
 __global__ __launch_bounds__(kScanBlock) void scan_local_kernel(
-    const uint32_t* __restrict__ sorted_slots, int64_t n,
-    const uint32_t* __restrict__ ntiles, uint32_t* __restrict__ local,
+    const uint32_t* __restrict__ nt_sorted, int64_t n, uint32_t* __restrict__ local,
     uint32_t* __restrict__ block_sums) {
   __shared__ uint32_t s_tmp[kScanBlock / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
@@ -62,7 +61,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_local_kernel(
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     int64_t i = base + k;
-    v[k] = i < n ? ntiles[sorted_slots[i]] : 0u;
+    v[k] = i < n ? nt_sorted[i] : 0u;
     sum += v[k];
   }
   uint32_t tot;
@@ -73,7 +72,10 @@ __global__ __launch_bounds__(kScanBlock) void scan_local_kernel(
     if (i < n) local[i] = ex;
     ex += v[k];
   }
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+  if (threadIdx.x == 0) {
+    block_sums[blockIdx.x] = tot;                 // scanned later if needed
+    block_sums[gridDim.x + blockIdx.x] = tot;     // kept as is
+  }
 }
 
 // Single work-group exclusive scan of the block sums (in place).
@@ -105,24 +107,36 @@ __global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(uint32_t* __res
 // contiguous run: each output position finds its slot by binary search over
 // the block's offsets in LDS, so consecutive threads write consecutive
 // addresses however unevenly the Gaussians' tile counts are spread.
+// Blocks up to this count find their output offset by summing the totals of
+// the blocks before them (no separate scan launch); beyond it the totals are
+// scanned by scan_blocks_kernel first.
+constexpr int kInlineBlocks = 2048;
+
 __global__ __launch_bounds__(kScanBlock) void emit_kernel(
-    const uint32_t* __restrict__ sorted_slots, int64_t n, int32_t n_gauss, int n_views,
-    const uint2* __restrict__ rect, const ViewDev* __restrict__ views,
-    const uint32_t* __restrict__ local, const uint32_t* __restrict__ block_off,
-    const unsigned long long* __restrict__ total_dev, uint32_t capacity,
-    uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_val) {
+    const uint32_t* __restrict__ sorted_slots, const uint2* __restrict__ rect_sorted, int64_t n,
+    int32_t n_gauss, int n_views, const ViewDev* __restrict__ views,
+    const uint32_t* __restrict__ local, const uint32_t* __restrict__ block_sums, int nblocks,
+    uint32_t capacity, uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_val) {
   __shared__ uint32_t s_off[kScanChunk + 1];
   __shared__ uint32_t s_slot[kScanChunk];
   __shared__ uint32_t s_tile0[kScanChunk];   // global tile of the rectangle's first tile
   __shared__ uint32_t s_geom[kScanChunk];    // width | tiles_x << 16
+  __shared__ uint32_t s_tmp[kScanBlock / 64];
   const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
   const int cnt = (int)min((int64_t)kScanChunk, n - b0);
-  const uint32_t out0 = block_off[blockIdx.x];
-  // the instance total comes from the projection's counters on the device, so
-  // the emission can be enqueued before the host has read it; writes beyond
-  // `capacity` are dropped (the host grows the buffers and emits again)
-  const uint32_t total = (uint32_t)min(*total_dev, 0xFFFFFFFFull);
-  const uint32_t out1 = (b0 + kScanChunk < n) ? block_off[blockIdx.x + 1] : total;
+  uint32_t out0;
+  if (nblocks <= kInlineBlocks) {
+    // the sum of the totals of the blocks before this one
+    uint32_t part = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBlock) part += block_sums[b];
+    uint32_t all;
+    (void)block_exclusive_scan(part, s_tmp, &all);
+    out0 = all;
+  } else {
+    out0 = block_sums[blockIdx.x];   // scanned in place
+  }
+  const uint32_t out1 = out0 + (nblocks <= kInlineBlocks ? block_sums[blockIdx.x]
+                                                         : block_sums[nblocks + blockIdx.x]);
   // loads first (all independent), then the LDS tables
   constexpr int kPerT = kScanChunk / kScanBlock;
   uint32_t slot_r[kPerT], off_r[kPerT];
@@ -136,7 +150,7 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
 #pragma unroll
   for (int q = 0; q < kPerT; ++q) {
     const int k = q * kScanBlock + threadIdx.x;
-    rect_r[q] = k < cnt ? rect[slot_r[q]] : make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+    rect_r[q] = k < cnt ? rect_sorted[b0 + k] : make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
   }
 #pragma unroll
   for (int q = 0; q < kPerT; ++q) {
@@ -271,30 +285,30 @@ __global__ __launch_bounds__(256) void ranges_gather_kernel(
 }  // namespace
 
 size_t scan_blocks_size(int64_t n) {
-  return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1;
+  return 2 * (size_t)((n + kScanChunk - 1) / kScanChunk) + 1;
 }
 
-void launch_emit_scan(const uint32_t* sorted_slots, int64_t n_slots, const ProjDev& proj,
-                      uint32_t* scan_local, uint32_t* block_sums, hipStream_t s) {
+void launch_emit_scan(const uint32_t* nt_sorted, int64_t n_slots, uint32_t* scan_local,
+                      uint32_t* block_sums, hipStream_t s) {
   if (n_slots <= 0) return;
   const int nblocks = (int)((n_slots + kScanChunk - 1) / kScanChunk);
-  hipLaunchKernelGGL(scan_local_kernel, dim3(nblocks), dim3(kScanBlock), 0, s,
-                     sorted_slots, n_slots, proj.ntiles, scan_local, block_sums);
-  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanBlock), 0, s, block_sums,
-                     nblocks);
+  hipLaunchKernelGGL(scan_local_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, nt_sorted,
+                     n_slots, scan_local, block_sums);
+  if (nblocks > kInlineBlocks)
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanBlock), 0, s, block_sums,
+                       nblocks);
 }
 
-void launch_emit_write(const uint32_t* sorted_slots, int64_t n_slots, int32_t n_gauss,
-                       const ProjDev& proj, const ViewDev* views, const uint32_t* scan_local,
-                       const uint32_t* block_sums, const unsigned long long* total_dev,
-                       uint32_t capacity, uint32_t* inst_tile, uint32_t* inst_val,
-                       hipStream_t s) {
+void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted, int64_t n_slots,
+                       int32_t n_gauss, const ViewDev* views, const uint32_t* scan_local,
+                       const uint32_t* block_sums, uint32_t capacity, uint32_t* inst_tile,
+                       uint32_t* inst_val, hipStream_t s) {
   if (n_slots <= 0) return;
   const int nblocks = (int)((n_slots + kScanChunk - 1) / kScanChunk);
   const int n_views = (int)(n_slots / n_gauss);
   hipLaunchKernelGGL(emit_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, sorted_slots,
-                     n_slots, n_gauss, n_views, proj.rect, views, scan_local, block_sums,
-                     total_dev, capacity, inst_tile, inst_val);
+                     rect_sorted, n_slots, n_gauss, n_views, views, scan_local, block_sums,
+                     nblocks, capacity, inst_tile, inst_val);
 }
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {

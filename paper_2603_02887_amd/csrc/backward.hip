@@ -31,10 +31,23 @@ namespace {
 
 constexpr float kL2e = 1.4426950408889634f;
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+// Sum over the 64 lanes with DPP moves (VALU only, no LDS): pairs, quads,
+// half-rows and rows by quad_perm / mirror patterns, then rows 1 and 3 take
+// row_bcast:15 and rows 2 and 3 take row_bcast:31; lane 63 ends with the total.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF,
+                                            ROW_MASK == 0xF);
+  return x + __int_as_float(y);
+}
+__device__ __forceinline__ float wave_total(float x) {
+  x = dpp_add<0xB1, 0xF>(x);    // quad_perm [1,0,3,2]
+  x = dpp_add<0x4E, 0xF>(x);    // quad_perm [2,3,0,1]
+  x = dpp_add<0x141, 0xF>(x);   // row_half_mirror
+  x = dpp_add<0x140, 0xF>(x);   // row_mirror
+  x = dpp_add<0x142, 0xA>(x);   // row_bcast:15 into rows 1, 3
+  x = dpp_add<0x143, 0xC>(x);   // row_bcast:31 into rows 2, 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 template <int MODEL, int TW, int TH>
@@ -161,27 +174,14 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
         }
       }
       if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
-        d_op = wave_sum(d_op);
-        d_u = wave_sum(d_u);
-        d_v = wave_sum(d_v);
-        d_A = wave_sum(d_A);
-        d_B = wave_sum(d_B);
-        d_C = wave_sum(d_C);
-        d_r = wave_sum(d_r);
-        d_g = wave_sum(d_g);
-        d_b = wave_sum(d_b);
-        if (lane == 0) {
-          float* gs = gslot + 9 * (size_t)__float_as_uint(r[10]);
-          atomicAdd(gs + 0, d_op);
-          atomicAdd(gs + 1, d_u);
-          atomicAdd(gs + 2, d_v);
-          atomicAdd(gs + 3, d_A);
-          atomicAdd(gs + 4, d_B);
-          atomicAdd(gs + 5, d_C);
-          atomicAdd(gs + 6, d_r);
-          atomicAdd(gs + 7, d_g);
-          atomicAdd(gs + 8, d_b);
-        }
+        // the wave's sums, then one 9-lane atomic: lane f adds field f
+        const float t[9] = {wave_total(d_op), wave_total(d_u), wave_total(d_v),
+                            wave_total(d_A),  wave_total(d_B), wave_total(d_C),
+                            wave_total(d_r),  wave_total(d_g), wave_total(d_b)};
+        float mine = 0.0f;
+#pragma unroll
+        for (int f = 0; f < 9; ++f) mine = lane == f ? t[f] : mine;
+        if (lane < 9) atomicAdd(gslot + 9 * (size_t)__float_as_uint(r[10]) + lane, mine);
       }
       all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
     }

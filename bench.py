@@ -7,8 +7,8 @@ Workload: 1,000,000 Gaussians drawn from 64 anisotropic clusters, SH degree 3,
 one 1920x1080 pinhole camera, 16x16 tiles.  One step renders that frame once
 with each transmittance model (exponential, linear, quadratic sublinear,
 quadratic superlinear): the whole path (projection, depth sort, binning, tile
-sort, gather, composite) runs for every render.  The scene is uploaded to HBM
-before the timed region.
+sort, tile ranges, composite with its gather) runs for every render.  The
+scene is uploaded to HBM before the timed region.
 
 The timed steps enqueue their renders back to back on one stream (a caller
 that pipelines renders); `value` is the frame's pixels over that time.

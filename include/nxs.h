@@ -7,8 +7,9 @@
  * formation of Sec. 4 of "Generalized non-exponential Gaussian splatting"
  * (eq. generalized_gaussian with the discrete extinction of eq. nexp_p and
  * the operators of Table 1).  Each call runs, on the caller's HIP stream:
- * EWA projection, depth sort, tile binning, a stable tile sort, a gather of
- * each tile's splats into contiguous order, and a per-tile composite.
+ * EWA projection, depth sort, tile binning, a stable tile sort, tile ranges,
+ * and a per-tile composite that gathers each tile's splats in sorted order
+ * batch by batch into on-chip memory.
  *
  * Conventions common to every entry point
  *   - Array pointers are DEVICE pointers of the context's device, unless the
@@ -292,7 +293,7 @@ const char* nxs_last_error(const nxs_context* ctx);
  * on its stream between its stages; nxs_inspect_stage_times then returns the
  * milliseconds of the last render's stages, in this order:
  *   0 projection, 1 depth sort, 2 instance emission, 3 tile sort,
- *   4 tile ranges + gather, 5 composite.
+ *   4 tile ranges, 5 composite (with the gather of the splats it reaches).
  * ms_host has n >= NXS_N_STAGES entries.  Waits for the last render. */
 #define NXS_N_STAGES 6
 nxs_status nxs_set_timing(nxs_context* ctx, int32_t enable);

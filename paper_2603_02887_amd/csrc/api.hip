@@ -31,7 +31,7 @@ struct nxs_context {
   DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, tinfo, nt_sorted, rect_sorted, prec;
   DevBuf scan_local, block_sums, counts;
   DevBuf inst_tile, inst_tile_alt, inst_val, inst_val_alt;
-  DevBuf crec, ranges, pstate, gslot, order, queue;
+  DevBuf ranges, pstate, gslot, order, queue;
   int n_cu = 256;
   std::string arch;
   size_t ws_limit = 0;   // 0: no limit on the workspace
@@ -211,7 +211,7 @@ nxs_status nxs_destroy(nxs_context* ctx) {
                    &ctx->slot_a,     &ctx->slot_b,        &ctx->tinfo,     &ctx->nt_sorted,     &ctx->rect_sorted,
                    &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
-                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->crec,      &ctx->ranges,
+                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->ranges,
                    &ctx->pstate,     &ctx->gslot,         &ctx->order,     &ctx->queue};
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
@@ -388,8 +388,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   const int tbits = bit_length((uint64_t)(total_tiles - 1));
   if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_words(std::max<int64_t>(S, M)))) ||
       (st = ensure(ctx, ctx->inst_tile, 4 * M)) || (st = ensure(ctx, ctx->inst_tile_alt, 4 * M)) ||
-      (st = ensure(ctx, ctx->inst_val, 4 * M)) || (st = ensure(ctx, ctx->inst_val_alt, 4 * M)) ||
-      (st = ensure(ctx, ctx->crec, 48 * M)))
+      (st = ensure(ctx, ctx->inst_val, 4 * M)) || (st = ensure(ctx, ctx->inst_val_alt, 4 * M)))
     return st;
   uint32_t* inst_tile = P<uint32_t>(ctx->inst_tile);
   uint32_t* inst_val = P<uint32_t>(ctx->inst_val);
@@ -408,10 +407,8 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
       inst_val = P<uint32_t>(ctx->inst_val_alt);
     }
     HIP_TRY(mark(5));
-    // 4. ranges and gather
-    launch_ranges_gather(inst_tile, inst_val, (int64_t)M, proj, dviews, n_views, tw, th,
-                         (float)std::log2((double)alpha_min), P<uint2>(ctx->ranges),
-                         P<float4>(ctx->crec), s);
+    // 4. tile ranges
+    launch_ranges(inst_tile, (int64_t)M, P<uint2>(ctx->ranges), s);
   } else {
     HIP_TRY(mark(5));
   }
@@ -432,8 +429,9 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   cp.param = param;
   for (int k = 0; k < 3; ++k) cp.bg[k] = opts->background[k];
   cp.lds_batch = batch;
+  // (the composite gathers the records of the sorted slots batch by batch)
   CompositeLaunch cl{sched, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),
-                     P<float4>(ctx->crec), nullptr, nullptr, ctx->n_cu};
+                     inst_val, proj.rec, nullptr, nullptr, ctx->n_cu};
   if (sched == NXS_SCHED_QUEUE) {
     if ((st = ensure(ctx, ctx->order, 4 * (size_t)total_tiles))) return st;
     if ((st = ensure(ctx, ctx->queue, 4))) return st;
@@ -499,7 +497,8 @@ nxs_status nxs_render_backward(nxs_context* ctx, const float* const* dL_drgb,
   launch_fill_u32(P<uint32_t>(ctx->gslot), 9 * S, 0u, s);
   launch_composite_bwd(ctx->bwd_model, ctx->bwd_tw, ctx->bwd_th, ctx->last_tiles,
                        P<ViewDev>(ctx->views), n_views, P<uint2>(ctx->ranges),
-                       P<float4>(ctx->crec), ctx->bwd_cp, P<float4>(ctx->pstate),
+                       ctx->last_inst_val, P<float4>(ctx->prec), ctx->bwd_cp,
+                       P<float4>(ctx->pstate),
                        P<float>(ctx->gslot), s);
   GaussDev gd{g.means, g.scales, g.quats, g.opacities, g.sh, g.n, g.sh_degree};
   GaussGradDev gg{grads->means, grads->scales, grads->quats, grads->opacities, grads->sh};
@@ -590,7 +589,7 @@ nxs_status nxs_release_workspace(nxs_context* ctx) {
                    &ctx->slot_a,     &ctx->slot_b,        &ctx->tinfo,     &ctx->nt_sorted,     &ctx->rect_sorted,
                    &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
-                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->crec,      &ctx->ranges,
+                   &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->ranges,
                    &ctx->pstate,     &ctx->gslot,         &ctx->order,     &ctx->queue};
   for (DevBuf* b : all) {
     if (b->p) HIP_TRY(hipFree(b->p));
@@ -625,7 +624,7 @@ nxs_status nxs_inspect_stage_times(nxs_context* ctx, float* ms_host, int32_t n) 
   if (!ctx->ev_valid) return fail(ctx, NXS_EINVAL, "no timed render on this context");
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipEventSynchronize(ctx->ev[7]));
-  // project, depth sort (incl. ranges clear), emit, tile sort, gather, composite
+  // project, depth sort (incl. ranges clear), emit, tile sort, ranges, composite
   const int from[NXS_N_STAGES] = {0, 2, 3, 4, 5, 6};
   const int to[NXS_N_STAGES] = {1, 3, 4, 5, 6, 7};
   for (int k = 0; k < NXS_N_STAGES; ++k)

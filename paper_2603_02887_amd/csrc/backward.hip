@@ -1,8 +1,8 @@
 // Path-replay backward of the render (models 0..4) and of the projection.
 //
 // composite_bwd: each wave re-walks its 8x8 block's splats front to back
-// exactly as the forward did (same records, same order, same float32
-// decisions), rebuilding each pixel's state from the start instead of
+// exactly as the forward did (the same records staged in LDS in the same
+// order, the same float32 decisions), rebuilding each pixel's state from the start instead of
 // storing anything per splat.  The adjoint of every composited splat comes
 // from quantities the forward left per pixel:
 //   exponential   dL/dalpha_i = T_i E_i - R_{i+1} / (1 - alpha_i), with the
@@ -24,6 +24,7 @@
 // Jacobian, the rotation and scales, and the SH emission.
 #include "nxs_internal.h"
 #include "nxs_ops.h"
+#include "nxs_stage.h"
 
 namespace nxs {
 
@@ -53,9 +54,12 @@ __device__ __forceinline__ float wave_total(float x) {
 template <int MODEL, int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const float4* __restrict__ crec, CompositeParams prm,
-    const float4* __restrict__ pstate, float* __restrict__ gslot) {
-  const uint32_t tile = blockIdx.x;
+    const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
+    const float4* __restrict__ pstate, float* __restrict__ gslot, uint32_t n_tiles,
+    uint32_t per_xcd) {
+  __shared__ float4 stage[(TW / 8) * (TH / 8) * kStageF4];
+  const uint32_t tile = xcd_banded(blockIdx.x, per_xcd);
+  if (tile >= n_tiles) return;
   int vi = 0;
   {
     int lo = 0, hi = n_views - 1;
@@ -75,7 +79,8 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
   const int px = tx * TW + lx, py = ty * TH + ly;
   const bool inside = px < v.width && py < v.height;
   const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
-  const uint32_t wbit = 1u << wid;
+  const StageBlock sb = stage_block<TW>(tx, ty, TH, wid, prm.log2_alpha_min);
+  float4* wlds = stage + wid * kStageF4;
   const uint2 rg = ranges[tile];
   const float amin = prm.log2_alpha_min;
   const float t_eps = prm.t_eps;
@@ -108,18 +113,12 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
 
   Op<MODEL> op;
   bool done = !inside;
-  const float* crf = reinterpret_cast<const float*>(crec);
   bool all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
   for (uint32_t base = rg.x; base < rg.y && !all_done; base += 64) {
-    const uint32_t j = base + (uint32_t)lane;
-    const uint32_t bits = j < rg.y ? __float_as_uint(crf[12 * (size_t)j + 9]) : 0u;
-    uint64_t rel = __builtin_amdgcn_ballot_w64((bits & wbit) != 0);
-    while (rel != 0 && !all_done) {
-      const uint32_t k = base + (uint32_t)__builtin_ctzll(rel);
-      rel &= rel - 1;
-      float r[11];
-#pragma unroll
-      for (int f = 0; f < 11; ++f) r[f] = crf[12 * (size_t)k + f];
+    const uint32_t n = stage_batch(inst_val, rec, base, rg.y, sb, wlds, lane);
+    for (uint32_t k = 0; k < n && !all_done; ++k) {
+      const float4 q0 = wlds[3 * k + 0], q1 = wlds[3 * k + 1], q2 = wlds[3 * k + 2];
+      const float r[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y};
       float d_op = 0.f, d_u = 0.f, d_v = 0.f, d_A = 0.f, d_B = 0.f, d_C = 0.f;
       float d_r = 0.f, d_g = 0.f, d_b = 0.f;
       bool contrib = false;
@@ -181,7 +180,7 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
         float mine = 0.0f;
 #pragma unroll
         for (int f = 0; f < 9; ++f) mine = lane == f ? t[f] : mine;
-        if (lane < 9) atomicAdd(gslot + 9 * (size_t)__float_as_uint(r[10]) + lane, mine);
+        if (lane < 9) atomicAdd(gslot + 9 * (size_t)__float_as_uint(r[9]) + lane, mine);
       }
       all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
     }
@@ -409,37 +408,41 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
 
 template <int MODEL, int TW, int TH>
 void bwd_t(int64_t n_tiles, const ViewDev* views, int n_views, const uint2* ranges,
-           const float4* crec, const CompositeParams& p, const float4* pstate, float* gslot,
-           hipStream_t s) {
-  hipLaunchKernelGGL((composite_bwd_kernel<MODEL, TW, TH>), dim3((unsigned)n_tiles),
-                     dim3(TW * TH), 0, s, views, n_views, ranges, crec, p, pstate, gslot);
+           const uint32_t* inst_val, const float4* rec, const CompositeParams& p,
+           const float4* pstate, float* gslot, hipStream_t s) {
+  const uint32_t per = (uint32_t)((n_tiles + 7) / 8);
+  hipLaunchKernelGGL((composite_bwd_kernel<MODEL, TW, TH>), dim3(per * 8), dim3(TW * TH), 0, s,
+                     views, n_views, ranges, inst_val, rec, p, pstate, gslot,
+                     (uint32_t)n_tiles, per);
 }
 
 template <int MODEL>
 void bwd_m(int tile_w, int tile_h, int64_t n_tiles, const ViewDev* views, int n_views,
-           const uint2* ranges, const float4* crec, const CompositeParams& p,
-           const float4* pstate, float* gslot, hipStream_t s) {
+           const uint2* ranges, const uint32_t* inst_val, const float4* rec,
+           const CompositeParams& p, const float4* pstate, float* gslot, hipStream_t s) {
   if (tile_w == 8 && tile_h == 8)
-    bwd_t<MODEL, 8, 8>(n_tiles, views, n_views, ranges, crec, p, pstate, gslot, s);
+    bwd_t<MODEL, 8, 8>(n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, gslot, s);
   else if (tile_w == 32 && tile_h == 8)
-    bwd_t<MODEL, 32, 8>(n_tiles, views, n_views, ranges, crec, p, pstate, gslot, s);
+    bwd_t<MODEL, 32, 8>(n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, gslot, s);
   else
-    bwd_t<MODEL, 16, 16>(n_tiles, views, n_views, ranges, crec, p, pstate, gslot, s);
+    bwd_t<MODEL, 16, 16>(n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, gslot, s);
 }
 
 }  // namespace
 
 void launch_composite_bwd(int model, int tile_w, int tile_h, int64_t n_tiles,
                           const ViewDev* views, int n_views, const uint2* ranges,
-                          const float4* crec, const CompositeParams& p,
+                          const uint32_t* inst_val, const float4* rec, const CompositeParams& p,
                           const float4* pstate, float* gslot, hipStream_t s) {
   if (n_tiles <= 0) return;
   switch (model) {
-    case 0: bwd_m<0>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, pstate, gslot, s); break;
-    case 1: bwd_m<1>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, pstate, gslot, s); break;
-    case 2: bwd_m<2>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, pstate, gslot, s); break;
-    case 3: bwd_m<3>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, pstate, gslot, s); break;
-    case 4: bwd_m<4>(tile_w, tile_h, n_tiles, views, n_views, ranges, crec, p, pstate, gslot, s); break;
+#define NXS_B(M)                                                                        \
+  case M:                                                                               \
+    bwd_m<M>(tile_w, tile_h, n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, \
+             gslot, s);                                                                 \
+    break;
+    NXS_B(0) NXS_B(1) NXS_B(2) NXS_B(3) NXS_B(4)
+#undef NXS_B
     default: break;
   }
 }

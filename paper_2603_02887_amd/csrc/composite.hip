@@ -1,12 +1,14 @@
 // Per-tile front-to-back composite with a pluggable transmittance operator.
 //
-// One work-group per screen tile, one thread per pixel; each wave owns an
-// 8x8 pixel block of the tile and runs on its own (no LDS, no barriers).
-// The tile's splats, gathered into depth order and contiguous in HBM, are
-// the same for every lane of a wave, so they are read with scalar loads into
-// SGPRs: no per-lane copies, no LDS bandwidth.  A splat whose footprint box
-// misses the wave's block (one bit of its record) is skipped by a scalar
-// branch.  Per pixel (Sec. 4, eq. generalized_gaussian and eq. nexp_p):
+// One wave per 8x8 pixel block of a screen tile, one lane per pixel; waves
+// run on their own (no barriers).  The tile's sorted list holds projected
+// slots: a wave walks it in batches of 64, each lane fetching one slot's
+// record and testing whether its footprint reaches the wave's block; the
+// records that do are written in order to the wave's LDS (the gather to
+// sorted order, done only for the part of the list the wave reaches before
+// its pixels stop).  Each staged splat is then read by the whole wave with
+// broadcast LDS reads.  Per pixel (Sec. 4, eq. generalized_gaussian and
+// eq. nexp_p):
 //   alpha = aleph exp(-q/2), evaluated as exp2 of a precomputed quadratic;
 //   splats with alpha < alpha_min are skipped;
 //   p = alpha * T                (exponential, T <- T (1 - alpha))
@@ -26,8 +28,10 @@
 //                block from a global atomic queue over all views' tiles, in
 //                an order with the longest tile lists first (their blocks
 //                start early instead of forming the tail).
+// The first two give each XCD a contiguous band of tiles.
 #include "nxs_internal.h"
 #include "nxs_ops.h"
+#include "nxs_stage.h"
 
 #include <algorithm>
 
@@ -39,8 +43,9 @@ namespace {
 template <int MODEL, int TW, int TH, bool STATE>
 __device__ __forceinline__ void composite_block(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const float4* __restrict__ crec, const CompositeParams& prm, float4* __restrict__ pstate,
-    uint32_t tile, int wid, int lane) {
+    const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec,
+    const CompositeParams& prm, float4* __restrict__ pstate, float4* wlds, uint32_t tile,
+    int wid, int lane) {
   static_assert(TW % 8 == 0 && TH % 8 == 0, "waves cover 8x8 blocks");
   int vi = 0;
   {
@@ -59,7 +64,7 @@ __device__ __forceinline__ void composite_block(
   const int px = tx * TW + lx, py = ty * TH + ly;
   const bool inside = px < v.width && py < v.height;
   const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
-  const uint32_t wbit = 1u << wid;
+  const StageBlock sb = stage_block<TW>(tx, ty, TH, wid, prm.log2_alpha_min);
 
   const uint2 rg = ranges[tile];
   const float amin = prm.log2_alpha_min;
@@ -75,28 +80,17 @@ __device__ __forceinline__ void composite_block(
   float ek0 = prm.bg[0], ek1 = prm.bg[1], ek2 = prm.bg[2], tau_s = 0.0f;
   float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
 
-  // Batches of 64 splats: lane j reads the block bits of splat (base + j)
-  // (one coalesced load); a ballot gives the wave a bitmap of the splats whose
-  // footprint reaches its 8x8 block.  Those are visited in order, one per
-  // iteration, each one's fields read with scalar loads into SGPRs (no
-  // per-lane copies, no LDS).  The per-pixel update is branch-free: a lane
-  // whose alpha is below alpha_min, or which has stopped, composites a = 0,
-  // which leaves every operator's state unchanged, so the loop carries no
-  // per-lane control flow and little scalar bookkeeping.
-  const float* crf = reinterpret_cast<const float*>(crec);
+  // Batches of 64 list entries are staged in LDS (only the splats that reach
+  // the block); each staged splat is then visited by the whole wave.  The
+  // per-pixel update is branch-free: a lane whose alpha is below alpha_min,
+  // or which has stopped, composites a = 0, which leaves every operator's
+  // state unchanged, so the loop carries no per-lane control flow.
   bool all_done = __builtin_amdgcn_ballot_w64(!op.stopped(t_eps)) == 0;
   for (uint32_t base = rg.x; base < rg.y && !all_done; base += 64) {
-    const uint32_t j = base + (uint32_t)lane;
-    const uint32_t bits = j < rg.y ? __float_as_uint(crf[12 * (size_t)j + 9]) : 0u;
-    uint64_t rel = __builtin_amdgcn_ballot_w64((bits & wbit) != 0);
-    const float* bp = crf + 12 * (size_t)base;
-    while (rel != 0) {
-      const uint32_t b = (uint32_t)__builtin_ctzll(rel);
-      rel ^= 1ull << b;
-      const float* r = bp + 12 * b;
-      float c[9];
-#pragma unroll
-      for (int f = 0; f < 9; ++f) c[f] = r[f];
+    const uint32_t n = stage_batch(inst_val, rec, base, rg.y, sb, wlds, lane);
+    for (uint32_t k = 0; k < n; ++k) {
+      const float4 q0 = wlds[3 * k + 0], q1 = wlds[3 * k + 1];
+      const float c[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, wlds[3 * k + 2].x};
       const float dx = fx - c[0], dy = fy - c[1];
       const float e = fmaf(dx, fmaf(c[2], dx, c[3] * dy), fmaf(c[4] * dy, dy, c[5]));
       const bool valid = (e >= amin) && !op.stopped(t_eps);
@@ -147,27 +141,37 @@ constexpr int kBlocksPerTile(int tw, int th) { return (tw / 8) * (th / 8); }
 template <int MODEL, int TW, int TH, bool STATE>
 __global__ __launch_bounds__(TW* TH) void composite_tiles_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const float4* __restrict__ crec, CompositeParams prm, float4* __restrict__ pstate) {
-  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, crec, prm, pstate, blockIdx.x,
-                                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
-                                        threadIdx.x & 63);
+    const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
+    float4* __restrict__ pstate, uint32_t n_tiles, uint32_t per_xcd) {
+  __shared__ float4 stage[kBlocksPerTile(TW, TH) * kStageF4];
+  const uint32_t tile = xcd_banded(blockIdx.x, per_xcd);
+  if (tile >= n_tiles) return;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
+                                        stage + wid * kStageF4, tile, wid, threadIdx.x & 63);
 }
 
 template <int MODEL, int TW, int TH, bool STATE>
 __global__ __launch_bounds__(64) void composite_blocks_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const float4* __restrict__ crec, CompositeParams prm, float4* __restrict__ pstate) {
+    const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
+    float4* __restrict__ pstate, uint32_t n_items, uint32_t per_xcd) {
+  __shared__ float4 stage[kStageF4];
   constexpr int B = kBlocksPerTile(TW, TH);
-  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, crec, prm, pstate,
-                                        blockIdx.x / B, (int)(blockIdx.x % B), threadIdx.x);
+  const uint32_t item = xcd_banded(blockIdx.x, per_xcd);
+  if (item >= n_items) return;
+  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
+                                        stage, item / B, (int)(item % B), threadIdx.x);
 }
 
 // Work item k of the queue is block (k mod B) of tile order[k / B].
 template <int MODEL, int TW, int TH, bool STATE>
 __global__ __launch_bounds__(64) void composite_queue_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
-    const float4* __restrict__ crec, CompositeParams prm, float4* __restrict__ pstate,
-    const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* __restrict__ queue) {
+    const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
+    float4* __restrict__ pstate, const uint32_t* __restrict__ order, uint32_t n_items,
+    uint32_t* __restrict__ queue) {
+  __shared__ float4 stage[kStageF4];
   constexpr int B = kBlocksPerTile(TW, TH);
   const int lane = threadIdx.x;
   for (;;) {
@@ -175,8 +179,8 @@ __global__ __launch_bounds__(64) void composite_queue_kernel(
     if (lane == 0) k = atomicAdd(queue, 1u);
     k = __builtin_amdgcn_readfirstlane(k);   // lane 0's ticket, wave-uniform
     if (k >= n_items) break;        // every wave ends once the queue is drained
-    composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, crec, prm, pstate,
-                                          order[k / B], (int)(k % B), lane);
+    composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
+                                          stage, order[k / B], (int)(k % B), lane);
   }
 }
 
@@ -224,20 +228,24 @@ void launch_s(const CompositeLaunch& L, const CompositeParams& p, float4* pstate
               hipStream_t s) {
   constexpr int B = kBlocksPerTile(TW, TH);
   if (L.schedule == NXS_SCHED_TILES) {
-    hipLaunchKernelGGL((composite_tiles_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)L.n_tiles),
-                       dim3(TW * TH), 0, s, L.views, L.n_views, L.ranges, L.crec, p, pstate);
+    const uint32_t per = (uint32_t)((L.n_tiles + 7) / 8);
+    hipLaunchKernelGGL((composite_tiles_kernel<MODEL, TW, TH, STATE>), dim3(per * 8),
+                       dim3(TW * TH), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
+                       pstate, (uint32_t)L.n_tiles, per);
   } else if (L.schedule == NXS_SCHED_BLOCKS) {
-    hipLaunchKernelGGL((composite_blocks_kernel<MODEL, TW, TH, STATE>),
-                       dim3((unsigned)(L.n_tiles * B)), dim3(64), 0, s, L.views, L.n_views,
-                       L.ranges, L.crec, p, pstate);
+    const int64_t items = L.n_tiles * B;
+    const uint32_t per = (uint32_t)((items + 7) / 8);
+    hipLaunchKernelGGL((composite_blocks_kernel<MODEL, TW, TH, STATE>), dim3(per * 8),
+                       dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
+                       pstate, (uint32_t)items, per);
   } else {
     hipLaunchKernelGGL(order_tiles_kernel, dim3(1), dim3(kOrderThreads), 0, s, L.ranges,
                        (uint32_t)L.n_tiles, L.order, L.queue);
     const int64_t items = L.n_tiles * B;
     const int64_t grid = std::min<int64_t>(items, (int64_t)L.n_cu * kQueueWavesPerCU);
     hipLaunchKernelGGL((composite_queue_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)grid),
-                       dim3(64), 0, s, L.views, L.n_views, L.ranges, L.crec, p, pstate,
-                       L.order, (uint32_t)items, L.queue);
+                       dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
+                       pstate, L.order, (uint32_t)items, L.queue);
   }
 }
 

@@ -105,20 +105,11 @@ void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted, i
 
 
 
-// Tile ranges and gather of the composite records in sorted order.
+// Tile ranges: ranges[tile] = [first, end) of the tile's entries in the
+// tile-sorted instance list (tiles without instances keep what the caller
+// filled in, normally [0, 0)).
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s);
-// Composite records, 3 float4 (12 dwords) per instance in sorted order:
-//   du, dv             centre relative to the tile corner (pixels)
-//   A', B', C', lo     log2(alpha) = lo + A' dx^2 + B' dx dy + C' dy^2
-//   r, g, b            emission
-//   mask               bit i set if the box where alpha >= alpha_min reaches
-//                      the tile's i-th 8x8 pixel block (row-major)
-//   slot               the projected slot (view * n + Gaussian), for gradients
-//   0
-void launch_ranges_gather(const uint32_t* inst_tile, const uint32_t* inst_val,
-                          int64_t m, const ProjDev& proj, const ViewDev* views,
-                          int n_views, int tile_w, int tile_h, float log2_alpha_min,
-                          uint2* ranges, float4* crec, hipStream_t s);
+void launch_ranges(const uint32_t* inst_tile, int64_t m, uint2* ranges, hipStream_t s);
 
 struct CompositeParams {
   float log2_alpha_min;
@@ -141,7 +132,8 @@ struct CompositeLaunch {
   const ViewDev* views;
   int n_views;
   const uint2* ranges;
-  const float4* crec;
+  const uint32_t* inst_val;  // tile-sorted list of projected slots
+  const float4* rec;         // the projection's records, per slot
   uint32_t* order;
   uint32_t* queue;
   int n_cu;
@@ -155,7 +147,7 @@ void launch_composite(int model, const CompositeLaunch& L, const CompositeParams
 // accumulated with atomics (the caller zeroes gslot).
 void launch_composite_bwd(int model, int tile_w, int tile_h, int64_t n_tiles,
                           const ViewDev* views, int n_views, const uint2* ranges,
-                          const float4* crec, const CompositeParams& p,
+                          const uint32_t* inst_val, const float4* rec, const CompositeParams& p,
                           const float4* pstate, float* gslot, hipStream_t s);
 
 // Gradients of the Gaussians' parameters from the per-slot gradients (summed

@@ -1,0 +1,118 @@
+// Gather of splat records into a wave's LDS, batch by batch, for the
+// composite and its backward (the tile's sorted list holds projected slots;
+// their records stay where the projection wrote them).
+#pragma once
+
+#include <hip/hip_fp16.h>
+
+#include "nxs_internal.h"
+
+namespace nxs {
+
+// Records staged per wave: 64 x 3 float4, in list order, only the splats
+// whose footprint reaches the wave's 8x8 block:
+//   (du, dv, A', B')   centre relative to the tile corner (pixels), conic terms
+//   (C', lo, r, g)     log2(alpha) = lo + A' dx^2 + B' dx dy + C' dy^2; emission
+//   (b, slot, 0, 0)    emission; the projected slot (view * n + Gaussian)
+constexpr int kStageF4 = 3 * 64;
+
+// Per-wave constants of the staging test.
+struct StageBlock {
+  float cu, cv;                 // tile corner (pixels)
+  float x0, x1, y0, y1;         // pixel-centre extent of the block, tile-relative
+  float amin;                   // log2(alpha_min)
+};
+
+template <int TW>
+__device__ __forceinline__ StageBlock stage_block(int tx, int ty, int th, int wid,
+                                                  float log2_alpha_min) {
+  StageBlock b;
+  b.cu = (float)(tx * TW);
+  b.cv = (float)(ty * th);
+  const int bx = (wid % (TW / 8)) * 8, by = (wid / (TW / 8)) * 8;
+  b.x0 = (float)bx + 0.5f;
+  b.x1 = (float)bx + 7.5f;
+  b.y0 = (float)by + 0.5f;
+  b.y1 = (float)by + 7.5f;
+  b.amin = log2_alpha_min;
+  return b;
+}
+
+// Lane j takes list entry base + j (if below end): loads its slot and the
+// slot's record, forms the tile-relative centre ((hi - corner) is exact,
+// then + lo), and keeps the splat if its alpha >= alpha_min box reaches the
+// block and, exactly, if the largest exponent over the rectangle spanned by
+// the block's pixel centres reaches log2(alpha_min) (2e-3 of margin in log2
+// units, so float32 rounding can keep a block that no pixel needs but never
+// drop one that some pixel needs: a kept splat that reaches no pixel
+// composites nothing).  The kept records are written, in list order, to
+// `wlds`; returns how many.
+__device__ __forceinline__ uint32_t stage_batch(const uint32_t* __restrict__ inst_val,
+                                                const float4* __restrict__ rec, uint32_t base,
+                                                uint32_t end, const StageBlock& b,
+                                                float4* wlds, int lane) {
+  const uint32_t j = base + (uint32_t)lane;
+  bool keep = false;
+  uint32_t slot = 0;
+  float du = 0.f, dv = 0.f;
+  float4 r1 = make_float4(0.f, 0.f, 0.f, 0.f), r2 = r1;
+  if (j < end) {
+    slot = inst_val[j];
+    const float4 r0 = rec[3 * (size_t)slot + 0];
+    r1 = rec[3 * (size_t)slot + 1];
+    r2 = rec[3 * (size_t)slot + 2];
+    du = (r0.x - b.cu) + r0.y;
+    dv = (r0.z - b.cv) + r0.w;
+    // half-extents of the alpha >= alpha_min box, two fp16 rounded up
+    const uint32_t hx = __float_as_uint(r2.w);
+    const float rx = __half2float(__ushort_as_half((unsigned short)(hx & 0xFFFFu)));
+    const float ry = __half2float(__ushort_as_half((unsigned short)(hx >> 16)));
+    if (!(dv - ry > b.y1 || dv + ry < b.y0 || du - rx > b.x1 || du + rx < b.x0)) {
+      const float qa = -r1.x, qb = -r1.y, qc = -r1.z;   // Q = -(e - lo) >= 0
+      const float qlim = r1.w - b.amin + 2e-3f;         // e >= amin <=> Q <= qlim
+      const float xlo = b.x0 - du, xhi = b.x1 - du;     // dx range over the block
+      const float ylo = b.y0 - dv, yhi = b.y1 - dv;     // dy range over the block
+      float qmin = 0.0f;
+      if (!(xlo <= 0.0f && xhi >= 0.0f && ylo <= 0.0f && yhi >= 0.0f)) {
+        // the centre is outside: the minimum of Q lies on an edge
+        const float ia = 0.5f / qa, ic = 0.5f / qc;
+        qmin = __builtin_inff();
+        const float xs[2] = {xlo, xhi}, ys[2] = {ylo, yhi};
+#pragma unroll
+        for (int e2 = 0; e2 < 2; ++e2) {
+          const float X = xs[e2];
+          const float y = fminf(fmaxf(-qb * X * ic, ylo), yhi);
+          qmin = fminf(qmin, X * (qa * X + qb * y) + qc * y * y);
+          const float Y = ys[e2];
+          const float x = fminf(fmaxf(-qb * Y * ia, xlo), xhi);
+          qmin = fminf(qmin, Y * (qc * Y + qb * x) + qa * x * x);
+        }
+      }
+      keep = qmin <= qlim;
+    }
+  }
+  const uint64_t sel = __builtin_amdgcn_ballot_w64(keep);
+  if (keep) {
+    // position among the kept lanes below this one
+    const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(sel >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)sel, 0u));
+    wlds[3 * pos + 0] = make_float4(du, dv, r1.x, r1.y);
+    wlds[3 * pos + 1] = make_float4(r1.z, r1.w, r2.x, r2.y);
+    wlds[3 * pos + 2] = make_float4(r2.z, __uint_as_float(slot), 0.0f, 0.0f);
+  }
+  // LDS operations of one wave complete in order: the reads that follow see
+  // these writes without a barrier; this keeps the compiler from moving them
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return (uint32_t)__builtin_popcountll(sel);
+}
+
+// Work-group -> item mapping that gives each of the 8 XCDs (which receive
+// work-groups round-robin) one contiguous band of items: neighbouring tiles,
+// which share Gaussians, then read their records from the same L2.
+__device__ __forceinline__ uint32_t xcd_banded(uint32_t wg, uint32_t per_xcd) {
+  return (wg % 8u) * per_xcd + wg / 8u;
+}
+
+}  // namespace nxs

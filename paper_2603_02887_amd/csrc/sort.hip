@@ -1,6 +1,6 @@
-// Binning: the scan + emission of tile instances, tile ranges and the gather
-// of the composite records into sorted order (the radix sort itself is in
-// radix.hip).
+// Binning: the scan + emission of tile instances and the tile ranges (the
+// radix sort itself is in radix.hip; the gather of records into sorted order
+// happens batch by batch inside the composite).
 //
 // Front-to-back order inside each tile (Sec. 3: splats sorted by depth) is
 // obtained in two sorts instead of one wide one:
@@ -11,15 +11,12 @@
 // single sort on the 64-bit key (tile << 32 | depth bits) with ties by index,
 // while moving 32-bit keys over fewer bits.
 //
-#include <hip/hip_fp16.h>
-
 #include "nxs_internal.h"
 
 namespace nxs {
 
 namespace {
 
-constexpr uint32_t kXcds = 8;   // accelerator complex dies of an MI355X
 
 // Block-wide exclusive scan of one value per thread (256 threads).
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s_tmp,
@@ -193,93 +190,22 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
   }
 }
 
-// ----------------------------------------------------- ranges + gather
-
+// ----------------------------------------------------------------- ranges
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = value;
 }
 
-__device__ __forceinline__ int view_of_tile(const ViewDev* views, int n_views, uint32_t tile) {
-  int lo = 0, hi = n_views - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if ((uint32_t)views[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__global__ __launch_bounds__(256) void ranges_gather_kernel(
-    const uint32_t* __restrict__ inst_tile, const uint32_t* __restrict__ inst_val,
-    int64_t m, ProjDev proj, const ViewDev* __restrict__ views, int n_views, int tile_w,
-    int tile_h, float log2_alpha_min, uint2* __restrict__ ranges,
-    float4* __restrict__ crec, uint32_t per_xcd) {
-  // Work-groups go to the 8 XCDs round-robin; give each XCD one contiguous
-  // eighth of the sorted list (a band of tile rows), so that the records of
-  // Gaussians shared by neighbouring tiles are re-read from that XCD's L2.
-  const uint32_t lb = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-  const int64_t j = (int64_t)lb * blockDim.x + threadIdx.x;
+// Entry j starts its tile's range if the entry before it has another tile,
+// and ends it if the entry after it has another tile.
+__global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict__ inst_tile,
+                                                     int64_t m, uint2* __restrict__ ranges) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const uint32_t tile = inst_tile[j];
   if (j == 0 || inst_tile[j - 1] != tile) ranges[tile].x = (uint32_t)j;
   if (j == m - 1 || inst_tile[j + 1] != tile) ranges[tile].y = (uint32_t)(j + 1);
-  const uint32_t slot = inst_val[j];
-  const int vi = view_of_tile(views, n_views, tile);
-  const ViewDev& v = views[vi];
-  const int lt = (int)(tile - (uint32_t)v.tile_off);
-  const int tx = lt % v.tiles_x, ty = lt / v.tiles_x;
-  const float4 r0 = proj.rec[3 * (int64_t)slot + 0];
-  const float4 r1 = proj.rec[3 * (int64_t)slot + 1];
-  const float4 r2 = proj.rec[3 * (int64_t)slot + 2];
-  // centre relative to the tile corner: (hi - corner) is exact, then + lo
-  const float du = (r0.x - (float)(tx * tile_w)) + r0.y;
-  const float dv = (r0.z - (float)(ty * tile_h)) + r0.w;
-  // half-extents of the alpha >= alpha_min box, packed as two fp16 (rounded up)
-  const uint32_t hx = __float_as_uint(r2.w);
-  const float rx = __half2float(__ushort_as_half((unsigned short)(hx & 0xFFFFu)));
-  const float ry = __half2float(__ushort_as_half((unsigned short)(hx >> 16)));
-  // which 8x8 pixel blocks of the tile (bit by * (tile_w / 8) + bx) the
-  // footprint reaches, judged at pixel centres; the composite's waves skip the
-  // others.  A block passes the box test, then the exact one: the largest
-  // exponent e = lo + A' dx^2 + B' dx dy + C' dy^2 over the rectangle spanned
-  // by its pixel centres must reach log2(alpha_min) (with a margin of 2e-3 in
-  // log2 units, so float32 rounding here can only keep a block, never drop one
-  // that some pixel needs).
-  const float qa = -r1.x, qb = -r1.y, qc = -r1.z;    // Q = -(e - lo) >= 0
-  const float qlim = r1.w - log2_alpha_min + 2e-3f;  // e >= log2(alpha_min) <=> Q <= qlim
-  const float ia = 0.5f / qa, ic = 0.5f / qc;
-  uint32_t mask = 0;
-  const int nbx = tile_w >> 3, nby = tile_h >> 3;
-  for (int by = 0; by < nby; ++by) {
-    const float y0 = (float)(8 * by) + 0.5f, y1 = (float)(8 * by) + 7.5f;
-    if (dv - ry > y1 || dv + ry < y0) continue;
-    const float ylo = y0 - dv, yhi = y1 - dv;          // dy range over the block
-    for (int bx = 0; bx < nbx; ++bx) {
-      const float x0 = (float)(8 * bx) + 0.5f, x1 = (float)(8 * bx) + 7.5f;
-      if (du - rx > x1 || du + rx < x0) continue;
-      const float xlo = x0 - du, xhi = x1 - du;        // dx range over the block
-      float qmin = 0.0f;
-      if (!(xlo <= 0.0f && xhi >= 0.0f && ylo <= 0.0f && yhi >= 0.0f)) {
-        // the centre is outside: the minimum lies on an edge of the rectangle
-        qmin = __builtin_inff();
-        const float xs[2] = {xlo, xhi}, ys[2] = {ylo, yhi};
-#pragma unroll
-        for (int e2 = 0; e2 < 2; ++e2) {
-          const float X = xs[e2];
-          const float y = fminf(fmaxf(-qb * X * ic, ylo), yhi);
-          qmin = fminf(qmin, X * (qa * X + qb * y) + qc * y * y);
-          const float Y = ys[e2];
-          const float x = fminf(fmaxf(-qb * Y * ia, xlo), xhi);
-          qmin = fminf(qmin, Y * (qc * Y + qb * x) + qa * x * x);
-        }
-      }
-      if (qmin <= qlim) mask |= 1u << (by * nbx + bx);
-    }
-  }
-  crec[3 * j + 0] = make_float4(du, dv, r1.x, r1.y);
-  crec[3 * j + 1] = make_float4(r1.z, r1.w, r2.x, r2.y);
-  crec[3 * j + 2] = make_float4(r2.z, __uint_as_float(mask), __uint_as_float(slot), 0.0f);
 }
 
 }  // namespace
@@ -317,16 +243,10 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {
                      p, n, value);
 }
 
-void launch_ranges_gather(const uint32_t* inst_tile, const uint32_t* inst_val, int64_t m,
-                          const ProjDev& proj, const ViewDev* views, int n_views,
-                          int tile_w, int tile_h, float log2_alpha_min, uint2* ranges,
-                          float4* crec, hipStream_t s) {
+void launch_ranges(const uint32_t* inst_tile, int64_t m, uint2* ranges, hipStream_t s) {
   if (m <= 0) return;
-  const uint32_t nb = (uint32_t)((m + 255) / 256);
-  const uint32_t per = (nb + kXcds - 1) / kXcds;
-  hipLaunchKernelGGL(ranges_gather_kernel, dim3(per * kXcds), dim3(256), 0, s, inst_tile,
-                     inst_val, m, proj, views, n_views, tile_w, tile_h, log2_alpha_min,
-                     ranges, crec, per);
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                     inst_tile, m, ranges);
 }
 
 }  // namespace nxs

@@ -337,7 +337,7 @@ class Renderer:
         return out
 
     # -------------------------------------------------------- inspection
-    STAGES = ("project", "depth_sort", "emit", "tile_sort", "gather", "composite")
+    STAGES = ("project", "depth_sort", "emit", "tile_sort", "ranges", "composite")
 
     def set_timing(self, enable=True):
         self._check(self._L.nxs_set_timing(self._ctx, int(bool(enable))))

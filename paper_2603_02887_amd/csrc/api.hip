@@ -327,7 +327,9 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
       (st = ensure(ctx, ctx->tinfo, 16 * S)) || (st = ensure(ctx, ctx->nt_sorted, 4 * S)) ||
       (st = ensure(ctx, ctx->rect_sorted, 8 * S)) ||
       (st = ensure(ctx, ctx->prec, 48 * S)) || (st = ensure(ctx, ctx->scan_local, 4 * S)) ||
-      (st = ensure(ctx, ctx->block_sums, 4 * scan_blocks_size(S))))
+      (st = ensure(ctx, ctx->block_sums, 4 * scan_blocks_size(S))) ||
+      (st = ensure(ctx, ctx->counts, 4 * radix_counts_words(S))) ||
+      (st = ensure(ctx, ctx->ranges, 8 * total_tiles)))
     return st;
   ProjDev proj{P<uint32_t>(ctx->depth_key), P<uint4>(ctx->tinfo), P<float4>(ctx->prec)};
   GaussDev gd{g->means, g->scales, g->quats, g->opacities, g->sh, g->n, g->sh_degree};
@@ -338,9 +340,9 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   };
   ctx->ev_valid = false;
   HIP_TRY(mark(0));
-  launch_init_counters(dcount, s);
+  // (also clears the tile ranges)
   launch_project(gd, dviews, n_views, kappa2, alpha_min, tw, th, proj,
-                 P<uint4>(ctx->partials), dcount, s);
+                 P<uint4>(ctx->partials), dcount, P<uint32_t>(ctx->ranges), 2 * total_tiles, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(1));
   // The instance count M is read by the host only where it sizes buffers and
@@ -349,11 +351,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   // enqueued first, so the GPU keeps working while the host waits.
   HIP_TRY(hipMemcpyAsync(ctx->host_counters, dcount, sizeof(Counters), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(ctx->counted, s));
-  if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_words(S))) ||
-      (st = ensure(ctx, ctx->ranges, 8 * total_tiles)))
-    return st;
   HIP_TRY(mark(2));
-  launch_fill_u32(P<uint32_t>(ctx->ranges), 2 * total_tiles, 0u, s);
   // 1. depth sort of the slots (values: the slots 0..S-1)
   //    (its last pass also lays out the slots' tile counts and rectangles in
   //    that order, so that the emission reads them coalesced)

@@ -53,17 +53,20 @@ struct ProjDev {
 struct Counters {
   unsigned long long total;
   uint32_t dmin, dmax;
-  // the depth sort's digits (shift | width << 8 per pass), from dmin ^ dmax
+  // the depth sort's digits (shift | width << 8 | kPassActive per pass),
+  // from dmin ^ dmax
   uint32_t plan[4];
 };
 
 // ---- launchers (all enqueue on `s`) ------------------------------------------
-void launch_init_counters(Counters* c, hipStream_t s);
-// `partials` needs project_partials_size(n) entries.
+// `partials` needs project_partials_size(n) entries.  Also sets `counters`
+// (total instances, depth-bit range, depth-sort plan) and zeroes
+// clear[0, n_clear).
 size_t project_partials_size(int n);
 void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
                     float kappa2, float alpha_min, int tile_w, int tile_h,
-                    const ProjDev& out, uint4* partials, Counters* counters, hipStream_t s);
+                    const ProjDev& out, uint4* partials, Counters* counters,
+                    uint32_t* clear, int64_t n_clear, hipStream_t s);
 
 // Stable LSD radix sort of (u32 key, u32 value) pairs on key bits [0, nbits).
 // Returns 0 if the result is in (keys, vals), 1 if in (keys_alt, vals_alt).
@@ -74,9 +77,13 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
 // radix_counts_words(n) u32.
 size_t radix_counts_words(int64_t n);
 // The same sort with its digits read from device memory: plan[p] = shift |
-// width << 8 for kPlanPasses passes (a pass of width 0 copies).  Enough for
-// keys of up to 32 varying bits.
+// width << 8 | kPassActive for kPlanPasses passes (an active pass of width 0
+// copies).  Passes 1..3 are always active, pass 0 only when three digits of
+// kMaxDigitBits do not cover the varying bits; the result lands in the same
+// buffers either way.  Enough for keys of up to 32 varying bits.
 constexpr int kPlanPasses = 4;
+constexpr int kMaxDigitBits = 9;
+constexpr uint32_t kPassActive = 1u << 16;
 // Its last pass also writes, in sorted order, each value's tile count and
 // rectangle from `tinfo` (indexed by value) into nt_out / rect_out.
 int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,

@@ -183,8 +183,14 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void project_kernel(
     GaussDev g, const ViewDev* __restrict__ views, int n_views, float kappa2,
-    float alpha_min, int tile_w, int tile_h, ProjDev out, uint4* __restrict__ partials) {
+    float alpha_min, int tile_w, int tile_h, ProjDev out, uint4* __restrict__ partials,
+    uint32_t* __restrict__ clear, int64_t n_clear) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  // the tile ranges of this render start empty (the ranges pass fills in the
+  // occupied tiles)
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n_clear;
+       k += (int64_t)gridDim.x * kBlock)
+    clear[k] = 0u;
   constexpr int NC = 3 * K;
   constexpr int STRIDE = NC + 1;
   __shared__ float s_sh[kBlock * STRIDE];
@@ -362,46 +368,45 @@ __global__ __launch_bounds__(1024) void reduce_counters_kernel(const uint4* __re
     c->total = tot;
     c->dmin = mn;
     c->dmax = mx;
-    // the depth sort needs the bits that vary among visible depths, in
-    // kPlanPasses balanced digits
+    // the depth sort needs the bits that vary among visible depths: three
+    // balanced digits of at most kMaxDigitBits in passes 1..3 when they cover
+    // them (pass 0 inactive), else four in passes 0..3
     const uint32_t diff = mn <= mx ? (mn ^ mx) : 0u;
     const int nbits = diff ? 32 - __clz((int)diff) : 0;
+    const int first = nbits <= 3 * kMaxDigitBits ? 1 : 0;
     int shift = 0;
-    for (int p = 0; p < kPlanPasses; ++p) {
+    c->plan[0] = 0u;
+    for (int p = first; p < kPlanPasses; ++p) {
       const int w = (nbits - shift + (kPlanPasses - p) - 1) / (kPlanPasses - p);
-      c->plan[p] = (uint32_t)shift | ((uint32_t)w << 8);
+      c->plan[p] = (uint32_t)shift | ((uint32_t)w << 8) | kPassActive;
       shift += w;
     }
   }
 }
 
-__global__ void init_counters_kernel(Counters* c) {
-  c->total = 0ull;
-  c->dmin = 0xFFFFFFFFu;
-  c->dmax = 0u;
-}
-
 }  // namespace
-
-void launch_init_counters(Counters* c, hipStream_t s) {
-  hipLaunchKernelGGL(init_counters_kernel, dim3(1), dim3(1), 0, s, c);
-}
 
 void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
                     float kappa2, float alpha_min, int tile_w, int tile_h,
-                    const ProjDev& out, uint4* partials, Counters* counters, hipStream_t s) {
-  if (g.n <= 0 || n_views <= 0) return;
-  dim3 grid((g.n + kBlock - 1) / kBlock);
+                    const ProjDev& out, uint4* partials, Counters* counters,
+                    uint32_t* clear, int64_t n_clear, hipStream_t s) {
+  const bool any = g.n > 0 && n_views > 0;
+  dim3 grid(any ? (g.n + kBlock - 1) / kBlock : 0);
 #define NXS_PROJECT(D)                                                                 \
   hipLaunchKernelGGL(project_kernel<D>, grid, dim3(kBlock), 0, s, g, views, n_views,  \
-                     kappa2, alpha_min, tile_w, tile_h, out, partials)
-  switch (g.sh_degree) {
-    case 0: NXS_PROJECT(0); break;
-    case 1: NXS_PROJECT(1); break;
-    case 2: NXS_PROJECT(2); break;
-    default: NXS_PROJECT(3); break;
+                     kappa2, alpha_min, tile_w, tile_h, out, partials, clear, n_clear)
+  if (any) {
+    switch (g.sh_degree) {
+      case 0: NXS_PROJECT(0); break;
+      case 1: NXS_PROJECT(1); break;
+      case 2: NXS_PROJECT(2); break;
+      default: NXS_PROJECT(3); break;
+    }
+  } else {
+    launch_fill_u32(clear, n_clear, 0u, s);
   }
 #undef NXS_PROJECT
+  // with no blocks this writes the counters of an empty render
   hipLaunchKernelGGL(reduce_counters_kernel, dim3(1), dim3(1024), 0, s, partials,
                      (int)grid.x, counters);
 }

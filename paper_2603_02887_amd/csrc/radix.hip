@@ -1,6 +1,6 @@
 // Stable LSD radix sort of (u32 key, u32 value) pairs, reduce-then-scan.
 //
-// Digits of up to 8 bits (as few passes as that allows, widths balanced) over
+// Digits of up to 9 bits (as few passes as that allows, widths balanced) over
 // chunks of 1,024 keys (small chunks: many work-groups, short per-group
 // latency, which is what bounds these passes at 1-3 million keys).  Each pass
 // is three kernels:
@@ -29,7 +29,9 @@ constexpr int kRWaves = kRThreads / 64;
 constexpr int kRItems = 4;
 constexpr int kRChunk = kRThreads * kRItems;   // 1,024 keys
 constexpr int kRPerWave = kRChunk / kRWaves;   // 256 keys, 4 rounds of 64
-constexpr int kRBins = 256;                    // digits of up to 8 bits
+constexpr int kRBins = 1 << kMaxDigitBits;     // digits of up to 9 bits
+constexpr int kRBinsPerThread = kRBins / kRThreads;
+static_assert(kRBinsPerThread == 2, "the scans below take two digits per thread");
 constexpr uint32_t kRXcds = 8;
 
 __device__ __forceinline__ uint32_t chunk_of(uint32_t b, uint32_t per) {
@@ -48,28 +50,49 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, int width, bool vali
 }
 
 // A pass's digit is (key >> shift) & (2^width - 1); with `plan` the pair comes
-// from device memory (plan[pass] = shift | width << 8), so a sort can be
-// enqueued before the host knows how many bits vary.
-__device__ __forceinline__ void pass_digit(const uint32_t* plan, int pass, int& shift,
+// from device memory (plan[pass] = shift | width << 8 | kPassActive), so a
+// sort can be enqueued before the host knows how many bits vary.  Returns
+// false for an inactive pass (every kernel of it does nothing).
+__device__ __forceinline__ bool pass_digit(const uint32_t* plan, int pass, int& shift,
                                            int& width) {
   if (plan) {
     const uint32_t w = plan[pass];
     shift = (int)(w & 0xFFu);
     width = (int)((w >> 8) & 0xFFu);
+    return (w & kPassActive) != 0;
+  }
+  return true;
+}
+
+// Only the first pass of a plan is optional: when it is inactive, the
+// second pass reads the sort's input (keys_first, vals_first) instead of the
+// first pass's output, and the result still lands where four passes put it.
+__device__ __forceinline__ void select_input(const uint32_t* plan, int pass,
+                                             const uint32_t* keys_first,
+                                             const uint32_t* vals_first, const uint32_t*& keys,
+                                             const uint32_t*& vals) {
+  if (plan && pass == 1 && !(plan[0] & kPassActive)) {
+    keys = keys_first;
+    vals = vals_first;
   }
 }
 
-__global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* __restrict__ keys,
-                                                      int64_t n, int shift, int width,
+__global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* keys,
+                                                      const uint32_t* keys_first, int64_t n,
+                                                      int shift, int width,
                                                       const uint32_t* __restrict__ plan,
                                                       int pass, uint32_t nchunks, uint32_t per,
                                                       uint32_t* __restrict__ counts) {
   __shared__ uint32_t h[kRBins];
-  pass_digit(plan, pass, shift, width);
+  if (!pass_digit(plan, pass, shift, width)) return;   // the whole grid
   const uint32_t c = chunk_of(blockIdx.x, per);
   if (c >= nchunks) return;                    // the whole work-group
+  {
+    const uint32_t* unused = nullptr;
+    select_input(plan, pass, keys_first, nullptr, keys, unused);
+  }
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  h[t] = 0;
+  for (int d = t; d < kRBins; d += kRThreads) h[d] = 0;
   __syncthreads();
   const uint32_t mask = (1u << width) - 1u;
   const int64_t base = (int64_t)c * kRChunk;
@@ -90,7 +113,7 @@ __global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* __restrict
     if (valid && (peers & lt_mask) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
   }
   __syncthreads();
-  if (t <= (int)mask) counts[(int64_t)t * nchunks + c] = h[t];
+  for (int d = t; d <= (int)mask; d += kRThreads) counts[(int64_t)d * nchunks + c] = h[d];
 }
 
 __device__ __forceinline__ uint32_t rx_block_scan(uint32_t x, uint32_t* s_tmp, uint32_t* total) {
@@ -118,12 +141,12 @@ __device__ __forceinline__ uint32_t rx_block_scan(uint32_t x, uint32_t* s_tmp, u
 // One work-group per digit: exclusive scan of counts[d][0..nchunks) in place.
 __global__ __launch_bounds__(kRThreads) void rx_scan(uint32_t* __restrict__ counts,
                                                      uint32_t nchunks,
-                                                     uint32_t* __restrict__ totals,
+                                                     uint32_t* __restrict__ totals, int width,
                                                      const uint32_t* __restrict__ plan,
                                                      int pass) {
   __shared__ uint32_t s_tmp[kRWaves];
-  int shift = 0, width = 8;
-  pass_digit(plan, pass, shift, width);
+  int shift = 0;
+  if (!pass_digit(plan, pass, shift, width)) return;   // the whole grid
   if (blockIdx.x >= (1u << width)) return;    // the whole work-group
   uint32_t* row = counts + (int64_t)blockIdx.x * nchunks;
   uint32_t running = 0;
@@ -148,11 +171,13 @@ __global__ __launch_bounds__(kRThreads) void rx_scan(uint32_t* __restrict__ coun
   if (threadIdx.x == 0) totals[blockIdx.x] = running;
 }
 
-// vals_in == nullptr: the values are the input positions.
+// vals_in == nullptr: the values are the input positions.  The last pass
+// also writes the payload from `tinfo` when it is given.
 __global__ __launch_bounds__(kRThreads) void rx_scatter(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n, int shift,
-    int width, const uint32_t* __restrict__ plan, int pass, uint32_t nchunks, uint32_t per,
+    const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* keys_first,
+    const uint32_t* vals_first, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, int64_t n, int shift, int width,
+    const uint32_t* __restrict__ plan, int pass, uint32_t nchunks, uint32_t per,
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
     const uint4* __restrict__ tinfo, uint32_t* __restrict__ nt_out,
     uint2* __restrict__ rect_out) {
@@ -163,12 +188,14 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
   __shared__ uint32_t s_lbase[kRBins];
   __shared__ uint32_t s_tmp[kRWaves];
 
-  pass_digit(plan, pass, shift, width);
+  if (!pass_digit(plan, pass, shift, width)) return;   // the whole grid
   const uint32_t c = chunk_of(blockIdx.x, per);
   if (c >= nchunks) return;                    // the whole work-group
+  select_input(plan, pass, keys_first, vals_first, keys_in, vals_in);
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
-  for (int w = 0; w < kRWaves; ++w) s_wave[w][t] = 0;
+  for (int w = 0; w < kRWaves; ++w)
+    for (int d = t; d < kRBins; d += kRThreads) s_wave[w][d] = 0;
   const uint32_t mask = (1u << width) - 1u;
   const int nd = 1 << width;
   const int64_t base = (int64_t)c * kRChunk;
@@ -185,14 +212,17 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
       v_reg[r] = vals_in ? vals_in[base + li] : (uint32_t)(base + li);
     }
   }
-  // global start of this chunk's run of digit t: keys of smaller digits plus
-  // keys of digit t in earlier chunks
+  // global start of this chunk's run of each digit: keys of smaller digits
+  // plus keys of that digit in earlier chunks (thread t: digits 2t, 2t + 1)
   {
-    const uint32_t tot = t < nd ? totals[t] : 0u;
-    const uint32_t off = t < nd ? counts[(int64_t)t * nchunks + c] : 0u;
+    const int d0 = 2 * t, d1 = 2 * t + 1;
+    const uint32_t tot0 = d0 < nd ? totals[d0] : 0u, tot1 = d1 < nd ? totals[d1] : 0u;
+    const uint32_t off0 = d0 < nd ? counts[(int64_t)d0 * nchunks + c] : 0u;
+    const uint32_t off1 = d1 < nd ? counts[(int64_t)d1 * nchunks + c] : 0u;
     uint32_t all;
-    const uint32_t ex = rx_block_scan(tot, s_tmp, &all);
-    s_gbase[t] = ex + off;
+    const uint32_t ex = rx_block_scan(tot0 + tot1, s_tmp, &all);
+    s_gbase[d0] = ex + off0;
+    s_gbase[d1] = ex + tot0 + off1;
   }
   __syncthreads();
   // per-wave ranks: keys of the same digit earlier in this wave's part
@@ -216,10 +246,16 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
   __syncthreads();
   // local start of each digit's run in the chunk
   {
-    uint32_t cnt = 0;
-    for (int w = 0; w < kRWaves; ++w) cnt += s_wave[w][t];
+    const int d0 = 2 * t, d1 = 2 * t + 1;
+    uint32_t cnt0 = 0, cnt1 = 0;
+    for (int w = 0; w < kRWaves; ++w) {
+      cnt0 += s_wave[w][d0];
+      cnt1 += s_wave[w][d1];
+    }
     uint32_t all;
-    s_lbase[t] = rx_block_scan(t < nd ? cnt : 0u, s_tmp, &all);
+    const uint32_t ex = rx_block_scan(cnt0 + cnt1, s_tmp, &all);
+    s_lbase[d0] = ex;
+    s_lbase[d1] = ex + cnt0;
   }
   __syncthreads();
 #pragma unroll
@@ -272,14 +308,14 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
     const int shift = shifts ? shifts[p] : 0, width = widths ? widths[p] : 8;
     uint32_t* kout = (cur == 0) ? k1 : k0;
     uint32_t* vout = (cur == 0) ? v1 : v0;
-    hipLaunchKernelGGL(rx_count, dim3(grid), dim3(kRThreads), 0, s, kin, n, shift, width, plan,
-                       p, nchunks, per, counts);
+    hipLaunchKernelGGL(rx_count, dim3(grid), dim3(kRThreads), 0, s, kin, keys_in, n, shift,
+                       width, plan, p, nchunks, per, counts);
     hipLaunchKernelGGL(rx_scan, dim3(plan ? kRBins : (1u << width)), dim3(kRThreads), 0, s,
-                       counts, nchunks, totals, plan, p);
+                       counts, nchunks, totals, width, plan, p);
     const bool last = p == passes - 1;
-    hipLaunchKernelGGL(rx_scatter, dim3(grid), dim3(kRThreads), 0, s, kin, vin, kout, vout, n,
-                       shift, width, plan, p, nchunks, per, counts, totals,
-                       last ? tinfo : nullptr, nt_out, rect_out);
+    hipLaunchKernelGGL(rx_scatter, dim3(grid), dim3(kRThreads), 0, s, kin, vin, keys_in,
+                       vals_in, kout, vout, n, shift, width, plan, p, nchunks, per, counts,
+                       totals, last ? tinfo : nullptr, nt_out, rect_out);
     kin = kout;
     vin = vout;
     cur = (cur == 0) ? 1 : 0;
@@ -294,7 +330,7 @@ int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
                hipStream_t s) {
   if (n <= 0) return 0;
   nbits = std::max(nbits, 1);
-  const int passes = (nbits + 7) / 8;
+  const int passes = (nbits + kMaxDigitBits - 1) / kMaxDigitBits;
   int shifts[4], widths[4], shift = 0;
   for (int p = 0; p < passes; ++p) {
     widths[p] = (nbits - shift + (passes - p) - 1) / (passes - p);

@@ -1,9 +1,10 @@
 // Stable LSD radix sort of (u32 key, u32 value) pairs, reduce-then-scan.
 //
 // Digits of up to 9 bits (as few passes as that allows, widths balanced) over
-// chunks of 1,024 keys (small chunks: many work-groups, short per-group
-// latency, which is what bounds these passes at 1-3 million keys).  Each pass
-// is three kernels:
+// chunks of 1,024 keys below 16M keys (many work-groups, short per-group
+// latency, which is what bounds these passes at 1-3 million keys) and of
+// 4,096 keys above (longer digit runs per chunk, which is what bounds them at
+// tens of millions).  Each pass is three kernels:
 //   count    per chunk and digit                counts[d * nchunks + c]
 //            (one LDS add per distinct digit per wave round: lanes with equal
 //            digits are matched by ballots first)
@@ -26,9 +27,14 @@ namespace {
 
 constexpr int kRThreads = 256;
 constexpr int kRWaves = kRThreads / 64;
-constexpr int kRItems = 4;
-constexpr int kRChunk = kRThreads * kRItems;   // 1,024 keys
-constexpr int kRPerWave = kRChunk / kRWaves;   // 256 keys, 4 rounds of 64
+// Keys per thread: 4 (chunks of 1,024) keeps the per-group latency short,
+// which is what bounds a pass at a few million keys; 16 (chunks of 4,096)
+// gives each digit runs four times longer in a chunk's output, which is what
+// bounds a pass at tens of millions of keys (partial cache lines at run ends).
+constexpr int kRItemsSmall = 4;
+constexpr int kRItemsLarge = 16;
+constexpr int64_t kRLargeFrom = int64_t(1) << 24;   // keys
+constexpr int kRChunkMin = kRThreads * kRItemsSmall;
 constexpr int kRBins = 1 << kMaxDigitBits;     // digits of up to 9 bits
 constexpr int kRBinsPerThread = kRBins / kRThreads;
 static_assert(kRBinsPerThread == 2, "the scans below take two digits per thread");
@@ -77,6 +83,7 @@ __device__ __forceinline__ void select_input(const uint32_t* plan, int pass,
   }
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* keys,
                                                       const uint32_t* keys_first, int64_t n,
                                                       int shift, int width,
@@ -95,18 +102,18 @@ __global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* keys,
   for (int d = t; d < kRBins; d += kRThreads) h[d] = 0;
   __syncthreads();
   const uint32_t mask = (1u << width) - 1u;
-  const int64_t base = (int64_t)c * kRChunk;
-  const int chunk_n = (int)min((int64_t)kRChunk, n - base);
+  const int64_t base = (int64_t)c * (kRThreads * ITEMS);
+  const int chunk_n = (int)min((int64_t)(kRThreads * ITEMS), n - base);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t k[kRItems];
+  uint32_t k[ITEMS];
 #pragma unroll
-  for (int r = 0; r < kRItems; ++r) {
-    const int li = wid * kRPerWave + r * 64 + lane;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = wid * (64 * ITEMS) + r * 64 + lane;
     k[r] = li < chunk_n ? keys[base + li] : 0u;
   }
 #pragma unroll
-  for (int r = 0; r < kRItems; ++r) {
-    const int li = wid * kRPerWave + r * 64 + lane;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = wid * (64 * ITEMS) + r * 64 + lane;
     const bool valid = li < chunk_n;
     const uint32_t d = (k[r] >> shift) & mask;
     const uint64_t peers = digit_peers(d, width, valid);
@@ -173,6 +180,7 @@ __global__ __launch_bounds__(kRThreads) void rx_scan(uint32_t* __restrict__ coun
 
 // vals_in == nullptr: the values are the input positions.  The last pass
 // also writes the payload from `tinfo` when it is given.
+template <int ITEMS>
 __global__ __launch_bounds__(kRThreads) void rx_scatter(
     const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* keys_first,
     const uint32_t* vals_first, uint32_t* __restrict__ keys_out,
@@ -181,8 +189,8 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
     const uint4* __restrict__ tinfo, uint32_t* __restrict__ nt_out,
     uint2* __restrict__ rect_out) {
-  __shared__ uint32_t s_key[kRChunk];
-  __shared__ uint32_t s_val[kRChunk];
+  __shared__ uint32_t s_key[(kRThreads * ITEMS)];
+  __shared__ uint32_t s_val[(kRThreads * ITEMS)];
   __shared__ uint32_t s_wave[kRWaves][kRBins];
   __shared__ uint32_t s_gbase[kRBins];
   __shared__ uint32_t s_lbase[kRBins];
@@ -198,13 +206,13 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     for (int d = t; d < kRBins; d += kRThreads) s_wave[w][d] = 0;
   const uint32_t mask = (1u << width) - 1u;
   const int nd = 1 << width;
-  const int64_t base = (int64_t)c * kRChunk;
-  const int chunk_n = (int)min((int64_t)kRChunk, n - base);
+  const int64_t base = (int64_t)c * (kRThreads * ITEMS);
+  const int chunk_n = (int)min((int64_t)(kRThreads * ITEMS), n - base);
 
-  uint32_t k_reg[kRItems], v_reg[kRItems];
+  uint32_t k_reg[ITEMS], v_reg[ITEMS];
 #pragma unroll
-  for (int r = 0; r < kRItems; ++r) {
-    const int li = wid * kRPerWave + r * 64 + lane;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = wid * (64 * ITEMS) + r * 64 + lane;
     k_reg[r] = 0u;
     v_reg[r] = 0u;
     if (li < chunk_n) {
@@ -227,10 +235,10 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
   __syncthreads();
   // per-wave ranks: keys of the same digit earlier in this wave's part
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t rank[kRItems], dig[kRItems];
+  uint32_t rank[ITEMS], dig[ITEMS];
 #pragma unroll
-  for (int r = 0; r < kRItems; ++r) {
-    const int li = wid * kRPerWave + r * 64 + lane;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = wid * (64 * ITEMS) + r * 64 + lane;
     const bool valid = li < chunk_n;
     const uint32_t d = valid ? (k_reg[r] >> shift) & mask : 0u;
     const uint64_t peers = digit_peers(d, width, valid);
@@ -259,8 +267,8 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kRItems; ++r) {
-    const int li = wid * kRPerWave + r * 64 + lane;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = wid * (64 * ITEMS) + r * 64 + lane;
     if (li < chunk_n) {
       const uint32_t d = dig[r];
       uint32_t off = s_lbase[d] + rank[r];
@@ -287,7 +295,7 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
 }  // namespace
 
 size_t radix_counts_words(int64_t n) {
-  const int64_t nchunks = std::max<int64_t>((n + kRChunk - 1) / kRChunk, 1);
+  const int64_t nchunks = std::max<int64_t>((n + kRChunkMin - 1) / kRChunkMin, 1);
   return (size_t)nchunks * kRBins + kRBins;
 }
 
@@ -297,7 +305,9 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
                uint32_t* k1, uint32_t* v1, int64_t n, int passes, const int* shifts,
                const int* widths, const uint32_t* plan, uint32_t* counts, const uint4* tinfo,
                uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
-  const uint32_t nchunks = (uint32_t)((n + kRChunk - 1) / kRChunk);
+  const bool large = n >= kRLargeFrom;
+  const int chunk = kRThreads * (large ? kRItemsLarge : kRItemsSmall);
+  const uint32_t nchunks = (uint32_t)((n + chunk - 1) / chunk);
   const uint32_t per = (nchunks + kRXcds - 1) / kRXcds;
   const unsigned grid = per * kRXcds;
   uint32_t* totals = counts + (size_t)nchunks * kRBins;
@@ -308,14 +318,23 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
     const int shift = shifts ? shifts[p] : 0, width = widths ? widths[p] : 8;
     uint32_t* kout = (cur == 0) ? k1 : k0;
     uint32_t* vout = (cur == 0) ? v1 : v0;
-    hipLaunchKernelGGL(rx_count, dim3(grid), dim3(kRThreads), 0, s, kin, keys_in, n, shift,
-                       width, plan, p, nchunks, per, counts);
+    if (large)
+      hipLaunchKernelGGL(rx_count<kRItemsLarge>, dim3(grid), dim3(kRThreads), 0, s, kin,
+                         keys_in, n, shift, width, plan, p, nchunks, per, counts);
+    else
+      hipLaunchKernelGGL(rx_count<kRItemsSmall>, dim3(grid), dim3(kRThreads), 0, s, kin,
+                         keys_in, n, shift, width, plan, p, nchunks, per, counts);
     hipLaunchKernelGGL(rx_scan, dim3(plan ? kRBins : (1u << width)), dim3(kRThreads), 0, s,
                        counts, nchunks, totals, width, plan, p);
     const bool last = p == passes - 1;
-    hipLaunchKernelGGL(rx_scatter, dim3(grid), dim3(kRThreads), 0, s, kin, vin, keys_in,
-                       vals_in, kout, vout, n, shift, width, plan, p, nchunks, per, counts,
-                       totals, last ? tinfo : nullptr, nt_out, rect_out);
+    if (large)
+      hipLaunchKernelGGL(rx_scatter<kRItemsLarge>, dim3(grid), dim3(kRThreads), 0, s, kin, vin,
+                         keys_in, vals_in, kout, vout, n, shift, width, plan, p, nchunks, per,
+                         counts, totals, last ? tinfo : nullptr, nt_out, rect_out);
+    else
+      hipLaunchKernelGGL(rx_scatter<kRItemsSmall>, dim3(grid), dim3(kRThreads), 0, s, kin, vin,
+                         keys_in, vals_in, kout, vout, n, shift, width, plan, p, nchunks, per,
+                         counts, totals, last ? tinfo : nullptr, nt_out, rect_out);
     kin = kout;
     vin = vout;
     cur = (cur == 0) ? 1 : 0;

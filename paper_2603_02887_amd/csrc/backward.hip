@@ -32,23 +32,28 @@ namespace {
 
 constexpr float kL2e = 1.4426950408889634f;
 
-// Sum over the 64 lanes with DPP moves (VALU only, no LDS): pairs, quads,
-// half-rows and rows by quad_perm / mirror patterns, then rows 1 and 3 take
-// row_bcast:15 and rows 2 and 3 take row_bcast:31; lane 63 ends with the total.
-template <int CTRL, int ROW_MASK>
+// Sum over each row of 16 lanes with DPP adds (VALU only): pairs and quads
+// by quad_perm, then half-rows and rows by mirror patterns; every lane of a
+// row ends with the row's total.
+template <int CTRL>
 __device__ __forceinline__ float dpp_add(float x) {
-  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF,
-                                            ROW_MASK == 0xF);
+  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true);
   return x + __int_as_float(y);
 }
-__device__ __forceinline__ float wave_total(float x) {
-  x = dpp_add<0xB1, 0xF>(x);    // quad_perm [1,0,3,2]
-  x = dpp_add<0x4E, 0xF>(x);    // quad_perm [2,3,0,1]
-  x = dpp_add<0x141, 0xF>(x);   // row_half_mirror
-  x = dpp_add<0x140, 0xF>(x);   // row_mirror
-  x = dpp_add<0x142, 0xA>(x);   // row_bcast:15 into rows 1, 3
-  x = dpp_add<0x143, 0xC>(x);   // row_bcast:31 into rows 2, 3
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+__device__ __forceinline__ float row_total(float x) {
+  x = dpp_add<0xB1>(x);    // quad_perm [1,0,3,2]
+  x = dpp_add<0x4E>(x);    // quad_perm [2,3,0,1]
+  x = dpp_add<0x141>(x);   // row_half_mirror
+  x = dpp_add<0x140>(x);   // row_mirror
+  return x;
+}
+
+// LDS operations of one wave complete in order; this keeps the compiler from
+// moving the wave's LDS accesses across it.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int MODEL, int TW, int TH>
@@ -58,6 +63,7 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
     const float4* __restrict__ pstate, float* __restrict__ gslot, uint32_t n_tiles,
     uint32_t per_xcd) {
   __shared__ float4 stage[(TW / 8) * (TH / 8) * kStageF4];
+  __shared__ float4 rsum[(TW / 8) * (TH / 8) * 12];   // per wave: 4 rows x 9 sums
   const uint32_t tile = xcd_banded(blockIdx.x, per_xcd);
   if (tile >= n_tiles) return;
   int vi = 0;
@@ -81,6 +87,7 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
   const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
   const StageBlock sb = stage_block<TW>(tx, ty, TH, wid, prm.log2_alpha_min);
   float4* wlds = stage + wid * kStageF4;
+  float* wred = reinterpret_cast<float*>(rsum + wid * 12);
   const uint2 rg = ranges[tile];
   const float amin = prm.log2_alpha_min;
   const float t_eps = prm.t_eps;
@@ -173,14 +180,23 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
         }
       }
       if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
-        // the wave's sums, then one 9-lane atomic: lane f adds field f
-        const float t[9] = {wave_total(d_op), wave_total(d_u), wave_total(d_v),
-                            wave_total(d_A),  wave_total(d_B), wave_total(d_C),
-                            wave_total(d_r),  wave_total(d_g), wave_total(d_b)};
-        float mine = 0.0f;
-#pragma unroll
-        for (int f = 0; f < 9; ++f) mine = lane == f ? t[f] : mine;
-        if (lane < 9) atomicAdd(gslot + 9 * (size_t)__float_as_uint(r[9]) + lane, mine);
+        // the wave's sums: row totals, written to LDS by each row's first
+        // lane, then lane f adds field f of the 4 rows and issues the atomic
+        const float t[9] = {row_total(d_op), row_total(d_u), row_total(d_v),
+                            row_total(d_A),  row_total(d_B), row_total(d_C),
+                            row_total(d_r),  row_total(d_g), row_total(d_b)};
+        if ((lane & 15) == 0) {
+          float4* rr = reinterpret_cast<float4*>(wred + 12 * (lane >> 4));
+          rr[0] = make_float4(t[0], t[1], t[2], t[3]);
+          rr[1] = make_float4(t[4], t[5], t[6], t[7]);
+          rr[2].x = t[8];
+        }
+        wave_lds_order();
+        if (lane < 9) {
+          const float sum = (wred[lane] + wred[12 + lane]) + (wred[24 + lane] + wred[36 + lane]);
+          atomicAdd(gslot + 9 * (size_t)__float_as_uint(r[9]) + lane, sum);
+        }
+        wave_lds_order();
       }
       all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
     }

@@ -86,8 +86,13 @@ __device__ __forceinline__ void composite_block(
   // or which has stopped, composites a = 0, which leaves every operator's
   // state unchanged, so the loop carries no per-lane control flow.
   bool all_done = __builtin_amdgcn_ballot_w64(!op.stopped(t_eps)) == 0;
+  StageSlot slots = stage_slot(inst_val, rg.x, rg.y, lane);
+  StageFetch fetched = stage_records(slots, rec);
+  slots = stage_slot(inst_val, (uint64_t)rg.x + 64, rg.y, lane);
   for (uint32_t base = rg.x; base < rg.y && !all_done; base += 64) {
-    const uint32_t n = stage_batch(inst_val, rec, base, rg.y, sb, wlds, lane);
+    const uint32_t n = stage_batch(fetched, sb, wlds);
+    fetched = stage_records(slots, rec);                              // batch base + 64
+    slots = stage_slot(inst_val, (uint64_t)base + 128, rg.y, lane);   // batch base + 128
     for (uint32_t k = 0; k < n; ++k) {
       const float4 q0 = wlds[3 * k + 0], q1 = wlds[3 * k + 1];
       const float c[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, wlds[3 * k + 2].x};

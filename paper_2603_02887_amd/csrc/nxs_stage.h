@@ -38,29 +38,56 @@ __device__ __forceinline__ StageBlock stage_block(int tx, int ty, int th, int wi
   return b;
 }
 
-// Lane j takes list entry base + j (if below end): loads its slot and the
-// slot's record, forms the tile-relative centre ((hi - corner) is exact,
-// then + lo), and keeps the splat if its alpha >= alpha_min box reaches the
-// block and, exactly, if the largest exponent over the rectangle spanned by
-// the block's pixel centres reaches log2(alpha_min) (2e-3 of margin in log2
-// units, so float32 rounding can keep a block that no pixel needs but never
-// drop one that some pixel needs: a kept splat that reaches no pixel
-// composites nothing).  The kept records are written, in list order, to
-// `wlds`; returns how many.
-__device__ __forceinline__ uint32_t stage_batch(const uint32_t* __restrict__ inst_val,
-                                                const float4* __restrict__ rec, uint32_t base,
-                                                uint32_t end, const StageBlock& b,
-                                                float4* wlds, int lane) {
-  const uint32_t j = base + (uint32_t)lane;
+// A batch's global reads, issued ahead of their use so that they are in
+// flight while earlier batches are composited: lane j takes list entry
+// base + j (if below end) and its slot (two batches ahead), then the slot's
+// record (one batch ahead).  Every lane reads (past the end: the list's last
+// entry again, end > 0), so that no branch makes a read complete early.
+struct StageSlot {
+  uint32_t slot;
+  bool valid;
+};
+struct StageFetch {
+  uint32_t slot;
+  bool valid;
+  float4 r0, r1, r2;
+};
+
+__device__ __forceinline__ StageSlot stage_slot(const uint32_t* __restrict__ inst_val,
+                                                uint64_t base, uint32_t end, int lane) {
+  StageSlot s;
+  const uint64_t j = base + (uint64_t)lane;
+  s.valid = j < end;
+  s.slot = inst_val[s.valid ? (uint32_t)j : end - 1];
+  return s;
+}
+
+__device__ __forceinline__ StageFetch stage_records(const StageSlot& s,
+                                                    const float4* __restrict__ rec) {
+  StageFetch f;
+  f.slot = s.slot;
+  f.valid = s.valid;
+  const float4* r = rec + 3 * (size_t)s.slot;
+  f.r0 = r[0];
+  f.r1 = r[1];
+  f.r2 = r[2];
+  return f;
+}
+
+// Forms the tile-relative centre ((hi - corner) is exact, then + lo) and
+// keeps the splat if its alpha >= alpha_min box reaches the block and,
+// exactly, if the largest exponent over the rectangle spanned by the block's
+// pixel centres reaches log2(alpha_min) (2e-3 of margin in log2 units, so
+// float32 rounding can keep a block that no pixel needs but never drop one
+// that some pixel needs: a kept splat that reaches no pixel composites
+// nothing).  The kept records are written, in list order, to `wlds`;
+// returns how many.
+__device__ __forceinline__ uint32_t stage_batch(const StageFetch& f, const StageBlock& b,
+                                                float4* wlds) {
   bool keep = false;
-  uint32_t slot = 0;
   float du = 0.f, dv = 0.f;
-  float4 r1 = make_float4(0.f, 0.f, 0.f, 0.f), r2 = r1;
-  if (j < end) {
-    slot = inst_val[j];
-    const float4 r0 = rec[3 * (size_t)slot + 0];
-    r1 = rec[3 * (size_t)slot + 1];
-    r2 = rec[3 * (size_t)slot + 2];
+  const float4 r0 = f.r0, r1 = f.r1, r2 = f.r2;
+  if (f.valid) {
     du = (r0.x - b.cu) + r0.y;
     dv = (r0.z - b.cv) + r0.w;
     // half-extents of the alpha >= alpha_min box, two fp16 rounded up
@@ -98,7 +125,7 @@ __device__ __forceinline__ uint32_t stage_batch(const uint32_t* __restrict__ ins
         (uint32_t)(sel >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)sel, 0u));
     wlds[3 * pos + 0] = make_float4(du, dv, r1.x, r1.y);
     wlds[3 * pos + 1] = make_float4(r1.z, r1.w, r2.x, r2.y);
-    wlds[3 * pos + 2] = make_float4(r2.z, __uint_as_float(slot), 0.0f, 0.0f);
+    wlds[3 * pos + 2] = make_float4(r2.z, __uint_as_float(f.slot), 0.0f, 0.0f);
   }
   // LDS operations of one wave complete in order: the reads that follow see
   // these writes without a barrier; this keeps the compiler from moving them

@@ -50,10 +50,10 @@ HBM_PEAK_GBS = 8000.0
 # from FETCH_SIZE and WRITE_SIZE counter runs scaled by a copy kernel of known
 # size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
 # kernel sources with this digest and are reported as null once those change.
-TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_internal.h")
-TRAFFIC = {"digest": "84decaceaa050874cd0f4e93e4cd2450590702167d63a62f123f9f17118425cf",
+TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_stage.h", "nxs_internal.h")
+TRAFFIC = {"digest": "f73f9a9f762fee2dd57154a44a21c011680066e5e7af623fae6329ee8b4ef49f",
            "tile": "16x16",
-           "bytes": {0: 158396922, 1: 96983881, 2: 106946674, 3: 93593283}}
+           "bytes": {0: 229277671, 1: 132885771, 2: 147387220, 3: 128661547}}
 
 
 def measured_traffic(model, tile):

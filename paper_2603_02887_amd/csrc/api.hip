@@ -55,6 +55,9 @@ struct nxs_context {
   std::vector<ViewDev> bwd_views;
   // state of the last render, for inspection
   int64_t last_m = 0, last_tiles = 0, last_slots = 0;
+  // first depth-sort pass to launch: 1 while the last render's plan left
+  // pass 0 inactive (at most 27 varying depth bits), else 0
+  int depth_first = 0;
   int32_t last_n = 0, last_views = 0;
   uint32_t* last_inst_tile = nullptr;
   uint32_t* last_inst_val = nullptr;
@@ -355,11 +358,16 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   // 1. depth sort of the slots (values: the slots 0..S-1)
   //    (its last pass also lays out the slots' tile counts and rectangles in
   //    that order, so that the emission reads them coalesced)
-  const int wd = radix_sort_planned(P<uint32_t>(ctx->depth_key), nullptr,
-                                    P<uint32_t>(ctx->dsort_a), P<uint32_t>(ctx->slot_a),
-                                    P<uint32_t>(ctx->dsort_b), P<uint32_t>(ctx->slot_b), S,
-                                    dcount->plan, P<uint32_t>(ctx->counts), proj.tinfo,
-                                    P<uint32_t>(ctx->nt_sorted), P<uint2>(ctx->rect_sorted), s);
+  //    (launched from the pass the last render's plan needed; checked below)
+  const int depth_first = ctx->depth_first;
+  auto depth_sort = [&](int first) {
+    return radix_sort_planned(P<uint32_t>(ctx->depth_key), nullptr, P<uint32_t>(ctx->dsort_a),
+                              P<uint32_t>(ctx->slot_a), P<uint32_t>(ctx->dsort_b),
+                              P<uint32_t>(ctx->slot_b), S, dcount->plan, first,
+                              P<uint32_t>(ctx->counts), proj.tinfo,
+                              P<uint32_t>(ctx->nt_sorted), P<uint2>(ctx->rect_sorted), s);
+  };
+  const int wd = depth_sort(depth_first);
   uint32_t* sorted_slots = wd ? P<uint32_t>(ctx->slot_b) : P<uint32_t>(ctx->slot_a);
   HIP_TRY(mark(3));
   // 2. emission in depth order, into the buffers as they are
@@ -374,6 +382,11 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventSynchronize(ctx->counted));
   const uint64_t M = ctx->host_counters->total;
+  // the depth sort skipped pass 0 but this render's plan needs it: sort and
+  // emit again below (the depth keys are intact)
+  const bool pass0 = (ctx->host_counters->plan[0] & kPassActive) != 0;
+  const bool resort = S > 0 && depth_first == 1 && pass0;
+  ctx->depth_first = pass0 ? 0 : 1;
   // what this render needs, visible through nxs_inspect_counts even if it fails
   ctx->last_m = (int64_t)M;
   ctx->last_tiles = total_tiles;
@@ -390,7 +403,12 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
     return st;
   uint32_t* inst_tile = P<uint32_t>(ctx->inst_tile);
   uint32_t* inst_val = P<uint32_t>(ctx->inst_val);
-  if (M > cap32)   // the emission above did not fit: emit again into the grown buffers
+  if (resort) {
+    (void)depth_sort(0);
+    launch_emit_scan(P<uint32_t>(ctx->nt_sorted), S, P<uint32_t>(ctx->scan_local),
+                     P<uint32_t>(ctx->block_sums), s);
+  }
+  if (resort || M > cap32)   // emit (again) into the grown buffers
     launch_emit_write(sorted_slots, P<uint2>(ctx->rect_sorted), S, g->n, dviews,
                       P<uint32_t>(ctx->scan_local), P<uint32_t>(ctx->block_sums), (uint32_t)M,
                       inst_tile, inst_val, s);

@@ -68,32 +68,34 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
                     const ProjDev& out, uint4* partials, Counters* counters,
                     uint32_t* clear, int64_t n_clear, hipStream_t s);
 
-// Stable LSD radix sort of (u32 key, u32 value) pairs on key bits [0, nbits).
-// Returns 0 if the result is in (keys, vals), 1 if in (keys_alt, vals_alt).
-// Stable LSD radix sort (reduce-then-scan, 8-bit digits): sorts (keys_in,
-// vals_in) by the low nbits of the keys (at least one pass), ping-ponging
-// through (k0, v0) and (k1, v1); returns which pair holds the result (0 or 1).
-// vals_in == nullptr: values are the input positions.  `counts` needs
-// radix_counts_words(n) u32.
-size_t radix_counts_words(int64_t n);
-// The same sort with its digits read from device memory: plan[p] = shift |
-// width << 8 | kPassActive for kPlanPasses passes (an active pass of width 0
-// copies).  Passes 1..3 are always active, pass 0 only when three digits of
-// kMaxDigitBits do not cover the varying bits; the result lands in the same
-// buffers either way.  Enough for keys of up to 32 varying bits.
 constexpr int kPlanPasses = 4;
 constexpr int kMaxDigitBits = 9;
 constexpr uint32_t kPassActive = 1u << 16;
-// Its last pass also writes, in sorted order, each value's tile count and
-// rectangle from `tinfo` (indexed by value) into nt_out / rect_out.
-int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
-                       uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
-                       const uint32_t* plan, uint32_t* counts, const uint4* tinfo,
-                       uint32_t* nt_out, uint2* rect_out, hipStream_t s);
+
+// Stable LSD radix sort of (u32 key, u32 value) pairs (reduce-then-scan,
+// digits of up to kMaxDigitBits): sorts (keys_in, vals_in) by the low nbits
+// of the keys (at least one pass), ping-ponging through (k0, v0) and (k1, v1);
+// returns which pair holds the result (0 or 1).  vals_in == nullptr: values
+// are the input positions.  `counts` needs radix_counts_words(n) u32.
+size_t radix_counts_words(int64_t n);
 int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
                hipStream_t s);
-
+// The same sort with its digits read from device memory: plan[p] = shift |
+// width << 8 | kPassActive for kPlanPasses passes (an active pass of width 0
+// copies).  Passes 1..3 are always active, pass 0 only when three digits of
+// kMaxDigitBits do not cover the varying bits.  Enough for keys of up to 32
+// varying bits.  first_pass = 0 launches all four passes (an inactive pass 0
+// does nothing and pass 1 then reads the input); first_pass = 1 launches
+// passes 1..3 only, which is right only if the plan leaves pass 0 inactive
+// (the caller checks plan[0] once it has read the counters, and sorts again
+// with first_pass = 0 otherwise).  The result is in (k1, v1); returns 1.
+// The last pass also writes, in sorted order, each value's tile count and
+// rectangle from `tinfo` (indexed by value) into nt_out / rect_out.
+int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
+                       uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
+                       const uint32_t* plan, int first_pass, uint32_t* counts,
+                       const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s);
 
 // Exclusive scan of ntiles in sorted-slot order and emission of instances.
 size_t scan_blocks_size(int64_t n);

@@ -176,6 +176,59 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
   return x;
 }
 
+// One work-group of NT threads folds the per-block partials into the counters
+// read by the host, and plans the depth sort.
+constexpr int kFoldThreads = 1024;
+template <int NT>
+__device__ void fold_partials(const uint4* partials, int nblocks, Counters* c) {
+  __shared__ unsigned long long s_tot[NT / 64];
+  __shared__ uint32_t s_mn[NT / 64], s_mx[NT / 64];
+  unsigned long long tot = 0;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  for (int b = threadIdx.x; b < nblocks; b += NT) {
+    const uint4 p = partials[b];
+    tot += p.x;
+    mn = min(mn, p.y);
+    mx = max(mx, p.z);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    tot += __shfl_xor(tot, o, 64);
+    mn = min(mn, (uint32_t)__shfl_xor(mn, o, 64));
+    mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_tot[wid] = tot;
+    s_mn[wid] = mn;
+    s_mx[wid] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < NT / 64; ++w) {
+      tot += s_tot[w];
+      mn = min(mn, s_mn[w]);
+      mx = max(mx, s_mx[w]);
+    }
+    c->total = tot;
+    c->dmin = mn;
+    c->dmax = mx;
+    // the depth sort needs the bits that vary among visible depths: three
+    // balanced digits of at most kMaxDigitBits in passes 1..3 when they cover
+    // them (pass 0 inactive), else four in passes 0..3
+    const uint32_t diff = mn <= mx ? (mn ^ mx) : 0u;
+    const int nbits = diff ? 32 - __clz((int)diff) : 0;
+    const int first = nbits <= 3 * kMaxDigitBits ? 1 : 0;
+    int shift = 0;
+    c->plan[0] = 0u;
+    for (int p = first; p < kPlanPasses; ++p) {
+      const int w = (nbits - shift + (kPlanPasses - p) - 1) / (kPlanPasses - p);
+      c->plan[p] = (uint32_t)shift | ((uint32_t)w << 8) | kPassActive;
+      shift += w;
+    }
+  }
+}
+
 // One work-group projects 256 consecutive Gaussians into every view.  The
 // block's SH coefficients (contiguous in HBM) are staged into LDS with
 // coalesced loads, padded to an odd stride so that per-thread reads are free
@@ -327,61 +380,18 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
       mn = min(mn, s_min[k]);
       mx = max(mx, s_max[k]);
     }
-    // one partial per block (no same-address atomics across thousands of blocks)
+    // one partial per block (no same-address atomics across thousands of
+    // blocks; a device-scope fence per block to let the last one fold them
+    // would write back L2 each time)
     partials[blockIdx.x] = make_uint4(tot, mn, mx, 0u);
   }
 }
 
-// One work-group folds the per-block partials into the counters read by the host.
-__global__ __launch_bounds__(1024) void reduce_counters_kernel(const uint4* __restrict__ partials,
-                                                               int nblocks,
-                                                               Counters* __restrict__ c) {
-  __shared__ unsigned long long s_tot[16];
-  __shared__ uint32_t s_mn[16], s_mx[16];
-  unsigned long long tot = 0;
-  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-  for (int b = threadIdx.x; b < nblocks; b += 1024) {
-    const uint4 p = partials[b];
-    tot += p.x;
-    mn = min(mn, p.y);
-    mx = max(mx, p.z);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    tot += __shfl_xor(tot, o, 64);
-    mn = min(mn, (uint32_t)__shfl_xor(mn, o, 64));
-    mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-    s_tot[wid] = tot;
-    s_mn[wid] = mn;
-    s_mx[wid] = mx;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < 16; ++w) {
-      tot += s_tot[w];
-      mn = min(mn, s_mn[w]);
-      mx = max(mx, s_mx[w]);
-    }
-    c->total = tot;
-    c->dmin = mn;
-    c->dmax = mx;
-    // the depth sort needs the bits that vary among visible depths: three
-    // balanced digits of at most kMaxDigitBits in passes 1..3 when they cover
-    // them (pass 0 inactive), else four in passes 0..3
-    const uint32_t diff = mn <= mx ? (mn ^ mx) : 0u;
-    const int nbits = diff ? 32 - __clz((int)diff) : 0;
-    const int first = nbits <= 3 * kMaxDigitBits ? 1 : 0;
-    int shift = 0;
-    c->plan[0] = 0u;
-    for (int p = first; p < kPlanPasses; ++p) {
-      const int w = (nbits - shift + (kPlanPasses - p) - 1) / (kPlanPasses - p);
-      c->plan[p] = (uint32_t)shift | ((uint32_t)w << 8) | kPassActive;
-      shift += w;
-    }
-  }
+// One work-group folds the projection's per-block partials (none for a render
+// with no Gaussians) into the counters read by the host.
+__global__ __launch_bounds__(kFoldThreads) void reduce_counters_kernel(
+    const uint4* __restrict__ partials, int nblocks, Counters* __restrict__ c) {
+  fold_partials<kFoldThreads>(partials, nblocks, c);
 }
 
 }  // namespace
@@ -391,10 +401,11 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
                     const ProjDev& out, uint4* partials, Counters* counters,
                     uint32_t* clear, int64_t n_clear, hipStream_t s) {
   const bool any = g.n > 0 && n_views > 0;
-  dim3 grid(any ? (g.n + kBlock - 1) / kBlock : 0);
-#define NXS_PROJECT(D)                                                                 \
-  hipLaunchKernelGGL(project_kernel<D>, grid, dim3(kBlock), 0, s, g, views, n_views,  \
-                     kappa2, alpha_min, tile_w, tile_h, out, partials, clear, n_clear)
+  const int nblocks = any ? (g.n + kBlock - 1) / kBlock : 0;
+#define NXS_PROJECT(D)                                                                  \
+  hipLaunchKernelGGL(project_kernel<D>, dim3(nblocks), dim3(kBlock), 0, s, g, views,   \
+                     n_views, kappa2, alpha_min, tile_w, tile_h, out, partials, clear, \
+                     n_clear)
   if (any) {
     switch (g.sh_degree) {
       case 0: NXS_PROJECT(0); break;
@@ -406,9 +417,8 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
     launch_fill_u32(clear, n_clear, 0u, s);
   }
 #undef NXS_PROJECT
-  // with no blocks this writes the counters of an empty render
-  hipLaunchKernelGGL(reduce_counters_kernel, dim3(1), dim3(1024), 0, s, partials,
-                     (int)grid.x, counters);
+  hipLaunchKernelGGL(reduce_counters_kernel, dim3(1), dim3(kFoldThreads), 0, s, partials,
+                     nblocks, counters);
 }
 
 size_t project_partials_size(int n) { return (size_t)((n + kBlock - 1) / kBlock) + 1; }

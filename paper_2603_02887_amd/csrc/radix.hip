@@ -301,10 +301,13 @@ size_t radix_counts_words(int64_t n) {
 
 namespace {
 
+// Passes first..passes-1; pass p writes (k0, v0) if p is even, else (k1, v1),
+// and the first launched pass reads the sort's input.  Returns which pair
+// holds the result.
 int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
-               uint32_t* k1, uint32_t* v1, int64_t n, int passes, const int* shifts,
-               const int* widths, const uint32_t* plan, uint32_t* counts, const uint4* tinfo,
-               uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
+               uint32_t* k1, uint32_t* v1, int64_t n, int first, int passes,
+               const int* shifts, const int* widths, const uint32_t* plan, uint32_t* counts,
+               const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
   const bool large = n >= kRLargeFrom;
   const int chunk = kRThreads * (large ? kRItemsLarge : kRItemsSmall);
   const uint32_t nchunks = (uint32_t)((n + chunk - 1) / chunk);
@@ -313,11 +316,10 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
   uint32_t* totals = counts + (size_t)nchunks * kRBins;
   const uint32_t* kin = keys_in;
   const uint32_t* vin = vals_in;
-  int cur = -1;
-  for (int p = 0; p < passes; ++p) {
+  for (int p = first; p < passes; ++p) {
     const int shift = shifts ? shifts[p] : 0, width = widths ? widths[p] : 8;
-    uint32_t* kout = (cur == 0) ? k1 : k0;
-    uint32_t* vout = (cur == 0) ? v1 : v0;
+    uint32_t* kout = (p & 1) ? k1 : k0;
+    uint32_t* vout = (p & 1) ? v1 : v0;
     if (large)
       hipLaunchKernelGGL(rx_count<kRItemsLarge>, dim3(grid), dim3(kRThreads), 0, s, kin,
                          keys_in, n, shift, width, plan, p, nchunks, per, counts);
@@ -337,9 +339,8 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
                          counts, totals, last ? tinfo : nullptr, nt_out, rect_out);
     kin = kout;
     vin = vout;
-    cur = (cur == 0) ? 1 : 0;
   }
-  return cur;
+  return (passes - 1) & 1;
 }
 
 }  // namespace
@@ -356,17 +357,17 @@ int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
     shifts[p] = shift;
     shift += widths[p];
   }
-  return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, passes, shifts, widths, nullptr,
+  return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, 0, passes, shifts, widths, nullptr,
                     counts, nullptr, nullptr, nullptr, s);
 }
 
 int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
                        uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
-                       const uint32_t* plan, uint32_t* counts, const uint4* tinfo,
-                       uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
-  if (n <= 0) return 0;
-  return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, kPlanPasses, nullptr, nullptr, plan,
-                    counts, tinfo, nt_out, rect_out, s);
+                       const uint32_t* plan, int first_pass, uint32_t* counts,
+                       const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
+  if (n <= 0) return 1;
+  return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, first_pass, kPlanPasses, nullptr,
+                    nullptr, plan, counts, tinfo, nt_out, rect_out, s);
 }
 
 }  // namespace nxs

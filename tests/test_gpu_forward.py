@@ -70,24 +70,47 @@ def test_multi_view_uneven_sizes(R):
             parity.compare_view(out[v], sc, cam, model, background=(0.2, 0.3, 0.4))
 
 
-@pytest.mark.parametrize("near,far", [(2.1, 15.0), (0.4, 60.0)])
-def test_depth_sort_plans(R, near, far):
-    """The depth sort takes three digits (9, 8, 8 bits) when the visible
-    depths differ in at most 27 bits (2.1 .. 15: 25 bits) and four when they
-    differ in more (0.4 .. 60: 31 bits); the 320x240 view has 300 16x16
-    tiles, so the tile sort is one 9-bit pass.  All bit-exact."""
+def _depth_range_scene(near, far):
     rng = np.random.default_rng(11)
     sc = synth.random_scene(11, 3000, sh_degree=0, log_scale=(-3.0, 0.3))
     z = rng.uniform(near, far, sc.n)
     sc.means[:, 0] = rng.uniform(-0.6, 0.6, sc.n) * z
     sc.means[:, 1] = rng.uniform(-0.45, 0.45, sc.n) * z
     sc.means[:, 2] = z - 3.0
+    return sc
+
+
+@pytest.mark.parametrize("near,far", [(2.1, 15.0), (0.4, 60.0)])
+def test_depth_sort_plans(R, near, far):
+    """The depth sort takes three digits (9, 8, 8 bits) when the visible
+    depths differ in at most 27 bits (2.1 .. 15: 25 bits) and four when they
+    differ in more (0.4 .. 60: 31 bits); the 320x240 view has 300 16x16
+    tiles, so the tile sort is one 9-bit pass.  All bit-exact."""
+    sc = _depth_range_scene(near, far)
     cam = synth.look_at_camera((0, 0, -3), width=320, height=240)
     px = parity.sample_pixels(cam, 4000, seed=3)
     for model in (0, 1):
         out = _render(R, sc, [cam], model)
         parity.compare_keys(R, sc, [cam])
         parity.compare_view(out[0], sc, cam, model, pixels=px)
+
+
+def test_depth_sort_plan_changes_between_renders():
+    """A context launches the depth-sort passes its previous render needed:
+    three after a 25-bit scene.  A following 31-bit scene needs four, which
+    the host sees after reading the counters: it sorts and emits again.
+    Alternating the two scenes keeps every instance list bit-exact."""
+    from paper_2603_02887_amd import nxs
+    r = nxs.Renderer(0)
+    try:
+        cam = synth.look_at_camera((0, 0, -3), width=96, height=80)
+        narrow, wide = _depth_range_scene(2.1, 15.0), _depth_range_scene(0.4, 60.0)
+        for sc in (narrow, narrow, wide, wide, narrow, wide):
+            out = _render(r, sc, [cam], 1)
+            parity.compare_keys(r, sc, [cam])
+            parity.compare_view(out[0], sc, cam, 1, pixels=parity.sample_pixels(cam, 600))
+    finally:
+        r.close()
 
 
 def test_sh_degree3_and_background(R):

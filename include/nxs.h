@@ -132,15 +132,19 @@ typedef struct {
 } nxs_render_opts;
 
 /* How the composite's work is laid onto the GPU (results are bitwise the same
- * under all three; only the time differs):
- *   TILES   one work-group per tile, one wave per 8x8 block of it
- *   BLOCKS  one single-wave work-group per 8x8 block
- *   QUEUE   persistent single-wave work-groups taking blocks from one atomic
- *           queue over all views' tiles, longest tile lists first */
+ * under all four; only the time differs):
+ *   TILES       one work-group per tile, one wave per 8x8 block of it
+ *   BLOCKS      one single-wave work-group per 8x8 block
+ *   QUEUE       the 8x8 blocks of all views' tiles in one queue ordered by
+ *               decreasing tile-list length, consumed in order by the
+ *               hardware dispatcher (single-wave work-group k takes item k)
+ *   PERSISTENT  a fixed grid of single-wave work-groups taking whole tiles
+ *               of that order from atomic counters (one per XCD) */
 typedef enum {
   NXS_SCHED_TILES = 1,
   NXS_SCHED_BLOCKS = 2,
-  NXS_SCHED_QUEUE = 3
+  NXS_SCHED_QUEUE = 3,
+  NXS_SCHED_PERSISTENT = 4
 } nxs_schedule;
 
 /* Per-view outputs (device pointers), row-major:

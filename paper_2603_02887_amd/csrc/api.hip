@@ -257,8 +257,8 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   if (!((tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 8)))
     return fail(ctx, NXS_EINVAL, "tile size %dx%d not supported (8x8, 16x16, 32x8)", tw, th);
   const int sched = opts->schedule ? opts->schedule : NXS_SCHED_TILES;
-  if (sched < NXS_SCHED_TILES || sched > NXS_SCHED_QUEUE)
-    return fail(ctx, NXS_EINVAL, "schedule %d not supported (0..3)", opts->schedule);
+  if (sched < NXS_SCHED_TILES || sched > NXS_SCHED_PERSISTENT)
+    return fail(ctx, NXS_EINVAL, "schedule %d not supported (0..4)", opts->schedule);
   int batch = opts->lds_batch ? opts->lds_batch : 256;
   if (batch != 128 && batch != 256 && batch != 512)
     return fail(ctx, NXS_EINVAL, "lds_batch must be 0, 128, 256 or 512");
@@ -448,9 +448,9 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   // (the composite gathers the records of the sorted slots batch by batch)
   CompositeLaunch cl{sched, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),
                      inst_val, proj.rec, nullptr, nullptr, ctx->n_cu};
-  if (sched == NXS_SCHED_QUEUE) {
+  if (sched == NXS_SCHED_QUEUE || sched == NXS_SCHED_PERSISTENT) {
     if ((st = ensure(ctx, ctx->order, 4 * (size_t)total_tiles))) return st;
-    if ((st = ensure(ctx, ctx->queue, 4))) return st;
+    if ((st = ensure(ctx, ctx->queue, 4 * kQueues))) return st;
     cl.order = P<uint32_t>(ctx->order);
     cl.queue = P<uint32_t>(ctx->queue);
   }
@@ -557,7 +557,7 @@ nxs_status nxs_autotune(nxs_context* ctx, const nxs_gaussians* g, const nxs_came
   nxs_tuning best{0, 0, 0, 0.0f};
   nxs_status st = NXS_OK;
   for (int sh = 0; sh < 3 && st == NXS_OK; ++sh) {
-    for (int sc = NXS_SCHED_TILES; sc <= NXS_SCHED_QUEUE && st == NXS_OK; ++sc) {
+    for (int sc = NXS_SCHED_TILES; sc <= NXS_SCHED_PERSISTENT && st == NXS_OK; ++sc) {
       nxs_render_opts o = *opts;
       o.tile_w = shapes[sh][0];
       o.tile_h = shapes[sh][1];

@@ -20,14 +20,21 @@
 //   L += E p, overdraw += 1 for every composited splat.
 // A wave leaves the tile when a ballot finds all its pixels stopped.
 //
-// Three schedules of the same per-block work, with bitwise-identical results:
+// Four schedules of the same per-block work, with bitwise-identical results:
 //   tile WGs     one work-group per tile, one wave per 8x8 block of it;
 //   block waves  one single-wave work-group per 8x8 block, so the dispatcher
 //                refills a wave slot as soon as any block finishes;
-//   persistent   a fixed grid of single-wave work-groups, each taking the next
-//                block from a global atomic queue over all views' tiles, in
-//                an order with the longest tile lists first (their blocks
-//                start early instead of forming the tail).
+//   queue        the blocks of all views' tiles in one queue ordered by
+//                decreasing tile-list length (the longest start early
+//                instead of forming the tail), consumed in order by the
+//                hardware dispatcher: work-group k takes queue item k;
+//   persistent   a fixed grid of single-wave work-groups taking whole tiles
+//                (their 8x8 blocks one after another) from atomic counters
+//                over the same order; one counter per XCD, each serving
+//                every eighth tile, so a ticket is contended only within one
+//                XCD.  Measured slower than the dispatcher on this GPU (a
+//                contended device-scope atomic per ticket); kept for callers
+//                that want a fixed grid.
 // The first two give each XCD a contiguous band of tiles.
 #include "nxs_internal.h"
 #include "nxs_ops.h"
@@ -169,32 +176,74 @@ __global__ __launch_bounds__(64) void composite_blocks_kernel(
                                         stage, item / B, (int)(item % B), threadIdx.x);
 }
 
-// Work item k of the queue is block (k mod B) of tile order[k / B].
+// Item k of the ordered queue is block (k mod B) of tile order[k / B].
+template <int MODEL, int TW, int TH, bool STATE>
+__global__ __launch_bounds__(64) void composite_ordered_kernel(
+    const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
+    float4* __restrict__ pstate, const uint32_t* __restrict__ order, uint32_t n_items) {
+  __shared__ float4 stage[kStageF4];
+  constexpr int B = kBlocksPerTile(TW, TH);
+  const uint32_t k = blockIdx.x;
+  if (k >= n_items) return;
+  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
+                                        stage, order[k / B], (int)(k % B), threadIdx.x);
+}
+
+// Queue q (the work-group's XCD under round-robin dispatch) hands out the
+// tiles order[q], order[q + 8], ...; the wave composites each tile's blocks in
+// turn.  Every queue has work-groups (the grid is a multiple of 8), and every
+// wave leaves once its queue is drained.
 template <int MODEL, int TW, int TH, bool STATE>
 __global__ __launch_bounds__(64) void composite_queue_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
-    float4* __restrict__ pstate, const uint32_t* __restrict__ order, uint32_t n_items,
+    float4* __restrict__ pstate, const uint32_t* __restrict__ order, uint32_t n_tiles,
     uint32_t* __restrict__ queue) {
   __shared__ float4 stage[kStageF4];
   constexpr int B = kBlocksPerTile(TW, TH);
   const int lane = threadIdx.x;
+  const uint32_t q = blockIdx.x % kQueues;
   for (;;) {
     uint32_t k = 0;
-    if (lane == 0) k = atomicAdd(queue, 1u);
+    if (lane == 0) k = atomicAdd(queue + q, 1u);
     k = __builtin_amdgcn_readfirstlane(k);   // lane 0's ticket, wave-uniform
-    if (k >= n_items) break;        // every wave ends once the queue is drained
-    composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
-                                          stage, order[k / B], (int)(k % B), lane);
+    const uint64_t i = (uint64_t)k * kQueues + q;
+    if (i >= n_tiles) break;
+    const uint32_t tile = order[i];
+    for (int b = 0; b < B; ++b)
+      composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
+                                            stage, tile, b, lane);
   }
 }
 
 // Tiles in order of decreasing list length, bucketed by floor(log2(length)):
 // a single work-group counts the buckets in LDS, scans them (longest first) and
-// scatters the tile ids.  Order within a bucket is whatever the LDS atomics
-// give; it only changes which wave runs a block, not any result.
+// scatters the tile ids.  Within a wave, lanes with equal buckets are matched
+// by ballots and add to the bucket with one LDS atomic (most tiles share a few
+// buckets, so per-lane atomics would serialise).  Order within a bucket is
+// whatever the atomics give; it only changes which wave runs a tile, not any
+// result.
 constexpr int kOrderThreads = 1024;
 constexpr int kBuckets = 33;
+constexpr int kBucketBits = 6;
+
+__device__ __forceinline__ uint32_t length_bucket(const uint2 r) {
+  const uint32_t len = r.y - r.x;
+  return len ? 32u - (uint32_t)__clz(len) : 0u;   // 0 for empty, else 1 + floor(log2)
+}
+
+// lanes of the wave (valid ones only) whose bucket equals this lane's
+__device__ __forceinline__ uint64_t bucket_peers(uint32_t b, bool valid) {
+  uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
+#pragma unroll
+  for (int k = 0; k < kBucketBits; ++k) {
+    const bool bit = (b >> k) & 1u;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
 
 __global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(
     const uint2* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ order,
@@ -202,29 +251,39 @@ __global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(
   __shared__ uint32_t cnt[kBuckets];
   __shared__ uint32_t pos[kBuckets];
   const uint32_t t = threadIdx.x;
+  const int lane = (int)(t & 63);
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   if (t < kBuckets) cnt[t] = 0;
-  if (t == 0) *queue = 0u;          // the queue of the composite that follows
+  if (t < kQueues) queue[t] = 0u;   // the queues of the composite that follows
   __syncthreads();
-  for (uint32_t i = t; i < n_tiles; i += kOrderThreads) {
-    const uint2 r = ranges[i];
-    const uint32_t len = r.y - r.x;
-    const int b = len ? 32 - __clz(len) : 0;      // 0 for empty, else 1 + floor(log2)
-    atomicAdd(&cnt[b], 1u);
+  for (uint32_t i0 = 0; i0 < n_tiles; i0 += kOrderThreads) {
+    const uint32_t i = i0 + t;
+    const bool valid = i < n_tiles;
+    const uint32_t b = valid ? length_bucket(ranges[i]) : 0u;
+    const uint64_t peers = bucket_peers(b, valid);
+    if (valid && (peers & lt_mask) == 0) atomicAdd(&cnt[b], (uint32_t)__popcll(peers));
   }
   __syncthreads();
   if (t == 0) {
     uint32_t run = 0;
-    for (int b = kBuckets - 1; b >= 0; --b) {
-      pos[b] = run;
-      run += cnt[b];
+    for (int k = kBuckets - 1; k >= 0; --k) {
+      pos[k] = run;
+      run += cnt[k];
     }
   }
   __syncthreads();
-  for (uint32_t i = t; i < n_tiles; i += kOrderThreads) {
-    const uint2 r = ranges[i];
-    const uint32_t len = r.y - r.x;
-    const int b = len ? 32 - __clz(len) : 0;
-    order[atomicAdd(&pos[b], 1u)] = i;
+  for (uint32_t i0 = 0; i0 < n_tiles; i0 += kOrderThreads) {
+    const uint32_t i = i0 + t;
+    const bool valid = i < n_tiles;
+    const uint32_t b = valid ? length_bucket(ranges[i]) : 0u;
+    const uint64_t peers = bucket_peers(b, valid);
+    const bool leader = valid && (peers & lt_mask) == 0;
+    uint32_t base = 0;
+    if (leader) base = atomicAdd(&pos[b], (uint32_t)__popcll(peers));
+    // every lane takes its leader's base (the lowest lane among its peers)
+    const int src = valid ? __builtin_ctzll(peers) : lane;
+    base = (uint32_t)__shfl((int)base, src, 64);
+    if (valid) order[base + (uint32_t)__popcll(peers & lt_mask)] = i;
   }
 }
 
@@ -243,14 +302,21 @@ void launch_s(const CompositeLaunch& L, const CompositeParams& p, float4* pstate
     hipLaunchKernelGGL((composite_blocks_kernel<MODEL, TW, TH, STATE>), dim3(per * 8),
                        dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
                        pstate, (uint32_t)items, per);
-  } else {
+  } else if (L.schedule == NXS_SCHED_QUEUE) {
     hipLaunchKernelGGL(order_tiles_kernel, dim3(1), dim3(kOrderThreads), 0, s, L.ranges,
                        (uint32_t)L.n_tiles, L.order, L.queue);
     const int64_t items = L.n_tiles * B;
-    const int64_t grid = std::min<int64_t>(items, (int64_t)L.n_cu * kQueueWavesPerCU);
+    hipLaunchKernelGGL((composite_ordered_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)items),
+                       dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
+                       pstate, L.order, (uint32_t)items);
+  } else {
+    hipLaunchKernelGGL(order_tiles_kernel, dim3(1), dim3(kOrderThreads), 0, s, L.ranges,
+                       (uint32_t)L.n_tiles, L.order, L.queue);
+    int64_t grid = std::min<int64_t>(L.n_tiles, (int64_t)L.n_cu * kQueueWavesPerCU);
+    grid = std::max<int64_t>((grid + kQueues - 1) / kQueues, 1) * kQueues;
     hipLaunchKernelGGL((composite_queue_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)grid),
                        dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
-                       pstate, L.order, (uint32_t)items, L.queue);
+                       pstate, L.order, (uint32_t)L.n_tiles, L.queue);
   }
 }
 

@@ -131,9 +131,10 @@ struct CompositeParams {
 //   (L0, L1, L2, T_final), (E_k, tau_k), (U, 0) with E_k the saturating splat's
 //   emission (background if none), tau_k the optical depth before it and
 //   U = sum_{j<k} E_j alpha_j.
-// Composite launch geometry.  schedule: NXS_SCHED_TILES, NXS_SCHED_BLOCKS or
-// NXS_SCHED_QUEUE (which also needs `order` [n_tiles] and the 4-byte `queue`
-// counter as scratch, and the CU count to size its grid).
+// Composite launch geometry.  schedule: NXS_SCHED_TILES, NXS_SCHED_BLOCKS,
+// NXS_SCHED_QUEUE or NXS_SCHED_PERSISTENT (the last two also need `order`
+// [n_tiles] and kQueues u32 queue counters as scratch; the persistent one
+// sizes its grid from the CU count).
 struct CompositeLaunch {
   int schedule;
   int tile_w, tile_h;
@@ -148,6 +149,7 @@ struct CompositeLaunch {
   int n_cu;
 };
 constexpr int kQueueWavesPerCU = 32;
+constexpr int kQueues = 8;   // one per XCD
 void launch_composite(int model, const CompositeLaunch& L, const CompositeParams& p,
                       float4* pstate, hipStream_t s);
 

@@ -63,7 +63,7 @@ class Tuning(ctypes.Structure):
                 ("ms", c_float)]
 
 
-SCHEDULES = {"tiles": 1, "blocks": 2, "queue": 3}
+SCHEDULES = {"tiles": 1, "blocks": 2, "queue": 3, "persistent": 4}
 
 
 class Image(ctypes.Structure):

@@ -1,6 +1,7 @@
 """Composite schedules, batched multi-view renders and the autotuner (GPU).
 
-Every schedule (tile work-groups, single-wave blocks, persistent queue) and a
+Every schedule (tile work-groups, single-wave blocks, the longest-first queue
+consumed by the dispatcher, the persistent grid on atomic counters) and a
 batched multi-view render must give results bitwise equal to each other and
 to one render per view: they change only which wave runs a block and when,
 never a pixel's sequence of float32 operations.
@@ -50,14 +51,14 @@ def test_schedules_bitwise_equal(R, tile, model):
     g = nxs.scene_to_device(sc)
     kw = {"tile": tile, "model": model, "param": 0.5 if model == 6 else 0.0}
     ref = R.render(g, cams, schedule="tiles", **kw)
-    for sched in ("blocks", "queue"):
+    for sched in ("blocks", "queue", "persistent"):
         out = R.render(g, cams, schedule=sched, **kw)
         torch.cuda.synchronize()
         for a, b in zip(ref, out):
             _same(a, b)
 
 
-@pytest.mark.parametrize("sched", ["tiles", "blocks", "queue"])
+@pytest.mark.parametrize("sched", ["tiles", "blocks", "queue", "persistent"])
 def test_batched_equals_per_view(R, sched):
     from paper_2603_02887_amd import nxs
     sc, cams = _uneven_views()
@@ -70,8 +71,9 @@ def test_batched_equals_per_view(R, sched):
         _same(batched[v], one[0])
 
 
-def test_queue_schedule_against_oracle(R):
-    """The persistent queue on ragged multi-view input, checked against the oracle."""
+@pytest.mark.parametrize("sched", ["queue", "persistent"])
+def test_queue_schedule_against_oracle(R, sched):
+    """The queue schedules on ragged multi-view input, checked against the oracle."""
     from paper_2603_02887_amd import nxs
     sc, cams = _uneven_views()
     g = nxs.scene_to_device(sc)
@@ -79,15 +81,16 @@ def test_queue_schedule_against_oracle(R):
     # passes near t_eps, or near float32 underflow without it, at many pixels,
     # where either decision is correct; its schedules are checked bitwise above)
     for model in (1, 2, 3):
-        out = R.render(g, cams, model=model, schedule="queue", tile=(32, 8))
+        out = R.render(g, cams, model=model, schedule=sched, tile=(32, 8))
         torch.cuda.synchronize()
         for v in (0, 4):
             parity.compare_view(out[v], sc, cams[v], model,
                                 pixels=parity.sample_pixels(cams[v], 300, seed=v))
 
 
-def test_queue_schedule_empty_tiles_and_repeat(R):
-    """Views where most tiles are empty, run twice: the queue restarts at zero."""
+@pytest.mark.parametrize("sched", ["queue", "persistent"])
+def test_queue_schedule_empty_tiles_and_repeat(R, sched):
+    """Views where most tiles are empty, run twice: the queues restart at zero."""
     from paper_2603_02887_amd import nxs
     sc = synth.random_scene(5, 40, log_scale=(-3.0, 0.3))
     cams = [synth.look_at_camera((0, 0, -3), width=300, height=200),
@@ -95,7 +98,7 @@ def test_queue_schedule_empty_tiles_and_repeat(R):
     g = nxs.scene_to_device(sc)
     ref = R.render(g, cams, model=0, schedule="tiles")
     for _ in range(2):
-        out = R.render(g, cams, model=0, schedule="queue")
+        out = R.render(g, cams, model=0, schedule=sched)
         torch.cuda.synchronize()
         for a, b in zip(ref, out):
             _same(a, b)
@@ -116,7 +119,7 @@ def test_autotune_and_cache(R, tmp_path):
     path = tmp_path / "tune.txt"
     t = R.autotune(g, cams, model=0, cache_path=path, reps=3)
     assert t["tile"] in ((8, 8), (16, 16), (32, 8))
-    assert t["schedule"] in ("tiles", "blocks", "queue") and t["ms"] > 0
+    assert t["schedule"] in ("tiles", "blocks", "queue", "persistent") and t["ms"] > 0
     lines = path.read_text().splitlines()
     assert len(lines) == 1 and lines[0].split()[1:4] == [str(t["tile"][0]), str(t["tile"][1]),
                                                          str(nxs.SCHEDULES[t["schedule"]])]

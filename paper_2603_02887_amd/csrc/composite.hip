@@ -100,9 +100,9 @@ __device__ __forceinline__ void composite_block(
     const uint32_t n = stage_batch(fetched, sb, wlds);
     fetched = stage_records(slots, rec);                              // batch base + 64
     slots = stage_slot(inst_val, (uint64_t)base + 128, rg.y, lane);   // batch base + 128
-    for (uint32_t k = 0; k < n; ++k) {
-      const float4 q0 = wlds[3 * k + 0], q1 = wlds[3 * k + 1];
-      const float c[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, wlds[3 * k + 2].x};
+    for (const float4 *r = wlds, *r_end = wlds + 3 * n; r != r_end; r += 3) {
+      const float4 q0 = r[0], q1 = r[1];
+      const float c[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, r[2].x};
       const float dx = fx - c[0], dy = fy - c[1];
       const float e = fmaf(dx, fmaf(c[2], dx, c[3] * dy), fmaf(c[4] * dy, dy, c[5]));
       const bool valid = (e >= amin) && !op.stopped(t_eps);

@@ -128,16 +128,16 @@ typedef struct {
                              composite walks its tile in batches of 64 splats) */
   float param;            /* operator parameter of models 4..7 (c, gamma or v) */
   int32_t keep_state;     /* nonzero: keep what nxs_render_backward needs */
-  int32_t schedule;       /* nxs_schedule of the composite; 0 -> NXS_SCHED_TILES */
+  int32_t schedule;       /* nxs_schedule of the composite; 0 -> NXS_SCHED_QUEUE */
 } nxs_render_opts;
 
 /* How the composite's work is laid onto the GPU (results are bitwise the same
  * under all four; only the time differs):
  *   TILES       one work-group per tile, one wave per 8x8 block of it
  *   BLOCKS      one single-wave work-group per 8x8 block
- *   QUEUE       the 8x8 blocks of all views' tiles in one queue ordered by
- *               decreasing tile-list length, consumed in order by the
- *               hardware dispatcher (single-wave work-group k takes item k)
+ *   QUEUE       all views' tiles in one queue ordered by decreasing
+ *               tile-list length, consumed in order by the hardware
+ *               dispatcher (single-wave work-groups, one per 8x8 block)
  *   PERSISTENT  a fixed grid of single-wave work-groups taking whole tiles
  *               of that order from atomic counters (one per XCD) */
 typedef enum {
@@ -297,7 +297,8 @@ const char* nxs_last_error(const nxs_context* ctx);
  * on its stream between its stages; nxs_inspect_stage_times then returns the
  * milliseconds of the last render's stages, in this order:
  *   0 projection, 1 depth sort, 2 instance emission, 3 tile sort,
- *   4 tile ranges, 5 composite (with the gather of the splats it reaches).
+ *   4 tile ranges (and the tile order of the queue schedules), 5 composite
+ *   (with the gather of the splats it reaches).
  * ms_host has n >= NXS_N_STAGES entries.  Waits for the last render. */
 #define NXS_N_STAGES 6
 nxs_status nxs_set_timing(nxs_context* ctx, int32_t enable);

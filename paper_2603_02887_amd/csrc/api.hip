@@ -31,7 +31,7 @@ struct nxs_context {
   DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, tinfo, nt_sorted, rect_sorted, prec;
   DevBuf scan_local, block_sums, counts;
   DevBuf inst_tile, inst_tile_alt, inst_val, inst_val_alt;
-  DevBuf ranges, pstate, gslot, order, queue;
+  DevBuf ranges, pstate, gslot, order;
   int n_cu = 256;
   std::string arch;
   size_t ws_limit = 0;   // 0: no limit on the workspace
@@ -58,6 +58,7 @@ struct nxs_context {
   // first depth-sort pass to launch: 1 while the last render's plan left
   // pass 0 inactive (at most 27 varying depth bits), else 0
   int depth_first = 0;
+  const uint32_t* bwd_order = nullptr;
   int32_t last_n = 0, last_views = 0;
   uint32_t* last_inst_tile = nullptr;
   uint32_t* last_inst_val = nullptr;
@@ -215,7 +216,7 @@ nxs_status nxs_destroy(nxs_context* ctx) {
                    &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
                    &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->ranges,
-                   &ctx->pstate,     &ctx->gslot,         &ctx->order,     &ctx->queue};
+                   &ctx->pstate,     &ctx->gslot,         &ctx->order};
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
@@ -256,7 +257,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   int tw = opts->tile_w ? opts->tile_w : 16, th = opts->tile_h ? opts->tile_h : 16;
   if (!((tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 8)))
     return fail(ctx, NXS_EINVAL, "tile size %dx%d not supported (8x8, 16x16, 32x8)", tw, th);
-  const int sched = opts->schedule ? opts->schedule : NXS_SCHED_TILES;
+  const int sched = opts->schedule ? opts->schedule : NXS_SCHED_QUEUE;
   if (sched < NXS_SCHED_TILES || sched > NXS_SCHED_PERSISTENT)
     return fail(ctx, NXS_EINVAL, "schedule %d not supported (0..4)", opts->schedule);
   int batch = opts->lds_batch ? opts->lds_batch : 256;
@@ -332,7 +333,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
       (st = ensure(ctx, ctx->prec, 48 * S)) || (st = ensure(ctx, ctx->scan_local, 4 * S)) ||
       (st = ensure(ctx, ctx->block_sums, 4 * scan_blocks_size(S))) ||
       (st = ensure(ctx, ctx->counts, 4 * radix_counts_words(S))) ||
-      (st = ensure(ctx, ctx->ranges, 8 * total_tiles)))
+      (st = ensure(ctx, ctx->ranges, 8 * total_tiles + 4 * kSchedCounters)))
     return st;
   ProjDev proj{P<uint32_t>(ctx->depth_key), P<uint4>(ctx->tinfo), P<float4>(ctx->prec)};
   GaussDev gd{g->means, g->scales, g->quats, g->opacities, g->sh, g->n, g->sh_degree};
@@ -343,9 +344,11 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   };
   ctx->ev_valid = false;
   HIP_TRY(mark(0));
-  // (also clears the tile ranges)
+  // (also clears the tile ranges and, after them, the composite schedules'
+  // counters)
   launch_project(gd, dviews, n_views, kappa2, alpha_min, tw, th, proj,
-                 P<uint4>(ctx->partials), dcount, P<uint32_t>(ctx->ranges), 2 * total_tiles, s);
+                 P<uint4>(ctx->partials), dcount, P<uint32_t>(ctx->ranges),
+                 2 * total_tiles + kSchedCounters, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(1));
   // The instance count M is read by the host only where it sizes buffers and
@@ -428,8 +431,16 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   } else {
     HIP_TRY(mark(5));
   }
-  HIP_TRY(mark(6));
-  // 5. composite (also writes the background where no splat lands)
+  // 4b. the tile order of the queue schedules (longest tile lists first)
+  // (the composite gathers the records of the sorted slots batch by batch)
+  CompositeLaunch cl{sched, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),
+                     inst_val, proj.rec, nullptr, nullptr, ctx->n_cu};
+  if (sched == NXS_SCHED_QUEUE || sched == NXS_SCHED_PERSISTENT) {
+    if ((st = ensure(ctx, ctx->order, 8 * (size_t)total_tiles))) return st;
+    cl.order = P<uint32_t>(ctx->order);
+    cl.sched_counters = P<uint32_t>(ctx->ranges) + 2 * total_tiles;
+    launch_composite_order(cl, s);
+  }
   float4* pstate = nullptr;
   if (opts->keep_state) {
     if ((st = ensure(ctx, ctx->pstate, 48 * (size_t)pix_off))) return st;
@@ -445,15 +456,8 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   cp.param = param;
   for (int k = 0; k < 3; ++k) cp.bg[k] = opts->background[k];
   cp.lds_batch = batch;
-  // (the composite gathers the records of the sorted slots batch by batch)
-  CompositeLaunch cl{sched, tw, th, total_tiles, dviews, n_views, P<uint2>(ctx->ranges),
-                     inst_val, proj.rec, nullptr, nullptr, ctx->n_cu};
-  if (sched == NXS_SCHED_QUEUE || sched == NXS_SCHED_PERSISTENT) {
-    if ((st = ensure(ctx, ctx->order, 4 * (size_t)total_tiles))) return st;
-    if ((st = ensure(ctx, ctx->queue, 4 * kQueues))) return st;
-    cl.order = P<uint32_t>(ctx->order);
-    cl.queue = P<uint32_t>(ctx->queue);
-  }
+  HIP_TRY(mark(6));
+  // 5. composite (also writes the background where no splat lands)
   launch_composite(opts->model, cl, cp, pstate, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(7));
@@ -466,6 +470,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
     ctx->bwd_tw = tw;
     ctx->bwd_th = th;
     ctx->bwd_cp = cp;
+    ctx->bwd_order = cl.order;   // the tile order, if the schedule made one
     ctx->bwd_views.assign(ctx->host_views, ctx->host_views + n_views);
   }
   ctx->ev_valid = ctx->timing;
@@ -514,8 +519,7 @@ nxs_status nxs_render_backward(nxs_context* ctx, const float* const* dL_drgb,
   launch_composite_bwd(ctx->bwd_model, ctx->bwd_tw, ctx->bwd_th, ctx->last_tiles,
                        P<ViewDev>(ctx->views), n_views, P<uint2>(ctx->ranges),
                        ctx->last_inst_val, P<float4>(ctx->prec), ctx->bwd_cp,
-                       P<float4>(ctx->pstate),
-                       P<float>(ctx->gslot), s);
+                       P<float4>(ctx->pstate), P<float>(ctx->gslot), ctx->bwd_order, s);
   GaussDev gd{g.means, g.scales, g.quats, g.opacities, g.sh, g.n, g.sh_degree};
   GaussGradDev gg{grads->means, grads->scales, grads->quats, grads->opacities, grads->sh};
   launch_project_bwd(gd, P<ViewDev>(ctx->views), n_views, P<float>(ctx->gslot), gg, s);
@@ -606,7 +610,7 @@ nxs_status nxs_release_workspace(nxs_context* ctx) {
                    &ctx->prec,       &ctx->scan_local,
                    &ctx->block_sums, &ctx->counts,        &ctx->inst_tile, &ctx->inst_tile_alt,
                    &ctx->inst_val,   &ctx->inst_val_alt,  &ctx->ranges,
-                   &ctx->pstate,     &ctx->gslot,         &ctx->order,     &ctx->queue};
+                   &ctx->pstate,     &ctx->gslot,         &ctx->order};
   for (DevBuf* b : all) {
     if (b->p) HIP_TRY(hipFree(b->p));
     b->p = nullptr;

@@ -61,11 +61,14 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
     const float4* __restrict__ pstate, float* __restrict__ gslot, uint32_t n_tiles,
-    uint32_t per_xcd) {
+    uint32_t per_xcd, const uint32_t* __restrict__ order) {
   __shared__ float4 stage[(TW / 8) * (TH / 8) * kStageF4];
   __shared__ float4 rsum[(TW / 8) * (TH / 8) * 12];   // per wave: 4 rows x 9 sums
-  const uint32_t tile = xcd_banded(blockIdx.x, per_xcd);
-  if (tile >= n_tiles) return;
+  // the forward's order (longest tile lists first) when it made one, else
+  // each XCD a contiguous band of tiles
+  const uint32_t w = order ? blockIdx.x : xcd_banded(blockIdx.x, per_xcd);
+  if (w >= n_tiles) return;
+  const uint32_t tile = order ? order[w] : w;
   int vi = 0;
   {
     int lo = 0, hi = n_views - 1;
@@ -430,23 +433,27 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
 template <int MODEL, int TW, int TH>
 void bwd_t(int64_t n_tiles, const ViewDev* views, int n_views, const uint2* ranges,
            const uint32_t* inst_val, const float4* rec, const CompositeParams& p,
-           const float4* pstate, float* gslot, hipStream_t s) {
+           const float4* pstate, float* gslot, const uint32_t* order, hipStream_t s) {
   const uint32_t per = (uint32_t)((n_tiles + 7) / 8);
   hipLaunchKernelGGL((composite_bwd_kernel<MODEL, TW, TH>), dim3(per * 8), dim3(TW * TH), 0, s,
                      views, n_views, ranges, inst_val, rec, p, pstate, gslot,
-                     (uint32_t)n_tiles, per);
+                     (uint32_t)n_tiles, per, order);
 }
 
 template <int MODEL>
 void bwd_m(int tile_w, int tile_h, int64_t n_tiles, const ViewDev* views, int n_views,
            const uint2* ranges, const uint32_t* inst_val, const float4* rec,
-           const CompositeParams& p, const float4* pstate, float* gslot, hipStream_t s) {
+           const CompositeParams& p, const float4* pstate, float* gslot, const uint32_t* order,
+           hipStream_t s) {
   if (tile_w == 8 && tile_h == 8)
-    bwd_t<MODEL, 8, 8>(n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, gslot, s);
+    bwd_t<MODEL, 8, 8>(n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, gslot, order,
+                       s);
   else if (tile_w == 32 && tile_h == 8)
-    bwd_t<MODEL, 32, 8>(n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, gslot, s);
+    bwd_t<MODEL, 32, 8>(n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, gslot, order,
+                        s);
   else
-    bwd_t<MODEL, 16, 16>(n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, gslot, s);
+    bwd_t<MODEL, 16, 16>(n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, gslot,
+                         order, s);
 }
 
 }  // namespace
@@ -454,13 +461,14 @@ void bwd_m(int tile_w, int tile_h, int64_t n_tiles, const ViewDev* views, int n_
 void launch_composite_bwd(int model, int tile_w, int tile_h, int64_t n_tiles,
                           const ViewDev* views, int n_views, const uint2* ranges,
                           const uint32_t* inst_val, const float4* rec, const CompositeParams& p,
-                          const float4* pstate, float* gslot, hipStream_t s) {
+                          const float4* pstate, float* gslot, const uint32_t* order,
+                          hipStream_t s) {
   if (n_tiles <= 0) return;
   switch (model) {
 #define NXS_B(M)                                                                        \
   case M:                                                                               \
     bwd_m<M>(tile_w, tile_h, n_tiles, views, n_views, ranges, inst_val, rec, p, pstate, \
-             gslot, s);                                                                 \
+             gslot, order, s);                                                          \
     break;
     NXS_B(0) NXS_B(1) NXS_B(2) NXS_B(3) NXS_B(4)
 #undef NXS_B

@@ -24,10 +24,11 @@
 //   tile WGs     one work-group per tile, one wave per 8x8 block of it;
 //   block waves  one single-wave work-group per 8x8 block, so the dispatcher
 //                refills a wave slot as soon as any block finishes;
-//   queue        the blocks of all views' tiles in one queue ordered by
-//                decreasing tile-list length (the longest start early
-//                instead of forming the tail), consumed in order by the
-//                hardware dispatcher: work-group k takes queue item k;
+//   queue        all views' tiles in one queue ordered by decreasing
+//                tile-list length (the longest start early instead of
+//                forming the tail), consumed in order by the hardware
+//                dispatcher, one single-wave work-group per 8x8 block, the
+//                blocks of a tile on one XCD;
 //   persistent   a fixed grid of single-wave work-groups taking whole tiles
 //                (their 8x8 blocks one after another) from atomic counters
 //                over the same order; one counter per XCD, each serving
@@ -176,18 +177,22 @@ __global__ __launch_bounds__(64) void composite_blocks_kernel(
                                         stage, item / B, (int)(item % B), threadIdx.x);
 }
 
-// Item k of the ordered queue is block (k mod B) of tile order[k / B].
+// The ordered queue dealt to the 8 XCDs (which receive work-groups
+// round-robin) at tile granularity: work-group w, the i-th on XCD x = w mod 8,
+// takes block (i mod B) of the tile of rank 8 (i / B) + x in the order, so the
+// longest tiles start first on every XCD and each tile's blocks share one L2.
 template <int MODEL, int TW, int TH, bool STATE>
 __global__ __launch_bounds__(64) void composite_ordered_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
-    float4* __restrict__ pstate, const uint32_t* __restrict__ order, uint32_t n_items) {
+    float4* __restrict__ pstate, const uint32_t* __restrict__ order, uint32_t n_tiles) {
   __shared__ float4 stage[kStageF4];
   constexpr int B = kBlocksPerTile(TW, TH);
-  const uint32_t k = blockIdx.x;
-  if (k >= n_items) return;
+  const uint32_t x = blockIdx.x % kQueues, i = blockIdx.x / kQueues;
+  const uint32_t r = (i / B) * kQueues + x;
+  if (r >= n_tiles) return;
   composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
-                                        stage, order[k / B], (int)(k % B), threadIdx.x);
+                                        stage, order[r], (int)(i % B), threadIdx.x);
 }
 
 // Queue q (the work-group's XCD under round-robin dispatch) hands out the
@@ -217,14 +222,14 @@ __global__ __launch_bounds__(64) void composite_queue_kernel(
   }
 }
 
-// Tiles in order of decreasing list length, bucketed by floor(log2(length)):
-// a single work-group counts the buckets in LDS, scans them (longest first) and
-// scatters the tile ids.  Within a wave, lanes with equal buckets are matched
-// by ballots and add to the bucket with one LDS atomic (most tiles share a few
-// buckets, so per-lane atomics would serialise).  Order within a bucket is
-// whatever the atomics give; it only changes which wave runs a tile, not any
-// result.
-constexpr int kOrderThreads = 1024;
+// Tiles in order of decreasing list length, bucketed by floor(log2(length)),
+// in two grid-wide passes: each tile takes a rank within its bucket from a
+// global counter (lanes of a wave with equal buckets are matched by ballots
+// and take one atomic together), then every work-group scans the bucket
+// counts, longest bucket first, and scatters its tiles.  The counters start
+// at zero (cleared with the tile ranges).  Order within a bucket is whatever
+// the atomics give; it only changes which wave runs a tile, not any result.
+constexpr int kOrderThreads = 256;
 constexpr int kBuckets = 33;
 constexpr int kBucketBits = 6;
 
@@ -245,47 +250,56 @@ __device__ __forceinline__ uint64_t bucket_peers(uint32_t b, bool valid) {
   return peers;
 }
 
-__global__ __launch_bounds__(kOrderThreads) void order_tiles_kernel(
-    const uint2* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ order,
-    uint32_t* __restrict__ queue) {
-  __shared__ uint32_t cnt[kBuckets];
-  __shared__ uint32_t pos[kBuckets];
-  const uint32_t t = threadIdx.x;
-  const int lane = (int)(t & 63);
+__global__ __launch_bounds__(kOrderThreads) void order_rank_kernel(
+    const uint2* __restrict__ ranges, uint32_t n_tiles, uint32_t* __restrict__ buckets,
+    uint32_t* __restrict__ rank) {
+  const uint32_t i = blockIdx.x * kOrderThreads + threadIdx.x;
+  const int lane = (int)(threadIdx.x & 63);
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  if (t < kBuckets) cnt[t] = 0;
-  if (t < kQueues) queue[t] = 0u;   // the queues of the composite that follows
-  __syncthreads();
-  for (uint32_t i0 = 0; i0 < n_tiles; i0 += kOrderThreads) {
-    const uint32_t i = i0 + t;
-    const bool valid = i < n_tiles;
-    const uint32_t b = valid ? length_bucket(ranges[i]) : 0u;
-    const uint64_t peers = bucket_peers(b, valid);
-    if (valid && (peers & lt_mask) == 0) atomicAdd(&cnt[b], (uint32_t)__popcll(peers));
-  }
-  __syncthreads();
+  const bool valid = i < n_tiles;
+  const uint32_t b = valid ? length_bucket(ranges[i]) : 0u;
+  const uint64_t peers = bucket_peers(b, valid);
+  const bool leader = valid && (peers & lt_mask) == 0;
+  uint32_t base = 0;
+  if (leader) base = atomicAdd(buckets + b, (uint32_t)__popcll(peers));
+  // every lane takes its leader's base (the lowest lane among its peers)
+  const int src = valid ? __builtin_ctzll(peers) : lane;
+  base = (uint32_t)__shfl((int)base, src, 64);
+  if (valid) rank[i] = base + (uint32_t)__popcll(peers & lt_mask);
+}
+
+__global__ __launch_bounds__(kOrderThreads) void order_scatter_kernel(
+    const uint2* __restrict__ ranges, uint32_t n_tiles, const uint32_t* __restrict__ buckets,
+    const uint32_t* __restrict__ rank, uint32_t* __restrict__ order) {
+  __shared__ uint32_t start[kBuckets];
+  const uint32_t t = threadIdx.x;
   if (t == 0) {
     uint32_t run = 0;
-    for (int k = kBuckets - 1; k >= 0; --k) {
-      pos[k] = run;
-      run += cnt[k];
+    for (int k = kBuckets - 1; k >= 0; --k) {   // longest lists first
+      start[k] = run;
+      run += buckets[k];
     }
   }
   __syncthreads();
-  for (uint32_t i0 = 0; i0 < n_tiles; i0 += kOrderThreads) {
-    const uint32_t i = i0 + t;
-    const bool valid = i < n_tiles;
-    const uint32_t b = valid ? length_bucket(ranges[i]) : 0u;
-    const uint64_t peers = bucket_peers(b, valid);
-    const bool leader = valid && (peers & lt_mask) == 0;
-    uint32_t base = 0;
-    if (leader) base = atomicAdd(&pos[b], (uint32_t)__popcll(peers));
-    // every lane takes its leader's base (the lowest lane among its peers)
-    const int src = valid ? __builtin_ctzll(peers) : lane;
-    base = (uint32_t)__shfl((int)base, src, 64);
-    if (valid) order[base + (uint32_t)__popcll(peers & lt_mask)] = i;
-  }
+  const uint32_t i = blockIdx.x * kOrderThreads + t;
+  if (i < n_tiles) order[start[length_bucket(ranges[i])] + rank[i]] = i;
 }
+
+}  // namespace
+
+void launch_composite_order(const CompositeLaunch& L, hipStream_t s) {
+  if (L.n_tiles <= 0 ||
+      (L.schedule != NXS_SCHED_QUEUE && L.schedule != NXS_SCHED_PERSISTENT))
+    return;
+  const unsigned grid = (unsigned)((L.n_tiles + kOrderThreads - 1) / kOrderThreads);
+  uint32_t* rank = L.order + L.n_tiles;
+  hipLaunchKernelGGL(order_rank_kernel, dim3(grid), dim3(kOrderThreads), 0, s, L.ranges,
+                     (uint32_t)L.n_tiles, L.sched_counters + kQueues, rank);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(grid), dim3(kOrderThreads), 0, s, L.ranges,
+                     (uint32_t)L.n_tiles, L.sched_counters + kQueues, rank, L.order);
+}
+
+namespace {
 
 template <int MODEL, int TW, int TH, bool STATE>
 void launch_s(const CompositeLaunch& L, const CompositeParams& p, float4* pstate,
@@ -303,20 +317,16 @@ void launch_s(const CompositeLaunch& L, const CompositeParams& p, float4* pstate
                        dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
                        pstate, (uint32_t)items, per);
   } else if (L.schedule == NXS_SCHED_QUEUE) {
-    hipLaunchKernelGGL(order_tiles_kernel, dim3(1), dim3(kOrderThreads), 0, s, L.ranges,
-                       (uint32_t)L.n_tiles, L.order, L.queue);
-    const int64_t items = L.n_tiles * B;
-    hipLaunchKernelGGL((composite_ordered_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)items),
+    const int64_t grid = (L.n_tiles + kQueues - 1) / kQueues * kQueues * B;
+    hipLaunchKernelGGL((composite_ordered_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)grid),
                        dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
-                       pstate, L.order, (uint32_t)items);
+                       pstate, L.order, (uint32_t)L.n_tiles);
   } else {
-    hipLaunchKernelGGL(order_tiles_kernel, dim3(1), dim3(kOrderThreads), 0, s, L.ranges,
-                       (uint32_t)L.n_tiles, L.order, L.queue);
     int64_t grid = std::min<int64_t>(L.n_tiles, (int64_t)L.n_cu * kQueueWavesPerCU);
     grid = std::max<int64_t>((grid + kQueues - 1) / kQueues, 1) * kQueues;
     hipLaunchKernelGGL((composite_queue_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)grid),
                        dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
-                       pstate, L.order, (uint32_t)L.n_tiles, L.queue);
+                       pstate, L.order, (uint32_t)L.n_tiles, L.sched_counters);
   }
 }
 

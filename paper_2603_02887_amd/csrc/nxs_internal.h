@@ -133,8 +133,9 @@ struct CompositeParams {
 //   U = sum_{j<k} E_j alpha_j.
 // Composite launch geometry.  schedule: NXS_SCHED_TILES, NXS_SCHED_BLOCKS,
 // NXS_SCHED_QUEUE or NXS_SCHED_PERSISTENT (the last two also need `order`
-// [n_tiles] and kQueues u32 queue counters as scratch; the persistent one
-// sizes its grid from the CU count).
+// [2 n_tiles] as scratch and kSchedCounters u32 counters that are zero at
+// the launch: kQueues queue counters, then the length-bucket counters; the
+// persistent one sizes its grid from the CU count).
 struct CompositeLaunch {
   int schedule;
   int tile_w, tile_h;
@@ -145,21 +146,28 @@ struct CompositeLaunch {
   const uint32_t* inst_val;  // tile-sorted list of projected slots
   const float4* rec;         // the projection's records, per slot
   uint32_t* order;
-  uint32_t* queue;
+  uint32_t* sched_counters;
   int n_cu;
 };
 constexpr int kQueueWavesPerCU = 32;
 constexpr int kQueues = 8;   // one per XCD
+constexpr int kSchedCounters = 64;
+// The tile order the queue schedules consume (longest tile lists first);
+// enqueue before launch_composite for NXS_SCHED_QUEUE and NXS_SCHED_PERSISTENT
+// (does nothing for the others).
+void launch_composite_order(const CompositeLaunch& L, hipStream_t s);
 void launch_composite(int model, const CompositeLaunch& L, const CompositeParams& p,
                       float4* pstate, hipStream_t s);
 
 // Path-replay backward of the composite (models 0..4): per-slot gradients
 // gslot[9 * slot + f] for f = dLoss/d(opacity, u, v, conic A, B, C, r, g, b),
-// accumulated with atomics (the caller zeroes gslot).
+// accumulated with atomics (the caller zeroes gslot).  `order`: the forward's
+// tile order (longest lists first) to walk the tiles in, or null.
 void launch_composite_bwd(int model, int tile_w, int tile_h, int64_t n_tiles,
                           const ViewDev* views, int n_views, const uint2* ranges,
                           const uint32_t* inst_val, const float4* rec, const CompositeParams& p,
-                          const float4* pstate, float* gslot, hipStream_t s);
+                          const float4* pstate, float* gslot, const uint32_t* order,
+                          hipStream_t s);
 
 // Gradients of the Gaussians' parameters from the per-slot gradients (summed
 // over views; overwrites the outputs).

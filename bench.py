@@ -42,8 +42,11 @@ METRIC = "Mpix/s + splats blended/s per transmittance model; p50/p99 render late
 # flops and the exp2 as 1: offset 2, exponent 8, exp2 1, accumulate 6, plus
 # the operator (exponential 3, linear 1, quadratic 5).
 FLOPS_PER_PAIR = {0: 20, 1: 18, 2: 22, 3: 22}
-# 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz, non-packed FP32
-FP32_VALU_PEAK_TFLOPS = 78.6432
+# MI355X FP32 vector peak: 256 CUs x 128 FP32 lanes x 2 flops (FMA) x 2.4 GHz.
+# (The kernels are built without packed FP32, but the measured VALU issue rate
+# of the composite exceeds one wave64 instruction per 4 cycles per SIMD, so
+# the 16-lane figure of half this would not be a ceiling.)
+FP32_VALU_PEAK_TFLOPS = 157.2864
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of each composite kernel on this workload (16x16 tiles),
@@ -51,9 +54,9 @@ HBM_PEAK_GBS = 8000.0
 # size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
 # kernel sources with this digest and are reported as null once those change.
 TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_stage.h", "nxs_internal.h")
-TRAFFIC = {"digest": "8a1f6a280f52db9aabd25ae606c037036290362a814b341020d6ab9c07110c7e",
+TRAFFIC = {"digest": "cb9b2c5f3f77af81d12cf354d8992c9e399570eb00a8f07b37439462b9679631",
            "tile": "16x16",
-           "bytes": {0: 226304215, 1: 132507014, 2: 147110357, 3: 128330630}}
+           "bytes": {0: 514901825, 1: 244128125, 2: 282237307, 3: 235350828}}
 
 
 def measured_traffic(model, tile):

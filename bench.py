@@ -475,6 +475,7 @@ def main():
                                 "one step = one render per transmittance model"),
                    "gaussians": scene.n, "width": W, "height": H,
                    "tile": f"{tw}x{th}", "lds_batch": args.lds_batch,
+                   "schedule": "queue (longest tile lists first; the library default)",
                    "instances": n_inst, "models": list(MODELS)},
         "per_model": per_model,
         "roofline": roofline,

@@ -31,6 +31,7 @@ namespace nxs {
 namespace {
 
 constexpr float kL2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;   // 1 / log2(e)
 
 // Sum over each row of 16 lanes with DPP adds (VALU only): pairs and quads
 // by quad_perm, then half-rows and rows by mirror patterns; every lane of a
@@ -154,7 +155,8 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
               dalpha = T_before * (g0 * (r[6] - prm.bg[0]) + g1 * (r[7] - prm.bg[1]) +
                                    g2 * (r[8] - prm.bg[2]) - gT);
             } else {
-              const float inv = 1.0f / (1.0f - a);
+              // (1 - a > 0 here: a splat with a = 1 leaves T = 0 and stops the pixel)
+              const float inv = __builtin_amdgcn_rcpf(1.0f - a);
               dalpha = T_before * (g0 * r[6] + g1 * r[7] + g2 * r[8]) -
                        inv * (g0 * R0 + g1 * R1 + g2 * R2 + gT * R3);
             }
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
             }
           }
           // alpha = aleph exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2
-          const float A = -2.0f * r[2] / kL2e, B = -r[3] / kL2e, C = -2.0f * r[4] / kL2e;
+          const float A = (-2.0f * kLn2) * r[2], B = -kLn2 * r[3], C = (-2.0f * kLn2) * r[4];
           const float dq = -0.5f * a * dalpha;
           d_op = dalpha * __builtin_amdgcn_exp2f(e - r[5]);
           d_u = -2.0f * dq * (A * dx + B * dy);

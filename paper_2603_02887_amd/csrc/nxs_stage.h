@@ -101,8 +101,10 @@ __device__ __forceinline__ uint32_t stage_batch(const StageFetch& f, const Stage
       const float ylo = b.y0 - dv, yhi = b.y1 - dv;     // dy range over the block
       float qmin = 0.0f;
       if (!(xlo <= 0.0f && xhi >= 0.0f && ylo <= 0.0f && yhi >= 0.0f)) {
-        // the centre is outside: the minimum of Q lies on an edge
-        const float ia = 0.5f / qa, ic = 0.5f / qc;
+        // the centre is outside: the minimum of Q lies on an edge (hardware
+        // reciprocals: a relative error of ~1e-7 in the edge's minimiser
+        // moves Q far less than the margin)
+        const float ia = 0.5f * __builtin_amdgcn_rcpf(qa), ic = 0.5f * __builtin_amdgcn_rcpf(qc);
         qmin = __builtin_inff();
         const float xs[2] = {xlo, xhi}, ys[2] = {ylo, yhi};
 #pragma unroll

@@ -100,22 +100,22 @@ __device__ __forceinline__ uint32_t stage_batch(const StageFetch& f, const Stage
       const float xlo = b.x0 - du, xhi = b.x1 - du;     // dx range over the block
       const float ylo = b.y0 - dv, yhi = b.y1 - dv;     // dy range over the block
       float qmin = 0.0f;
-      if (!(xlo <= 0.0f && xhi >= 0.0f && ylo <= 0.0f && yhi >= 0.0f)) {
-        // the centre is outside: the minimum of Q lies on an edge (hardware
-        // reciprocals: a relative error of ~1e-7 in the edge's minimiser
+      const bool face_x = !(xlo <= 0.0f && xhi >= 0.0f);   // the centre is left or right
+      const bool face_y = !(ylo <= 0.0f && yhi >= 0.0f);   // the centre is above or below
+      if (face_x || face_y) {
+        // the centre is outside: Q is convex, so its minimum over the
+        // rectangle lies on an edge that faces the centre (at most one in x
+        // and one in y), at the edge's own minimiser clamped to the edge
+        // (hardware reciprocals: a relative error of ~1e-7 in the minimiser
         // moves Q far less than the margin)
         const float ia = 0.5f * __builtin_amdgcn_rcpf(qa), ic = 0.5f * __builtin_amdgcn_rcpf(qc);
-        qmin = __builtin_inff();
-        const float xs[2] = {xlo, xhi}, ys[2] = {ylo, yhi};
-#pragma unroll
-        for (int e2 = 0; e2 < 2; ++e2) {
-          const float X = xs[e2];
-          const float y = fminf(fmaxf(-qb * X * ic, ylo), yhi);
-          qmin = fminf(qmin, X * (qa * X + qb * y) + qc * y * y);
-          const float Y = ys[e2];
-          const float x = fminf(fmaxf(-qb * Y * ia, xlo), xhi);
-          qmin = fminf(qmin, Y * (qc * Y + qb * x) + qa * x * x);
-        }
+        const float X = xlo > 0.0f ? xlo : xhi;
+        const float y = fminf(fmaxf(-qb * X * ic, ylo), yhi);
+        const float qx = X * (qa * X + qb * y) + qc * y * y;
+        const float Y = ylo > 0.0f ? ylo : yhi;
+        const float x = fminf(fmaxf(-qb * Y * ia, xlo), xhi);
+        const float qy = Y * (qc * Y + qb * x) + qa * x * x;
+        qmin = fminf(face_x ? qx : __builtin_inff(), face_y ? qy : __builtin_inff());
       }
       keep = qmin <= qlim;
     }

@@ -134,6 +134,37 @@ def test_autograd_function_matches_direct_backward(R):
         assert torch.allclose(leaf.grad, direct[k], rtol=1e-4, atol=1e-5 * scale), k
 
 
+@pytest.mark.parametrize("model", [0, 2])
+def test_backward_same_under_every_schedule(R, model):
+    """The backward walks the tiles in the forward's order when the forward's
+    schedule made one (queue, persistent) and in plain tile order otherwise;
+    the gradients agree to float32 rounding of sums taken in another order
+    (float atomics: on this scene two runs of one schedule already differ by
+    up to 5e-5, and two schedules by up to 1.1e-4, of the largest gradient)."""
+    from paper_2603_02887_amd import nxs
+    sc = synth.scenes.clustered_scene(14, 20_000, 8, log_scale=(-3.5, 0.4), logit=(0.0, 1.0),
+                                      sh_degree=1)
+    rng = np.random.default_rng(3)
+    sizes = [(203, 97), (64, 64), (131, 180)]
+    cams = synth.orbit_cameras(len(sizes), 7.0, [w for w, _ in sizes], [h for _, h in sizes],
+                               rng=rng, elevation_deg=(-30.0, 30.0),
+                               azimuths=rng.uniform(0, 2 * np.pi, len(sizes)))
+    g = nxs.scene_to_device(sc)
+    gen = torch.Generator(device="cpu").manual_seed(9)
+    w = [torch.randn((c.height, c.width, 3), generator=gen).cuda() for c in cams]
+    grads = {}
+    for sched in ("tiles", "blocks", "queue", "persistent"):
+        R.render(g, cams, model=model, keep_state=True, schedule=sched)
+        grads[sched] = {k: v.clone() for k, v in R.backward(g, w).items()}
+        torch.cuda.synchronize()
+    ref = grads["queue"]
+    for sched, gr in grads.items():
+        for k, v in gr.items():
+            scale = float(ref[k].abs().max())
+            assert scale > 0, k
+            assert torch.allclose(v, ref[k], rtol=1e-4, atol=5e-4 * scale), (sched, k)
+
+
 def test_autograd_rejects_stale_state(R):
     from paper_2603_02887_amd import nxs
     sc, cams = _scene()

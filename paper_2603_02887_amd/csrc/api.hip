@@ -193,8 +193,14 @@ nxs_status nxs_create(nxs_context** out, int device) {
       hipHostMalloc((void**)&ctx->host_counters, sizeof(Counters), hipHostMallocDefault) !=
           hipSuccess ||
       hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->counted, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->counted, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->projected, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess) {
     if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+    if (ctx->done) (void)hipEventDestroy(ctx->done);
+    if (ctx->counted) (void)hipEventDestroy(ctx->counted);
+    if (ctx->projected) (void)hipEventDestroy(ctx->projected);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
     return NXS_EHIP;
   }
@@ -354,7 +360,9 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   // The instance count M is read by the host only where it sizes buffers and
   // grids: the depth sort (its digits planned on the device) and the emission
   // (total read on the device, writes bounded by the current capacity) are
-  // enqueued first, so the GPU keeps working while the host waits.
+  // enqueued first, so the GPU keeps working while the host waits.  (Copying
+  // the counters on a second stream, beside the depth sort, was measured
+  // slower: the cross-stream wait costs more than the copy.)
   HIP_TRY(hipMemcpyAsync(ctx->host_counters, dcount, sizeof(Counters), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(ctx->counted, s));
   HIP_TRY(mark(2));

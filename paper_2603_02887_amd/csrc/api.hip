@@ -193,14 +193,10 @@ nxs_status nxs_create(nxs_context** out, int device) {
       hipHostMalloc((void**)&ctx->host_counters, sizeof(Counters), hipHostMallocDefault) !=
           hipSuccess ||
       hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->counted, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->projected, hipEventDisableTiming) != hipSuccess ||
-      hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->counted, hipEventDisableTiming) != hipSuccess) {
     if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
     if (ctx->done) (void)hipEventDestroy(ctx->done);
     if (ctx->counted) (void)hipEventDestroy(ctx->counted);
-    if (ctx->projected) (void)hipEventDestroy(ctx->projected);
-    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
     return NXS_EHIP;
   }

@@ -124,15 +124,17 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
 
   Op<MODEL> op;
   bool done = !inside;
-  bool all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
+  // running lanes; each batch is staged against the rows and columns that
+  // still hold one
+  uint64_t act = __builtin_amdgcn_ballot_w64(!done);
   StageSlot slots = stage_slot(inst_val, rg.x, rg.y, lane);
   StageFetch fetched = stage_records(slots, rec);
   slots = stage_slot(inst_val, (uint64_t)rg.x + 64, rg.y, lane);
-  for (uint32_t base = rg.x; base < rg.y && !all_done; base += 64) {
-    const uint32_t n = stage_batch(fetched, sb, wlds);
+  for (uint32_t base = rg.x; base < rg.y && act != 0; base += 64) {
+    const uint32_t n = stage_batch(fetched, stage_shrink(sb, act), wlds);
     fetched = stage_records(slots, rec);                              // batch base + 64
     slots = stage_slot(inst_val, (uint64_t)base + 128, rg.y, lane);   // batch base + 128
-    for (uint32_t k = 0; k < n && !all_done; ++k) {
+    for (uint32_t k = 0; k < n && act != 0; ++k) {
       const float4 q0 = wlds[3 * k + 0], q1 = wlds[3 * k + 1], q2 = wlds[3 * k + 2];
       const float r[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y};
       float d_op = 0.f, d_u = 0.f, d_v = 0.f, d_A = 0.f, d_B = 0.f, d_C = 0.f;
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
         }
         wave_lds_order();
       }
-      all_done = __builtin_amdgcn_ballot_w64(!done) == 0;
+      act = __builtin_amdgcn_ballot_w64(!done);
     }
   }
 }

@@ -3,8 +3,9 @@
 // One wave per 8x8 pixel block of a screen tile, one lane per pixel; waves
 // run on their own (no barriers).  The tile's sorted list holds projected
 // slots: a wave walks it in batches of 64, each lane fetching one slot's
-// record and testing whether its footprint reaches the wave's block; the
-// records that do are written in order to the wave's LDS (the gather to
+// record and testing whether its footprint reaches the rows and columns of
+// the wave's block that still hold a running pixel; the records that do are
+// written in order to the wave's LDS (the gather to
 // sorted order, done only for the part of the list the wave reaches before
 // its pixels stop).  Each staged splat is then read by the whole wave with
 // broadcast LDS reads.  Per pixel (Sec. 4, eq. generalized_gaussian and
@@ -93,12 +94,14 @@ __device__ __forceinline__ void composite_block(
   // per-pixel update is branch-free: a lane whose alpha is below alpha_min,
   // or which has stopped, composites a = 0, which leaves every operator's
   // state unchanged, so the loop carries no per-lane control flow.
-  bool all_done = __builtin_amdgcn_ballot_w64(!op.stopped(t_eps)) == 0;
+  // Each batch is staged against the rows and columns that still hold a
+  // running pixel (act: the wave's running lanes).
+  uint64_t act = __builtin_amdgcn_ballot_w64(!op.stopped(t_eps));
   StageSlot slots = stage_slot(inst_val, rg.x, rg.y, lane);
   StageFetch fetched = stage_records(slots, rec);
   slots = stage_slot(inst_val, (uint64_t)rg.x + 64, rg.y, lane);
-  for (uint32_t base = rg.x; base < rg.y && !all_done; base += 64) {
-    const uint32_t n = stage_batch(fetched, sb, wlds);
+  for (uint32_t base = rg.x; base < rg.y && act != 0; base += 64) {
+    const uint32_t n = stage_batch(fetched, stage_shrink(sb, act), wlds);
     fetched = stage_records(slots, rec);                              // batch base + 64
     slots = stage_slot(inst_val, (uint64_t)base + 128, rg.y, lane);   // batch base + 128
     for (const float4 *r = wlds, *r_end = wlds + 3 * n; r != r_end; r += 3) {
@@ -126,10 +129,8 @@ __device__ __forceinline__ void composite_block(
       L1 = fmaf(c[7], p, L1);
       L2 = fmaf(c[8], p, L2);
       od += valid ? 1 : 0;
-      if (__builtin_amdgcn_ballot_w64(!op.stopped(t_eps)) == 0) {
-        all_done = true;
-        break;
-      }
+      act = __builtin_amdgcn_ballot_w64(!op.stopped(t_eps));
+      if (act == 0) break;
     }
   }
   if (inside) {

@@ -38,6 +38,28 @@ __device__ __forceinline__ StageBlock stage_block(int tx, int ty, int th, int wi
   return b;
 }
 
+// The block's extent cut down to the rows and columns that still hold a
+// running pixel (bit 8 r + c of `act` is the pixel in row r, column c of the
+// block; act != 0).  A splat that reaches none of those pixels would
+// composite a = 0 on every running lane, so leaving it out of a batch
+// changes no result; the cut only shrinks as pixels stop.
+__device__ __forceinline__ StageBlock stage_shrink(const StageBlock& b, uint64_t act) {
+  uint64_t c = act | (act >> 32);
+  c |= c >> 16;
+  c |= c >> 8;
+  const uint32_t cols = (uint32_t)c & 0xFFu;
+  uint64_t r = act | (act >> 1);
+  r |= r >> 2;
+  r |= r >> 4;
+  r &= 0x0101010101010101ull;   // bit 8 k: row k holds a running pixel
+  StageBlock s = b;
+  s.x0 = b.x0 + (float)__builtin_ctz(cols);
+  s.x1 = b.x0 + (float)(31 - __builtin_clz(cols));
+  s.y0 = b.y0 + (float)(__builtin_ctzll(r) >> 3);
+  s.y1 = b.y0 + (float)((63 - __builtin_clzll(r)) >> 3);
+  return s;
+}
+
 // A batch's global reads, issued ahead of their use so that they are in
 // flight while earlier batches are composited: lane j takes list entry
 // base + j (if below end) and its slot (two batches ahead), then the slot's

@@ -101,13 +101,17 @@ __global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(uint32_t* __res
 }
 
 // One work-group per 1024 sorted slots writes all of their instances as one
-// contiguous run: each output position finds its slot by binary search over
-// the block's offsets in LDS, so consecutive threads write consecutive
-// addresses however unevenly the Gaussians' tile counts are spread.
+// contiguous run, consecutive threads at consecutive addresses however
+// unevenly the Gaussians' tile counts are spread: the run is taken in windows
+// of kEmitWindow positions, each slot first marks the positions of its
+// instances in the window with its index (an owner map in LDS), then each
+// position is written from its owner's record.
 // Blocks up to this count find their output offset by summing the totals of
 // the blocks before them (no separate scan launch); beyond it the totals are
 // scanned by scan_blocks_kernel first.
 constexpr int kInlineBlocks = 2048;
+constexpr uint32_t kEmitWindow = 8192;   // positions per owner map (16 KB)
+constexpr uint32_t kEmitShort = 32;      // longer runs are marked by a whole wave
 
 __global__ __launch_bounds__(kScanBlock) void emit_kernel(
     const uint32_t* __restrict__ sorted_slots, const uint2* __restrict__ rect_sorted, int64_t n,
@@ -119,6 +123,7 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
   __shared__ uint32_t s_tile0[kScanChunk];   // global tile of the rectangle's first tile
   __shared__ uint32_t s_geom[kScanChunk];    // width | tiles_x << 16
   __shared__ uint32_t s_tmp[kScanBlock / 64];
+  __shared__ uint16_t s_owner[kEmitWindow];   // block-local slot of each position
   const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
   const int cnt = (int)min((int64_t)kScanChunk, n - b0);
   uint32_t out0;
@@ -170,23 +175,50 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
   }
   __syncthreads();
   const uint32_t tot = out1 - out0;
-  for (uint32_t q = threadIdx.x; q < tot; q += kScanBlock) {
-    int lo = 0, hi = cnt - 1;   // last slot whose offset is <= q (it has q inside)
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= q) lo = mid; else hi = mid - 1;
+  // slot k owns positions [s_off[k], s_off[k + 1]) (the last one: up to tot)
+  const int lane = threadIdx.x & 63;
+  uint32_t end_r[kPerT];
+#pragma unroll
+  for (int q = 0; q < kPerT; ++q) {
+    const int k = q * kScanBlock + threadIdx.x;
+    end_r[q] = k + 1 < cnt ? s_off[k + 1] : (k < cnt ? tot : off_r[q]);
+  }
+  for (uint32_t w0 = 0; w0 < tot; w0 += kEmitWindow) {
+    const uint32_t w1 = min(tot, w0 + kEmitWindow);
+    // a short run is marked by its slot's thread, a long one by the whole
+    // wave (the slot's lane broadcasts its bounds)
+#pragma unroll
+    for (int q = 0; q < kPerT; ++q) {
+      const int k = q * kScanBlock + threadIdx.x;
+      const uint32_t a = off_r[q], e = end_r[q];
+      const bool longrun = e - a > kEmitShort;
+      if (!longrun)
+        for (uint32_t j = max(a, w0); j < min(e, w1); ++j) s_owner[j - w0] = (uint16_t)k;
+      uint64_t runs = __ballot(longrun);
+      while (runs) {
+        const int b = __builtin_ctzll(runs);
+        runs &= runs - 1;
+        const uint32_t ba = __shfl(a, b, 64), be = __shfl(e, b, 64);
+        const uint16_t bk = (uint16_t)(k - lane + b);
+        for (uint32_t j = max(ba, w0) + lane; j < min(be, w1); j += 64) s_owner[j - w0] = bk;
+      }
     }
-    const uint32_t geom = s_geom[lo];
-    const uint32_t w = geom & 0xFFFF, tiles_x = geom >> 16;
-    const uint32_t l = q - s_off[lo];
-    // row = l / w in float (exact for l < 2^24 after the +-1 fix-up)
-    uint32_t row = (uint32_t)((float)l * __frcp_rn((float)w));
-    if (row * w > l) --row;
-    if ((row + 1) * w <= l) ++row;
-    if (out0 + q < capacity) {
-      inst_tile[out0 + q] = s_tile0[lo] + row * tiles_x + (l - row * w);
-      inst_val[out0 + q] = s_slot[lo];
+    __syncthreads();
+    for (uint32_t q = w0 + threadIdx.x; q < w1; q += kScanBlock) {
+      const int k = s_owner[q - w0];
+      const uint32_t geom = s_geom[k];
+      const uint32_t w = geom & 0xFFFF, tiles_x = geom >> 16;
+      const uint32_t l = q - s_off[k];
+      // row = l / w in float (exact for l < 2^24 after the +-1 fix-up)
+      uint32_t row = (uint32_t)((float)l * __frcp_rn((float)w));
+      if (row * w > l) --row;
+      if ((row + 1) * w <= l) ++row;
+      if (out0 + q < capacity) {
+        inst_tile[out0 + q] = s_tile0[k] + row * tiles_x + (l - row * w);
+        inst_val[out0 + q] = s_slot[k];
+      }
     }
+    __syncthreads();   // the next window's marks overwrite this one's
   }
 }
 

@@ -113,6 +113,26 @@ def test_depth_sort_plan_changes_between_renders():
         r.close()
 
 
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_emission_of_large_footprints(R, tile):
+    """Splats from a few pixels up to the whole 256x192 view: 1,024
+    depth-sorted slots then emit 16K-220K tile instances (many windows of
+    the emission's owner map, runs crossing window edges) and about half to
+    nine tenths of the runs are longer than 32 tiles (marked by a whole wave
+    rather than one thread).  Keys bit-exact; sampled pixels, of which the
+    oracle flags about one in eight as boundary cases under the exponential
+    model here (some 76 composited splats per pixel, each a chance of an
+    alpha within 1e-5 of alpha_min or a step near the cutoff), so the cap on
+    flagged pixels is raised to a quarter."""
+    sc = synth.random_scene(13, 2500, sh_degree=0, log_scale=(-2.2, 0.9))
+    cam = synth.look_at_camera((0, 0, -3), width=256, height=192)
+    px = parity.sample_pixels(cam, 300, seed=4)
+    for model in (0, 1):
+        out = _render(R, sc, [cam], model, tile=tile)
+        parity.compare_keys(R, sc, [cam], tile_w=tile[0], tile_h=tile[1])
+        parity.compare_view(out[0], sc, cam, model, pixels=px, max_ambiguous=0.25)
+
+
 def test_sh_degree3_and_background(R):
     sc = synth.random_scene(8, 2000, sh_degree=3, log_scale=(-3.0, 0.5), logit=(1.0, 1.5))
     cam = synth.look_at_camera((0.5, -0.3, -2.8), width=96, height=80)

@@ -10,11 +10,15 @@ quadratic superlinear): the whole path (projection, depth sort, binning, tile
 sort, tile ranges, composite with its gather) runs for every render.  The
 scene is uploaded to HBM before the timed region.
 
-The timed steps enqueue their renders back to back on one stream (a caller
-that pipelines renders); `value` is the frame's pixels over that time.
-Latency is measured separately, waiting for each render: p50/p99 per model,
-with per-stage GPU times from hipEvents the library records on the render
-stream.
+The timed steps enqueue their renders back to back, alternating between two
+library contexts, each on a stream of its own (a caller that pipelines
+renders): one render's short, latency-bound sort kernels then overlap the
+other's projection or composite.  `value` is the frame's pixels over that
+time.  Per-model throughput is also given for one context on one stream.
+Latency is measured separately, one render at a time, waiting for each:
+p50/p99 per model, with per-stage GPU times from hipEvents the library
+records on the render stream (the composite's time there, alone on the GPU,
+is the one the roofline uses).
 
 Prints one JSON line: aggregate Mpix/s over all renders, per-model Mpix/s,
 splats blended per second (sum of per-pixel overdraw / time), mean overdraw,
@@ -54,9 +58,9 @@ HBM_PEAK_GBS = 8000.0
 # size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
 # kernel sources with this digest and are reported as null once those change.
 TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_stage.h", "nxs_internal.h")
-TRAFFIC = {"digest": "4b5379ad74f7c8683e86d7441c75b2ea72b92bd9a282a24205343010f81f3030",
+TRAFFIC = {"digest": "3b33e2e3f82691af8d78b84656e79cc22644bb47832fc357ad8a3e8595e18920",
            "tile": "16x16",
-           "bytes": {0: 508050734, 1: 245530542, 2: 278871754, 3: 235524735}}
+           "bytes": {0: 501938783, 1: 249077553, 2: 281115662, 3: 237340685}}
 
 
 def measured_traffic(model, tile):
@@ -380,18 +384,31 @@ def main():
     def render(m):
         R.render(g, [cam], model=m, tile=(tw, th), lds_batch=args.lds_batch, outputs=outs[m])
 
-    for _ in range(args.warmup):
-        for m in range(4):
-            render(m)
-    torch.cuda.synchronize()
     # Throughput (the timed steps): each step enqueues one render per model back
-    # to back, as a pipelined caller would; the stream orders them.
+    # to back, as a pipelined caller would, alternating between two contexts on
+    # two streams (each stream orders its own renders; each model writes its
+    # own outputs)
+    ctxs = [R, nxs.Renderer(0)]
+    streams = [torch.cuda.Stream(dev), torch.cuda.Stream(dev)]
+
+    def step():
+        for m in range(4):
+            with torch.cuda.stream(streams[m % 2]):
+                ctxs[m % 2].render(g, [cam], model=m, tile=(tw, th),
+                                   lds_batch=args.lds_batch, outputs=outs[m])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        for m in range(4):
-            render(m)
+        step()
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    ctxs[1].close()
+    for m in range(4):
+        render(m)
+    torch.cuda.synchronize()
     # per model, the same back-to-back throughput
     thr = {}
     for m in range(4):
@@ -476,6 +493,7 @@ def main():
                    "gaussians": scene.n, "width": W, "height": H,
                    "tile": f"{tw}x{th}", "lds_batch": args.lds_batch,
                    "schedule": "queue (longest tile lists first; the library default)",
+                   "in_flight": "renders alternate between two contexts on two streams",
                    "instances": n_inst, "models": list(MODELS)},
         "per_model": per_model,
         "roofline": roofline,

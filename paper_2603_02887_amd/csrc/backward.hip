@@ -137,60 +137,57 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
     for (uint32_t k = 0; k < n && act != 0; ++k) {
       const float4 q0 = wlds[3 * k + 0], q1 = wlds[3 * k + 1], q2 = wlds[3 * k + 2];
       const float r[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y};
-      float d_op = 0.f, d_u = 0.f, d_v = 0.f, d_A = 0.f, d_B = 0.f, d_C = 0.f;
-      float d_r = 0.f, d_g = 0.f, d_b = 0.f;
-      bool contrib = false;
-      if (!done) {
-        const float dx = fx - r[0], dy = fy - r[1];
-        const float e = fmaf(dx, fmaf(r[2], dx, r[3] * dy), fmaf(r[4] * dy, dy, r[5]));
-        if (e >= amin) {
-          contrib = true;
-          const float a = __builtin_amdgcn_exp2f(e);
-          const float T_before = op.T, tau_before = op.tau, S_before = op.S;
-          const float p = op.step(a, param, t_eps, done);
-          float dalpha;
-          if (MODEL == 0) {
-            R0 -= r[6] * p;
-            R1 -= r[7] * p;
-            R2 -= r[8] * p;
-            if (done) {
-              dalpha = T_before * (g0 * (r[6] - prm.bg[0]) + g1 * (r[7] - prm.bg[1]) +
-                                   g2 * (r[8] - prm.bg[2]) - gT);
-            } else {
-              // (1 - a > 0 here: a splat with a = 1 leaves T = 0 and stops the pixel)
-              const float inv = __builtin_amdgcn_rcpf(1.0f - a);
-              dalpha = T_before * (g0 * r[6] + g1 * r[7] + g2 * r[8]) -
-                       inv * (g0 * R0 + g1 * R1 + g2 * R2 + gT * R3);
-            }
+      // Every lane runs the same arithmetic: a lane that has stopped, or
+      // whose alpha is below alpha_min, takes a = 0 and dL/dalpha = 0, which
+      // leaves its state unchanged and makes each of its terms an exact zero.
+      const float dx = fx - r[0], dy = fy - r[1];
+      const float e = fmaf(dx, fmaf(r[2], dx, r[3] * dy), fmaf(r[4] * dy, dy, r[5]));
+      const bool contrib = !done && e >= amin;
+      const float a = contrib ? __builtin_amdgcn_exp2f(e) : 0.0f;
+      const float T_before = op.T, tau_before = op.tau;
+      bool stops;
+      const float p = op.step(a, param, t_eps, stops);
+      float dalpha = 0.0f;
+      if (MODEL == 0) {
+        R0 -= r[6] * p;
+        R1 -= r[7] * p;
+        R2 -= r[8] * p;
+      }
+      if (contrib) {
+        if (MODEL == 0) {
+          if (stops) {
+            dalpha = T_before * (g0 * (r[6] - prm.bg[0]) + g1 * (r[7] - prm.bg[1]) +
+                                 g2 * (r[8] - prm.bg[2]) - gT);
           } else {
-            (void)S_before;
-            if (done) {
-              dalpha = 0.0f;   // the saturating splat takes the remainder
-            } else {
-              const float e0 = r[6] - k0, e1 = r[7] - k1, e2 = r[8] - k2, e3 = -k3;
-              th0 -= e0 * a;
-              th1 -= e1 * a;
-              th2 -= e2 * a;
-              th3 -= e3 * a;
-              const float w = fmaf(c, tau_before, 1.0f);
-              dalpha = g0 * fmaf(e0, w, c * th0) + g1 * fmaf(e1, w, c * th1) +
-                       g2 * fmaf(e2, w, c * th2) + gT * fmaf(e3, w, c * th3);
-            }
+            // (1 - a > 0 here: a splat with a = 1 leaves T = 0 and stops the pixel)
+            const float inv = __builtin_amdgcn_rcpf(1.0f - a);
+            dalpha = T_before * (g0 * r[6] + g1 * r[7] + g2 * r[8]) -
+                     inv * (g0 * R0 + g1 * R1 + g2 * R2 + gT * R3);
           }
-          // alpha = aleph exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2
-          const float A = (-2.0f * kLn2) * r[2], B = -kLn2 * r[3], C = (-2.0f * kLn2) * r[4];
-          const float dq = -0.5f * a * dalpha;
-          d_op = dalpha * __builtin_amdgcn_exp2f(e - r[5]);
-          d_u = -2.0f * dq * (A * dx + B * dy);
-          d_v = -2.0f * dq * (B * dx + C * dy);
-          d_A = dq * dx * dx;
-          d_B = 2.0f * dq * dx * dy;
-          d_C = dq * dy * dy;
-          d_r = p * g0;
-          d_g = p * g1;
-          d_b = p * g2;
+        } else if (!stops) {   // the saturating splat takes the remainder: 0
+          const float e0 = r[6] - k0, e1 = r[7] - k1, e2 = r[8] - k2, e3 = -k3;
+          th0 -= e0 * a;
+          th1 -= e1 * a;
+          th2 -= e2 * a;
+          th3 -= e3 * a;
+          const float w = fmaf(c, tau_before, 1.0f);
+          dalpha = g0 * fmaf(e0, w, c * th0) + g1 * fmaf(e1, w, c * th1) +
+                   g2 * fmaf(e2, w, c * th2) + gT * fmaf(e3, w, c * th3);
         }
       }
+      done = done || stops;
+      // alpha = aleph exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2
+      const float A = (-2.0f * kLn2) * r[2], B = -kLn2 * r[3], C = (-2.0f * kLn2) * r[4];
+      const float dq = -0.5f * a * dalpha;
+      const float d_op = dalpha * __builtin_amdgcn_exp2f(e - r[5]);
+      const float d_u = -2.0f * dq * (A * dx + B * dy);
+      const float d_v = -2.0f * dq * (B * dx + C * dy);
+      const float d_A = dq * dx * dx;
+      const float d_B = 2.0f * dq * dx * dy;
+      const float d_C = dq * dy * dy;
+      const float d_r = p * g0;
+      const float d_g = p * g1;
+      const float d_b = p * g2;
       if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
         // the wave's sums: row totals, written to LDS by each row's first
         // lane, then lane f adds field f of the 4 rows and issues the atomic

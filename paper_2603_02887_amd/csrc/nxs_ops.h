@@ -37,7 +37,10 @@ struct Op {
     if (MODEL == 6) return S2 >= 1.0f && !(T >= t_eps);
     return S >= 1.0f;
   }
+  // (no contraction into FMAs in the update: the forward and its backward,
+  // compiled apart, must round it identically)
   __device__ __forceinline__ float saturate(float p) {
+#pragma clang fp contract(off)
     const float Sn = S + p;
     const bool sat = Sn >= 1.0f;
     p = sat ? 1.0f - S : p;
@@ -45,6 +48,7 @@ struct Op {
     return p;
   }
   __device__ __forceinline__ float step(float a, float param, float t_eps) {
+#pragma clang fp contract(off)
     if (MODEL == 0) {
       const float p = a * T;
       T = T * (1.0f - a);
@@ -88,6 +92,7 @@ struct Op {
     return p;
   }
   __device__ __forceinline__ float transmittance(float param) const {
+#pragma clang fp contract(off)
     if (MODEL == 0) return T;
     if (MODEL == 6) return fmaf(param, T - (1.0f - S2), 1.0f - S2);
     return 1.0f - S;

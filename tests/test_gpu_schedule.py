@@ -142,3 +142,34 @@ def test_autotune_and_cache(R, tmp_path):
     torch.cuda.synchronize()
     for a, b in zip(ref, out):
         _same(a, b)
+
+
+def test_two_contexts_on_two_streams(R):
+    """Renders enqueued back to back alternately on two contexts, each on a
+    stream of its own (so that they overlap on the GPU), give every model's
+    images bitwise equal to the same renders one at a time on one context."""
+    from paper_2603_02887_amd import nxs
+    sc, cams = _uneven_views()
+    g = nxs.scene_to_device(sc)
+    ref = {}
+    for m in range(4):
+        o = R.render(g, cams[:3], model=m)
+        torch.cuda.synchronize()
+        ref[m] = [{k: v.clone() for k, v in d.items()} for d in o]
+    R2 = nxs.Renderer(0)
+    try:
+        ctxs = [R, R2]
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        outs = {m: None for m in range(4)}
+        for _ in range(3):
+            for m in range(4):
+                with torch.cuda.stream(streams[m % 2]):
+                    outs[m] = ctxs[m % 2].render(g, cams[:3], model=m, outputs=outs[m])
+        torch.cuda.synchronize()
+        for m in range(4):
+            for v in range(3):
+                for k in ("rgb", "trans", "overdraw"):
+                    assert torch.equal(outs[m][v][k], ref[m][v][k]), (m, v, k)
+    finally:
+        torch.cuda.synchronize()
+        R2.close()

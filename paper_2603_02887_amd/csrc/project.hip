@@ -245,17 +245,42 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
        k += (int64_t)gridDim.x * kBlock)
     clear[k] = 0u;
   constexpr int NC = 3 * K;
-  constexpr int STRIDE = NC + 1;
-  __shared__ float s_sh[kBlock * STRIDE];
+  // The block's SH coefficients are staged in LDS, one row per Gaussian.
+  // When a Gaussian's coefficients fill whole float4s (degrees 1 and 3), a
+  // row is an odd number of float4s and every access is a 16-byte one: the
+  // eight lanes served together then cover all 32 banks (conflict-free both
+  // ways).  Otherwise rows are an odd number of floats, accessed by float.
+  constexpr bool kVec = NC % 4 == 0;
+  constexpr int NC4 = NC / 4;
+  constexpr int STRIDE4 = NC4 % 2 == 1 ? NC4 : NC4 + 1;   // float4s per row (kVec)
+  constexpr int STRIDE = kVec ? 4 * STRIDE4 : NC + 1;    // floats per row
+  __shared__ __align__(16) float s_sh[kBlock * STRIDE];
   const int base = blockIdx.x * kBlock;
   const int cnt = min(kBlock, g.n - base);
   {
-    // every load of the block's coefficients is issued before any is used:
-    // NC/4 float4 per thread (the region is 16-byte aligned when sh is)
+    // every load of the block's coefficients is issued before any is used
     const float* src = g.sh + (int64_t)base * NC;
     const int nf = cnt * NC;
-    constexpr int kIter = (kBlock * NC / 4 + kBlock - 1) / kBlock;
-    if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0) {
+    const bool aligned = (reinterpret_cast<uintptr_t>(src) & 15u) == 0;
+    if (kVec && aligned) {
+      // NC4 float4 per thread, each stored whole into its row
+      const float4* src4 = reinterpret_cast<const float4*>(src);
+      float4* s4 = reinterpret_cast<float4*>(s_sh);
+      const int n4 = cnt * NC4;
+      float4 buf[NC4 > 0 ? NC4 : 1];
+#pragma unroll
+      for (int r = 0; r < NC4; ++r) {
+        const int f = r * kBlock + threadIdx.x;
+        buf[r] = f < n4 ? src4[f] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+#pragma unroll
+      for (int r = 0; r < NC4; ++r) {
+        const int f = r * kBlock + threadIdx.x;
+        if (f < n4) s4[(f / NC4) * STRIDE4 + f % NC4] = buf[r];
+      }
+    } else if (aligned) {
+      // NC/4 float4 per thread (the region is 16-byte aligned when sh is)
+      constexpr int kIter = (kBlock * NC / 4 + kBlock - 1) / kBlock;
       float4 buf[kIter];
 #pragma unroll
       for (int r = 0; r < kIter; ++r) {
@@ -343,7 +368,22 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
                   ddz = m[2] - v.campos[2];
       const float idn = 1.0f / sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
       float rgb[3];
-      sh_colour<DEG>(s_sh + threadIdx.x * STRIDE, ddx * idn, ddy * idn, ddz * idn, rgb);
+      if (kVec) {
+        // the row as whole float4s, into registers
+        float coef[NC];
+        const float4* row = reinterpret_cast<const float4*>(s_sh) + threadIdx.x * STRIDE4;
+#pragma unroll
+        for (int r = 0; r < NC4; ++r) {
+          const float4 c4 = row[r];
+          coef[4 * r + 0] = c4.x;
+          coef[4 * r + 1] = c4.y;
+          coef[4 * r + 2] = c4.z;
+          coef[4 * r + 3] = c4.w;
+        }
+        sh_colour<DEG>(coef, ddx * idn, ddy * idn, ddz * idn, rgb);
+      } else {
+        sh_colour<DEG>(s_sh + threadIdx.x * STRIDE, ddx * idn, ddy * idn, ddz * idn, rgb);
+      }
       // half-extents of the box where alpha >= alpha_min: q <= 2 ln(aleph / alpha_min),
       // q the Mahalanobis form of Sigma2D; enlarged, rounded up (to +inf beyond the
       // fp16 range), packed as fp16

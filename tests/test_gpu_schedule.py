@@ -173,3 +173,32 @@ def test_two_contexts_on_two_streams(R):
     finally:
         torch.cuda.synchronize()
         R2.close()
+
+
+def test_batched_workload_full_size(R):
+    """The batched workload at its full size (3M Gaussians, 16 views of uneven
+    size, about 194M tile instances) in the benchmark's launch configuration
+    (16x16 tiles, the default schedule): views of the one batched call equal
+    the same views rendered alone, bitwise, and sampled pixels of two views
+    match the oracle.  Under the exponential model each pixel here composites
+    many splats, so the oracle flags 10-15 % of the sampled pixels as float32
+    boundary cases (an alpha within 1e-5 of alpha_min, or a step near the
+    cutoff); the cap on flagged pixels is raised to a quarter."""
+    from paper_2603_02887_amd import nxs
+    sc, cams = synth.batched_scene()
+    g = nxs.scene_to_device(sc)
+    out = R.render(g, cams, model=0)
+    torch.cuda.synchronize()
+    n_inst, _ = R.counts()
+    print("instances", n_inst)
+    assert n_inst > 150_000_000
+    for v in (0, 7, 15):
+        alone = R.render(g, [cams[v]], model=0)
+        torch.cuda.synchronize()
+        _same(out[v], alone[0])
+    for v in (3, 12):
+        parity.compare_view(out[v], sc, cams[v], 0,
+                            pixels=parity.sample_pixels(cams[v], 150, seed=v),
+                            max_ambiguous=0.25)
+    del out, alone, g
+    torch.cuda.empty_cache()

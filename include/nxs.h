@@ -49,7 +49,8 @@ typedef enum {
                             than the context's limit allows (outputs undefined;
                             retry with fewer views or after
                             nxs_release_workspace) */
-  NXS_EUNSUPPORTED = -5  /* feature not available in this build */
+  NXS_EUNSUPPORTED = -5  /* operation not supported for these arguments (e.g. a
+                            backward of a model that has none) */
 } nxs_status;
 
 /* Transmittance models (Table 1 and Sec. 5 of the paper).

@@ -322,7 +322,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--lds-batch", type=int, default=256)
-    ap.add_argument("--cpu-pixels", type=int, default=32768)
+    ap.add_argument("--cpu-pixels", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 16-view batched workload")

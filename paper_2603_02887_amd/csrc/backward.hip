@@ -127,9 +127,14 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
   // running lanes; each batch is staged against the rows and columns that
   // still hold one
   uint64_t act = __builtin_amdgcn_ballot_w64(!done);
-  StageSlot slots = stage_slot(inst_val, rg.x, rg.y, lane);
-  StageFetch fetched = stage_records(slots, rec);
-  slots = stage_slot(inst_val, (uint64_t)rg.x + 64, rg.y, lane);
+  // (an empty tile fetches nothing: its range is [0, 0) or [x, x))
+  StageSlot slots{0u, false};
+  StageFetch fetched{};
+  if (rg.x < rg.y) {
+    slots = stage_slot(inst_val, rg.x, rg.y, lane);
+    fetched = stage_records(slots, rec);
+    slots = stage_slot(inst_val, (uint64_t)rg.x + 64, rg.y, lane);
+  }
   for (uint32_t base = rg.x; base < rg.y && act != 0; base += 64) {
     const uint32_t n = stage_batch(fetched, stage_shrink(sb, act), wlds);
     fetched = stage_records(slots, rec);                              // batch base + 64

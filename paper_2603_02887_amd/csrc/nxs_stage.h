@@ -64,7 +64,9 @@ __device__ __forceinline__ StageBlock stage_shrink(const StageBlock& b, uint64_t
 // flight while earlier batches are composited: lane j takes list entry
 // base + j (if below end) and its slot (two batches ahead), then the slot's
 // record (one batch ahead).  Every lane reads (past the end: the list's last
-// entry again, end > 0), so that no branch makes a read complete early.
+// entry again), so that no branch makes a read complete early.  Callers
+// fetch only for a non-empty list (end > 0); for end = 0 the index would
+// still be 0, never end - 1 wrapped around.
 struct StageSlot {
   uint32_t slot;
   bool valid;
@@ -80,7 +82,7 @@ __device__ __forceinline__ StageSlot stage_slot(const uint32_t* __restrict__ ins
   StageSlot s;
   const uint64_t j = base + (uint64_t)lane;
   s.valid = j < end;
-  s.slot = inst_val[s.valid ? (uint32_t)j : end - 1];
+  s.slot = inst_val[s.valid ? (uint32_t)j : (end ? end - 1 : 0u)];
   return s;
 }
 

@@ -6,7 +6,10 @@ them as plain whitespace-separated text, one value per line, so the oracle's
 tests can check themselves against numbers the paper prints.  It is run once
 by hand; no test runs it, and nothing here computes anything of the method.
 
-    python tests/golden/extract_figure_data.py /root/reference/PAPER.md
+    python tests/golden/extract_figure_data.py <the paper's LaTeX source>
+
+(the source holds the coordinate lists of Fig. "Transmittance comparison"
+and Fig. "Blending comparison" (a) as pgfplots data).
 
 Fixtures written:
   fig_transmittance_dots.txt    Fig. "Transmittance comparison", blue dots:

@@ -122,7 +122,7 @@ def p_unsaturated(op, alpha, tau_bar, prod):
 
 
 def composite_sequence(alphas, op, emissions=None, background=None,
-                       alpha_min=0.0, t_eps=None):
+                       alpha_min=0.0, t_eps=None, flips=frozenset()):
     """Composite one front-to-back sequence with operator `op` (pure Python, FP64).
 
     alphas     per-splat opacity alpha_i = aleph_i K_i, front to back
@@ -131,6 +131,15 @@ def composite_sequence(alphas, op, emissions=None, background=None,
     alpha_min  splats with alpha < alpha_min are skipped entirely
     t_eps      exponential only: stop after the first splat leaving T < t_eps
                (default 0, i.e. never)
+    flips      discrete decisions to take the other way, for enumerating the
+               outcomes a float32 evaluation may legitimately reach at a
+               boundary (module render): (i, 0) composites splat i if its
+               alpha is below alpha_min and skips it otherwise; (i, 1)
+               reverses whether the pixel stops after compositing splat i
+               (the saturation test of eq. nexp_p, or the exponential's
+               termination).  For Vicini's operator (i, 1) and (i, 2) are
+               the stops of its linear and exponential parts.  Empty: the
+               plain definition.
 
     Returns a dict:
       p      [N] p_i per input splat (0 for skipped or post-termination splats)
@@ -141,6 +150,7 @@ def composite_sequence(alphas, op, emissions=None, background=None,
       T_final  final transmittance
       p_raw  [N] the operator's formula value before the saturation clamp
              (NaN where not composited)
+      done   whether the pixel stopped (later splats were not considered)
     """
     alphas = [float(a) for a in alphas]
     n = len(alphas)
@@ -151,7 +161,7 @@ def composite_sequence(alphas, op, emissions=None, background=None,
     C = E.shape[1]
     Lb = np.zeros(C) if background is None else np.asarray(background, np.float64).reshape(C)
     if op.kind == "vicini":
-        return _vicini(alphas, op.param, E, Lb, alpha_min, t_eps)
+        return _vicini(alphas, op.param, E, Lb, alpha_min, t_eps, flips)
     t_eps = 0.0 if t_eps is None else float(t_eps)
 
     S = 0.0            # sum of p_j so far; T = 1 - S
@@ -168,8 +178,9 @@ def composite_sequence(alphas, op, emissions=None, background=None,
         if done:
             T_seen[i:] = T
             break
-        if a < alpha_min:
+        if (a < alpha_min) != ((i, 0) in flips):
             continue
+        flip_stop = (i, 1) in flips
         p = p_unsaturated(op, a, tau, prod)
         p_raw[i] = p
         if op.kind == "exponential":
@@ -177,8 +188,8 @@ def composite_sequence(alphas, op, emissions=None, background=None,
             # reaches 0 (saturation) only where some alpha is 1
             S += p
             T = prod * (1.0 - a)
-            done = T == 0.0
-        elif S + p >= 1.0:               # splat i saturates: it is the k of eq. nexp_p
+            done = (T == 0.0 or T < t_eps) != flip_stop
+        elif (S + p >= 1.0) != flip_stop:    # splat i saturates: it is the k of eq. nexp_p
             p = 1.0 - S
             S, T, done = 1.0, 0.0, True
         else:
@@ -190,24 +201,26 @@ def composite_sequence(alphas, op, emissions=None, background=None,
         p_out[i] = p
         od += 1
         k = i
-        if not done and op.kind == "exponential" and T < t_eps:
-            done = True
     T_seen[n] = T
     L += Lb * T
     return {"p": p_out, "T": T_seen, "L": L, "od": od, "k": k, "T_final": T,
-            "p_raw": p_raw}
+            "p_raw": p_raw, "done": done}
 
 
-def _vicini(alphas, g, E, Lb, alpha_min, t_eps):
-    lin = composite_sequence(alphas, LINEAR, E, None, alpha_min)
-    ex = composite_sequence(alphas, EXPONENTIAL, E, None, alpha_min, t_eps)
+def _vicini(alphas, g, E, Lb, alpha_min, t_eps, flips=frozenset()):
+    keep = {f for f in flips if f[1] == 0}
+    lin = composite_sequence(alphas, LINEAR, E, None, alpha_min,
+                             flips=keep | {f for f in flips if f[1] == 1})
+    ex = composite_sequence(alphas, EXPONENTIAL, E, None, alpha_min, t_eps,
+                            flips=keep | {(f[0], 1) for f in flips if f[1] == 2})
     p = (1.0 - g) * lin["p"] + g * ex["p"]
     T = (1.0 - g) * lin["T"] + g * ex["T"]
     T_final = T[-1]
     L = (1.0 - g) * lin["L"] + g * ex["L"] + Lb * T_final
     return {"p": p, "T": T, "L": L, "od": max(lin["od"], ex["od"]),
             "k": max(lin["k"], ex["k"]), "T_final": T_final,
-            "p_raw": (1.0 - g) * lin["p_raw"] + g * ex["p_raw"]}
+            "p_raw": (1.0 - g) * lin["p_raw"] + g * ex["p_raw"],
+            "done": lin["done"] and ex["done"], "parts": (lin, ex)}
 
 
 def back_to_front(p, T, E, background):

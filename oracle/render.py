@@ -18,12 +18,15 @@ bounding box of the ellipse q <= 2 ln(1 / (alpha_min (1 - 1e-5))), which
 contains every point where alpha >= alpha_min (1 - 1e-5) because aleph <= 1.
 That list only prunes; it does not change any result.
 
-Each pixel also gets an `ambiguous` flag, set where float32 rounding on the
-GPU may legitimately take a different discrete decision than this FP64
-evaluation: some considered alpha within 1e-5 relative of alpha_min, some
-composited step of a running-sum operator whose transmittance lands within
-1e-6 of 0 (saturation), an exponential step landing within 1e-6 of t_eps
-(termination) or below 1e-30 (where a float32 product may flush to 0).
+Where float32 rounding may legitimately take a discrete decision the other
+way than this FP64 evaluation (a considered alpha within 1e-5 relative of
+alpha_min; a step whose transmittance lands within 1e-6 of the cutoff: 0
+for the running-sum operators, t_eps for the exponential, or below 1e-30
+where a float32 product may flush to zero), the pixel is flagged and every
+outcome reachable by taking such decisions the other way is listed beside
+the definition's (boundary_decisions, composite_pixel).  The renderer's
+result must then match one of them (Sec. 4 fixes the result only away from
+these measure-zero boundaries).
 """
 import math
 
@@ -69,32 +72,79 @@ def _cell_lists(proj, vis_idx, alpha_min, width, height):
     return ncx, starts, ends, gid
 
 
-def composite_pixel(alphas, rgb, op, alpha_min, t_eps, background):
-    """Composite one pixel's front-to-back list (alphas already >= alpha_min
-    or near it) and derive its ambiguity flag from the composited steps."""
-    res = _ops.composite_sequence(alphas, op, rgb, background, alpha_min, t_eps)
+def boundary_decisions(alphas, res, op, alpha_min, t_eps):
+    """The discrete decisions of one composited sequence that lie within
+    float32 reach of their boundary, as flip keys of
+    operators.composite_sequence (sorted by position in the sequence):
+
+      (i, 0)  splat i's alpha within ALPHA_REL (relative) of alpha_min: a
+              float32 alpha may keep or drop it;
+      (i, 1)  the step of splat i leaves a transmittance within CUTOFF_ABS of
+              the cutoff: for the running-sum operators T = 1 - sum p near 0
+              (the saturation test of eq. nexp_p), for the exponential T near
+              t_eps; with no termination threshold (t_eps <= UNDERFLOW) an
+              exponential step that leaves T < UNDERFLOW while the sequence
+              goes on, where the float32 product may flush to zero and stop;
+      (i, 2)  Vicini's operator: the exponential part's (i, 1).
+
+    Only splats the sequence reached are considered (a pixel that stopped at
+    splat k never looks at splat k + 1)."""
     if op.kind == "vicini":
-        # its two parts stop on their own: a boundary case of either is one of it
-        _, a1 = composite_pixel(alphas, rgb, _ops.LINEAR, alpha_min, t_eps, background)
-        _, a2 = composite_pixel(alphas, rgb, _ops.EXPONENTIAL, alpha_min, t_eps, background)
-        return res, a1 or a2
-    amb = bool(np.any(np.abs(np.asarray(alphas) - alpha_min) <= ALPHA_REL * alpha_min))
+        lin, ex = res["parts"]
+        d = set(boundary_decisions(alphas, lin, _ops.LINEAR, alpha_min, t_eps))
+        for i, s in boundary_decisions(alphas, ex, _ops.EXPONENTIAL, alpha_min, t_eps):
+            d.add((i, 2 if s == 1 else 0))
+        return sorted(d)
+    last = res["k"] if res["done"] else len(alphas) - 1
     T, p_raw = res["T"], res["p_raw"]
-    for i in range(res["k"] + 1):
-        if alphas[i] < alpha_min:
-            continue
-        # transmittance this step would leave before any clamp
+    out = []
+    for i in range(last + 1):
+        if abs(alphas[i] - alpha_min) <= ALPHA_REL * alpha_min:
+            out.append((i, 0))
+        if math.isnan(p_raw[i]):
+            continue                   # not composited
+        # transmittance this step leaves before any clamp
         t_next = T[i] - p_raw[i]
-        # the running-sum operators decide saturation where T reaches 0; the
-        # exponential keeps T as a product, which reaches 0 only at alpha = 1
-        # or where float32 underflows
-        if op.kind != "exponential" and abs(t_next) <= CUTOFF_ABS:
-            amb = True
-        if op.kind == "exponential" and t_next < UNDERFLOW:
-            amb = True
-        if op.kind == "exponential" and t_eps and abs(t_next - t_eps) <= CUTOFF_ABS:
-            amb = True
-    return res, amb
+        if op.kind != "exponential":
+            near = abs(t_next) <= CUTOFF_ABS
+        elif t_eps is not None and t_eps > UNDERFLOW:
+            near = abs(t_next - t_eps) <= CUTOFF_ABS
+        else:
+            near = t_next < UNDERFLOW and not (res["done"] and i == res["k"])
+        if near:
+            out.append((i, 1))
+    return out
+
+
+def composite_pixel(alphas, rgb, op, alpha_min, t_eps, background, max_outcomes=4096):
+    """Composite one pixel's front-to-back list (alphas already >= alpha_min
+    or near it).
+
+    Returns (res, outcomes, amb_alpha, amb_cut): `res` is the plain
+    definition (operators.composite_sequence); `outcomes` lists (L, T_final,
+    od) for the definition and for every combination of boundary decisions
+    taken the other way (each flipped decision within reach of float32
+    rounding in the sequence that the earlier flips produce), the
+    definition first; amb_alpha / amb_cut: the definition has an alpha_min
+    boundary decision / a cutoff boundary decision."""
+    outcomes = []
+
+    def run(flips, after):
+        r = _ops.composite_sequence(alphas, op, rgb, background, alpha_min, t_eps,
+                                    flips=flips)
+        outcomes.append((r["L"], r["T_final"], r["od"]))
+        if len(outcomes) > max_outcomes:
+            raise RuntimeError("more than %d boundary outcomes at one pixel" % max_outcomes)
+        dec = boundary_decisions(alphas, r, op, alpha_min, t_eps)
+        for d in dec:
+            if d > after:
+                run(flips | {d}, d)
+        return r, dec
+
+    res, dec = run(frozenset(), (-1, -1))
+    amb_alpha = any(s == 0 for _, s in dec)
+    amb_cut = any(s != 0 for _, s in dec)
+    return res, outcomes, amb_alpha, amb_cut
 
 
 def render(scene, cam, op, alpha_min=1e-3, t_eps=None, background=(0.0, 0.0, 0.0),
@@ -102,8 +152,12 @@ def render(scene, cam, op, alpha_min=1e-3, t_eps=None, background=(0.0, 0.0, 0.0
     """Render `pixels` (an [P,2] int array of (x, y); default: the whole image).
 
     op: an operators.Op (or a library model id 0..3).  t_eps defaults to 1e-4
-    for the exponential (and Vicini's exponential part) and 0 otherwise.  Returns a dict of per-pixel arrays:
-    rgb [P,3], trans [P], od [P] (int), ambiguous [P] (bool), pixels [P,2].
+    for the exponential (and Vicini's exponential part) and 0 otherwise.
+    Returns a dict of per-pixel arrays: rgb [P,3], trans [P], od [P] (int),
+    amb_alpha / amb_cut / ambiguous [P] (bool: an alpha_min boundary, a
+    cutoff boundary, either), pixels [P,2]; and `outcomes`, a dict from the
+    index of every flagged pixel to its list of legitimate (rgb, trans, od)
+    (composite_pixel), the definition's first.
     """
     if isinstance(op, int):
         op = _ops.MODELS[op]
@@ -128,7 +182,9 @@ def render(scene, cam, op, alpha_min=1e-3, t_eps=None, background=(0.0, 0.0, 0.0
     rgb = np.zeros((P, 3))
     trans = np.zeros(P)
     od = np.zeros(P, np.int64)
-    amb = np.zeros(P, bool)
+    amb_alpha = np.zeros(P, bool)
+    amb_cut = np.zeros(P, bool)
+    outcomes = {}
     cell_of = (pixels[:, 1] // CELL) * ncx + pixels[:, 0] // CELL
     for cell in np.unique(cell_of):
         sel = np.nonzero(cell_of == cell)[0]
@@ -143,13 +199,17 @@ def render(scene, cam, op, alpha_min=1e-3, t_eps=None, background=(0.0, 0.0, 0.0
                 a_p, g_p = al[r][keep], cand[keep]
             else:
                 a_p, g_p = np.zeros(0), cand
-            res, amb_p = composite_pixel(list(a_p), proj["rgb"][g_p], op,
-                                         alpha_min, t_eps, bg)
+            res, outs, aa, ac = composite_pixel(list(a_p), proj["rgb"][g_p], op,
+                                                alpha_min, t_eps, bg)
             rgb[pi] = res["L"]
             trans[pi] = res["T_final"]
             od[pi] = res["od"]
-            amb[pi] = amb_p
-    return {"rgb": rgb, "trans": trans, "od": od, "ambiguous": amb, "pixels": pixels}
+            amb_alpha[pi], amb_cut[pi] = aa, ac
+            if aa or ac:
+                outcomes[pi] = outs
+    return {"rgb": rgb, "trans": trans, "od": od, "amb_alpha": amb_alpha,
+            "amb_cut": amb_cut, "ambiguous": amb_alpha | amb_cut,
+            "outcomes": outcomes, "pixels": pixels}
 
 
 def render_brute(scene, cam, op, alpha_min=1e-3, t_eps=None, background=(0.0, 0.0, 0.0)):

@@ -2,9 +2,11 @@
 
 Tolerances: tile keys, sort order, tile ranges, per-Gaussian depth bits and
 tile rectangles bit-exact; colour and transmittance within 1e-4 absolute per
-channel; overdraw exact except at pixels the oracle flags as boundary cases
-(an alpha within 1e-5 relative of alpha_min, or a transmittance step within
-1e-6 of the cutoff).
+channel at every pixel without an alpha_min boundary splat; overdraw exact
+except at pixels the oracle flags as boundary cases (an alpha within 1e-5
+relative of alpha_min, or a transmittance step within 1e-6 of the cutoff),
+where colour, transmittance and overdraw must match one of the oracle's
+legitimate outcomes.
 """
 import math
 
@@ -119,18 +121,17 @@ def test_emission_of_large_footprints(R, tile):
     depth-sorted slots then emit 16K-220K tile instances (many windows of
     the emission's owner map, runs crossing window edges) and about half to
     nine tenths of the runs are longer than 32 tiles (marked by a whole wave
-    rather than one thread).  Keys bit-exact; sampled pixels, of which the
-    oracle flags about one in eight as boundary cases under the exponential
-    model here (some 76 composited splats per pixel, each a chance of an
-    alpha within 1e-5 of alpha_min or a step near the cutoff), so the cap on
-    flagged pixels is raised to a quarter."""
+    rather than one thread).  Keys bit-exact; sampled pixels against the
+    oracle (about one in eight is a boundary case under the exponential
+    model here, some 76 composited splats per pixel: those must match one of
+    the oracle's legitimate outcomes)."""
     sc = synth.random_scene(13, 2500, sh_degree=0, log_scale=(-2.2, 0.9))
     cam = synth.look_at_camera((0, 0, -3), width=256, height=192)
     px = parity.sample_pixels(cam, 300, seed=4)
     for model in (0, 1):
         out = _render(R, sc, [cam], model, tile=tile)
         parity.compare_keys(R, sc, [cam], tile_w=tile[0], tile_h=tile[1])
-        parity.compare_view(out[0], sc, cam, model, pixels=px, max_ambiguous=0.25)
+        parity.compare_view(out[0], sc, cam, model, pixels=px)
 
 
 def test_sh_degree3_and_background(R):
@@ -240,14 +241,14 @@ def scene_scale():
 def test_scene_scale_1m_1080p(R, scene_scale, model):
     """The benchmark workload (1M Gaussians, SH degree 3, 1920x1080) in the
     benchmark's launch configuration: every key and the tile ranges
-    bit-exact, 1,500 sampled pixels against the oracle."""
+    bit-exact, 4,096 sampled pixels against the oracle."""
     sc, cams = scene_scale
     out = _render(R, sc, cams, model)
     if model == 0:
         m = parity.compare_keys(R, sc, cams)
         print("instances", m)
     st = parity.compare_view(out[0], sc, cams[0], model,
-                             pixels=parity.sample_pixels(cams[0], 1500, seed=model))
+                             pixels=parity.sample_pixels(cams[0], 4096, seed=model))
     print("scene", model, st)
 
 

@@ -219,12 +219,13 @@ def _diff_workload():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("model,op,n_focus", [(3, O.SUPERLINEAR, 16), (0, O.EXPONENTIAL, 8)])
-def test_gradients_at_workload_size(R, model, op, n_focus):
+@pytest.mark.parametrize("model,op", [(0, O.EXPONENTIAL), (1, O.LINEAR), (2, O.SUBLINEAR),
+                                      (3, O.SUPERLINEAR)])
+def test_gradients_at_workload_size(R, model, op):
     """500,000 Gaussians, 8 views at 1280x720, per-pixel L1 loss against a
-    render of the jittered scene: gradients of random parameters (4 per
-    Gaussian, over visible Gaussians drawn among those with footprints under 4 px in
-    every view) against FP64 central differences (tests/fd_local.py)."""
+    render of the jittered scene: gradients of 64 random parameters (4 per
+    Gaussian, over 16 visible Gaussians drawn among those with footprints under
+    4 px in every view) against FP64 central differences (tests/fd_local.py)."""
     from oracle import project as P
     from paper_2603_02887_amd import nxs
     from tests import fd_local
@@ -251,26 +252,26 @@ def test_gradients_at_workload_size(R, model, op, n_focus):
     torch.cuda.synchronize()
     live = G0["opacities"].abs().cpu().numpy() > 0
     rng = np.random.default_rng(77 + model)
-    focus = rng.choice(np.nonzero(seen & (smax < 4.0) & live)[0], n_focus, replace=False)
-    L = fd_local.LocalLoss(sc, cams, op, focus)
-    L.mask_weights(w)
-    R.render(g, cams, model=model, overdraw=False, keep_state=True)
-    G = R.backward(g, [torch.from_numpy(a).float().cuda() for a in w])
-    torch.cuda.synchronize()
-    G = {k: v.double().cpu().numpy() for k, v in G.items()}
+    focus = rng.choice(np.nonzero(seen & (smax < 4.0) & live)[0], 16, replace=False)
     params = fd.params_of(sc)
     fields = [("means", (0,)), ("means", (1,)), ("means", (2,)), ("scales", (0,)),
               ("scales", (2,)), ("quats", (1,)), ("quats", (3,)), ("opacities", ()),
               ("sh", (0, 0)), ("sh", (0, 2))]
-    got, want = [], []
+    items = []
     for i in focus:
         for f in rng.choice(len(fields), 4, replace=False):
             field, sub = fields[f]
             idx = (int(i),) + sub
             h = H_STEP * (abs(params[field][idx]) if field == "scales" else 1.0)
-            want.append(L.grad_element(params, w, field, idx, h))
-            got.append(G[field][idx])
-    got, want = np.array(got), np.array(want)
+            items.append((field, idx, h))
+    with fd_local.LocalLoss(sc, cams, op, focus) as L:
+        L.mask_weights(w)
+        R.render(g, cams, model=model, overdraw=False, keep_state=True)
+        G = R.backward(g, [torch.from_numpy(a).float().cuda() for a in w])
+        torch.cuda.synchronize()
+        G = {k: v.double().cpu().numpy() for k, v in G.items()}
+        want = np.array(L.grad_elements(w, items))
+    got = np.array([G[field][idx] for field, idx, _ in items])
     scale = np.abs(want).max()
     tol = 2e-3 * np.abs(want) + 2e-4 * scale
     bad = np.nonzero(np.abs(got - want) > tol)[0]

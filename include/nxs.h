@@ -18,12 +18,18 @@
  *   - The caller owns every input and output buffer.  Inputs must stay
  *     unmodified and alive until the stream has passed the call's work.
  *     Outputs are fully overwritten; they need no clearing.
- *   - The context owns its workspace (device memory grown on demand with
- *     hipMalloc and kept until nxs_destroy) and a small pinned host buffer.
+ *   - The context owns its workspace: device memory grown on demand, in
+ *     stream order, from the caller's allocator (nxs_create) or, without
+ *     one, from a memory pool of the library's own, and kept until
+ *     nxs_destroy or nxs_release_workspace; and a small pinned host buffer.
+ *     A forward that keeps backward state hands the buffers the backward
+ *     needs to an nxs_fwd_state, which owns them until nxs_state_release.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
- *     nxs_render_forward synchronises that stream once, after projection,
- *     to read the number of tile instances and size the workspace; it
- *     returns once the remaining work is enqueued.
+ *     nxs_render_forward waits once on the host, after projection, for the
+ *     number of tile instances that sizes the workspace, unless the render
+ *     is deferred (NXS_FLAG_DEFERRED): it then waits for nothing and a
+ *     render that outgrew the workspace is reported by
+ *     nxs_forward_status.  Calls return once their work is enqueued.
  *   - No exception crosses the ABI.  Every call returns an nxs_status; for
  *     a non-OK status nxs_last_error() gives a message.  Arguments are
  *     checked before any launch, so NXS_EINVAL leaves outputs untouched.
@@ -45,10 +51,12 @@ typedef enum {
   NXS_EINVAL = -1,       /* bad argument; nothing was launched */
   NXS_ENOMEM = -2,       /* workspace allocation failed */
   NXS_EHIP = -3,         /* a HIP runtime call failed; see nxs_last_error */
-  NXS_ECAPACITY = -4,    /* more than 2^32 - 1 tile instances, or more workspace
-                            than the context's limit allows (outputs undefined;
-                            retry with fewer views or after
-                            nxs_release_workspace) */
+  NXS_ECAPACITY = -4,    /* more than 2^32 - 1 tile instances, more workspace
+                            than the context's limit (or the no-alloc entry
+                            point's scratch) allows, or a deferred render
+                            that outgrew the workspace (outputs undefined;
+                            retry, with fewer views where the limit is the
+                            cause) */
   NXS_EUNSUPPORTED = -5  /* operation not supported for these arguments (e.g. a
                             backward of a model that has none) */
 } nxs_status;
@@ -125,12 +133,26 @@ typedef struct {
                              0 -> 1e-4, < 0 -> only once T falls below the
                              smallest normal float32 (1.2e-38) */
   int32_t tile_w, tile_h; /* 8x8, 16x16 or 32x8; 0 -> 16x16 */
-  int32_t lds_batch;      /* accepted for compatibility: 0, 128, 256, 512 (the
-                             composite walks its tile in batches of 64 splats) */
+  int32_t lds_batch;      /* sorted-list entries each wave of the composite
+                             gathers into LDS per round, culls against its
+                             8x8 block and then composites: 64, 128 or 256;
+                             0 -> 64 */
   float param;            /* operator parameter of models 4..7 (c, gamma or v) */
-  int32_t keep_state;     /* nonzero: keep what nxs_render_backward needs */
+  int32_t flags;          /* NXS_FLAG_* */
   int32_t schedule;       /* nxs_schedule of the composite; 0 -> NXS_SCHED_QUEUE */
 } nxs_render_opts;
+
+/* opts.flags
+ *   NXS_FLAG_DEFERRED  the forward does not wait on the host for the
+ *       instance count: the instance buffers and the grids of the tile sort
+ *       are sized from the context's current capacity (what earlier renders
+ *       needed, with headroom).  A render that needs more instances than that
+ *       (or a depth sort of more passes than the context planned) is detected
+ *       on the device, does no work after the emission (its outputs are the
+ *       background) and is reported by the next nxs_forward_status, which
+ *       also grows the capacity so that repeating the render succeeds.
+ *       Results are bitwise those of a render that waits. */
+#define NXS_FLAG_DEFERRED 1
 
 /* How the composite's work is laid onto the GPU (results are bitwise the same
  * under all four; only the time differs):
@@ -161,19 +183,58 @@ typedef struct {
 
 typedef struct nxs_context nxs_context;
 
-/* Creates a context on HIP device `device`.  *ctx receives the handle. */
-nxs_status nxs_create(nxs_context** ctx, int device);
+/* What a forward keeps for its backward (appendix "Adjoints": the per-pixel
+ * final values and the sorted splat lists the path replay re-walks). */
+typedef struct nxs_fwd_state nxs_fwd_state;
 
-/* Frees the workspace (waiting for the device first) and the context. */
+/* Device allocator of the caller (e.g. a framework's caching allocator).
+ *   alloc(bytes, stream, user): device memory of at least `bytes` bytes on
+ *       the context's device, usable by work enqueued on `stream` after the
+ *       call; NULL on failure (the render then fails with NXS_ENOMEM).
+ *   free(ptr, stream, user): gives back a block from alloc.  Work enqueued
+ *       on `stream` before the call may still use it, and all other work
+ *       that used it is ordered before that point of `stream`: the
+ *       allocator must not hand the block to work that can run earlier
+ *       (a stream-ordered free).
+ * Both are called from inside nxs_* calls on the calling thread. */
+typedef void* (*nxs_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*nxs_free_fn)(void* ptr, void* stream, void* user);
+
+/* Creates a context on HIP device `device`; *ctx receives the handle.
+ * alloc and free: the caller's allocator (both or neither; `user` is passed
+ * back to them).  Without them the workspace comes from a stream-ordered
+ * memory pool the context creates (hipMallocFromPoolAsync / hipFreeAsync),
+ * so that growing it never waits for the device. */
+nxs_status nxs_create(nxs_context** ctx, int device, nxs_alloc_fn alloc, nxs_free_fn free,
+                      void* user);
+
+/* Waits for the context's work, then frees the workspace and the context.
+ * States the caller has not released stay valid until it releases them. */
 nxs_status nxs_destroy(nxs_context* ctx);
 
-/* Renders n_views >= 1 views of the same Gaussians.
+/* Renders n_views >= 1 views of the same Gaussians (Sec. 4, eq.
+ * generalized_gaussian with the operator of opts.model).
  *   cams [n_views] host array; out [n_views] host array of device outputs.
- * Views may differ in size; all share opts.  n = 0 renders background. */
+ * Views may differ in size; all share opts.  n = 0 renders background.
+ *   state  NULL: nothing is kept for a backward.  Otherwise *state receives
+ *          a new nxs_fwd_state holding what nxs_render_backward needs (the
+ *          sorted splat lists and records, the tile ranges and order, 12
+ *          floats per pixel); the caller releases it with nxs_state_release.
+ *          Models 0..4 only (NXS_EUNSUPPORTED otherwise).  On failure
+ *          *state is NULL. */
 nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
                               const nxs_camera* cams, int32_t n_views,
                               const nxs_render_opts* opts, const nxs_image* out,
-                              void* stream);
+                              nxs_fwd_state** state, void* stream);
+
+/* Outcome of the deferred forwards (NXS_FLAG_DEFERRED) on the context since
+ * the last call: waits for the context's last render, then returns NXS_OK,
+ * or NXS_ECAPACITY if any of them outgrew the workspace (their outputs are
+ * the background; their states, if any, hold no lists).  Before returning
+ * NXS_ECAPACITY it grows the instance capacity to the largest count
+ * needed (within the workspace limit), so repeating those renders succeeds.
+ * needed (may be NULL): the largest instance count any of them needed. */
+nxs_status nxs_forward_status(nxs_context* ctx, int64_t* needed);
 
 /* Gradients of the Gaussians' parameters, device arrays shaped like the
  * inputs of nxs_gaussians (means [n,3], scales [n,3], quats [n,4],
@@ -186,9 +247,10 @@ typedef struct {
   float* sh;
 } nxs_gaussians_grad;
 
-/* Path-replay backward of the last nxs_render_forward on this context, which
- * must have had opts.keep_state set (appendix "Adjoints": the linear and
- * quadratic recursions; the front-to-back form for the exponential).
+/* Path-replay backward of the forward that made `state` (appendix
+ * "Adjoints": the linear and quadratic recursions; the front-to-back form
+ * for the exponential).
+ *   state     from nxs_render_forward on this context, not yet released
  *   dL_drgb   [n_views] host array of device [H,W,3] upstream gradients
  *   dL_dtrans [n_views] host array of device [H,W] gradients, or NULL (the
  *             array itself, or any entry, may be NULL for "zero")
@@ -197,25 +259,34 @@ typedef struct {
  *             to float32 rounding, not bitwise
  * Each tile's splats are re-walked front to back, rebuilding every pixel's
  * state from the start with the same float32 decisions as the forward;
- * nothing is stored per splat, only 12 floats per pixel.  The Gaussians and
- * camera inputs of the forward must be unchanged.  Models 0..4 only
- * (NXS_EUNSUPPORTED otherwise).  NXS_EINVAL if the last forward on the
- * context (failed ones included) did not keep its state, or on a NULL
- * dL_drgb entry or gradient array.  Enqueued on `stream` after that forward;
- * the gradients are complete when the stream reaches this point. */
-nxs_status nxs_render_backward(nxs_context* ctx, const float* const* dL_drgb,
-                               const float* const* dL_dtrans,
+ * nothing is stored per splat, only 12 floats per pixel.  The Gaussians of
+ * the forward must be unchanged.  Any number of backwards may use one state,
+ * and other forwards may run between its forward and its backward.
+ * NXS_EINVAL on a NULL state, dL_drgb entry or gradient array, or a state
+ * of another context; NXS_ECAPACITY for the state of a deferred forward that
+ * outgrew the workspace.  Enqueued on `stream` after the context's earlier
+ * calls; the gradients are complete when the stream reaches this point. */
+nxs_status nxs_render_backward(nxs_context* ctx, const nxs_fwd_state* state,
+                               const float* const* dL_drgb, const float* const* dL_dtrans,
                                const nxs_gaussians_grad* grads, void* stream);
 
-/* Measured choice of tile shape and composite schedule for one workload. */
+/* Frees a state (stream-ordered on `stream`, after every call that used it).
+ * NULL state: nothing. */
+nxs_status nxs_state_release(nxs_context* ctx, nxs_fwd_state* state, void* stream);
+
+/* Measured choice of tile shape, composite schedule and LDS batch for one
+ * workload. */
 typedef struct {
   int32_t tile_w, tile_h;
   int32_t schedule;       /* nxs_schedule */
+  int32_t lds_batch;      /* list entries gathered per round (64, 128, 256) */
   float ms;               /* median render time of the choice when measured */
 } nxs_tuning;
 
-/* Autotuner: the tile shape (8x8, 16x16, 32x8) and composite schedule with the
- * lowest median time of a whole nxs_render_forward on this workload.
+/* Autotuner: the tile shape (8x8, 16x16, 32x8), composite schedule and LDS
+ * batch (64, 128, 256 list entries per round) with the lowest median time
+ * of a whole nxs_render_forward on this workload: every tile shape and
+ * schedule at a batch of 64, then the other batches at the best of those.
  * The result is cached per (GPU architecture, CU count, n, SH degree, model,
  * number and sizes of the views): first in the context, then, if cache_path
  * is not NULL, in that text file (one line per workload; read on a miss,
@@ -223,8 +294,9 @@ typedef struct {
  * every candidate is rendered once untimed and `reps` times (0 -> 5) timed
  * with events on `stream`, writing `out` (the outputs are those of the last
  * candidate) and synchronising the stream.  Other fields of `opts` are used
- * as given; its tile and schedule fields are ignored.  Errors as for
- * nxs_render_forward; an unreadable or unwritable cache file is ignored. */
+ * as given; its tile, schedule and lds_batch fields are ignored.  Errors as
+ * for nxs_render_forward; an unreadable or unwritable cache file is
+ * ignored. */
 nxs_status nxs_autotune(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* cams,
                         int32_t n_views, const nxs_render_opts* opts, const nxs_image* out,
                         const char* cache_path, int32_t reps, nxs_tuning* result,
@@ -232,9 +304,10 @@ nxs_status nxs_autotune(nxs_context* ctx, const nxs_gaussians* g, const nxs_came
 
 /* Workspace: the device memory a context keeps between renders (sort
  * buffers, per-slot and per-instance records), grown on demand and never
- * shrunk.  With a limit set (bytes; 0 = none), a render that would grow it past
- * the limit returns NXS_ECAPACITY.  nxs_release_workspace synchronises the
- * device and frees all of it (it also ends any kept backward state). */
+ * shrunk; states hold their own buffers and are not counted.  With a limit
+ * set (bytes; 0 = none), a render that would grow it past the limit returns
+ * NXS_ECAPACITY.  nxs_release_workspace waits for the context's work and
+ * frees all of it (states stay valid). */
 nxs_status nxs_set_workspace_limit(nxs_context* ctx, size_t bytes);
 nxs_status nxs_workspace_bytes(const nxs_context* ctx, size_t* bytes);
 nxs_status nxs_release_workspace(nxs_context* ctx);
@@ -267,7 +340,10 @@ nxs_status nxs_server_destroy(nxs_server* server);
 nxs_status nxs_server_add_scene(nxs_server* server, const nxs_gaussians* g,
                                 int32_t* scene_id);
 /* Queue one view of a scene; `out` (device images, caller-owned) is written
- * before a step reports the request.  opts.keep_state must be 0. */
+ * before a step reports the request.  Served renders keep no backward state;
+ * opts.flags must be 0 (the server defers every batch itself: a batch that
+ * outgrows its slot's workspace is detected when it completes and rendered
+ * again, after the slot has grown or the batch has been split). */
 nxs_status nxs_server_submit(nxs_server* server, int32_t scene_id, const nxs_camera* cam,
                              const nxs_render_opts* opts, const nxs_image* out, int64_t tag);
 /* One scheduling step.  tags / status: host arrays of `capacity` entries

@@ -48,8 +48,9 @@ namespace nxs {
 
 namespace {
 
-// One wave composites the 8x8 block `wid` of global tile `tile`.
-template <int MODEL, int TW, int TH, bool STATE>
+// One wave composites the 8x8 block `wid` of global tile `tile`, gathering
+// NB batches of 64 list entries per round (wlds holds NB * kStageF4).
+template <int MODEL, int TW, int TH, bool STATE, int NB>
 __device__ __forceinline__ void composite_block(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec,
@@ -89,26 +90,41 @@ __device__ __forceinline__ void composite_block(
   float ek0 = prm.bg[0], ek1 = prm.bg[1], ek2 = prm.bg[2], tau_s = 0.0f;
   float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
 
-  // Batches of 64 list entries are staged in LDS (only the splats that reach
-  // the block); each staged splat is then visited by the whole wave.  The
-  // per-pixel update is branch-free: a lane whose alpha is below alpha_min,
-  // or which has stopped, composites a = 0, which leaves every operator's
-  // state unchanged, so the loop carries no per-lane control flow.
-  // Each batch is staged against the rows and columns that still hold a
-  // running pixel (act: the wave's running lanes).
+  // Rounds of NB batches of 64 list entries are staged in LDS (only the
+  // splats that reach the block, in list order); each staged splat is then
+  // visited by the whole wave.  The per-pixel update is branch-free: a lane
+  // whose alpha is below alpha_min, or which has stopped, composites a = 0,
+  // which leaves every operator's state unchanged, so the loop carries no
+  // per-lane control flow.  Each round is staged against the rows and
+  // columns that still hold a running pixel (act: the wave's running lanes).
+  // Slot indices are read two rounds ahead and records one round ahead.
+  constexpr uint32_t kRound = 64u * NB;
   uint64_t act = __builtin_amdgcn_ballot_w64(!op.stopped(t_eps));
   // (an empty tile fetches nothing: its range is [0, 0) or [x, x))
-  StageSlot slots{0u, false};
-  StageFetch fetched{};
-  if (rg.x < rg.y) {
-    slots = stage_slot(inst_val, rg.x, rg.y, lane);
-    fetched = stage_records(slots, rec);
-    slots = stage_slot(inst_val, (uint64_t)rg.x + 64, rg.y, lane);
+  StageSlot slots[NB];
+  StageFetch fetched[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    slots[k] = StageSlot{0u, false};
+    fetched[k] = StageFetch{};
   }
-  for (uint32_t base = rg.x; base < rg.y && act != 0; base += 64) {
-    const uint32_t n = stage_batch(fetched, stage_shrink(sb, act), wlds);
-    fetched = stage_records(slots, rec);                              // batch base + 64
-    slots = stage_slot(inst_val, (uint64_t)base + 128, rg.y, lane);   // batch base + 128
+  if (rg.x < rg.y) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      slots[k] = stage_slot(inst_val, (uint64_t)rg.x + 64u * k, rg.y, lane);
+      fetched[k] = stage_records(slots[k], rec);
+      slots[k] = stage_slot(inst_val, (uint64_t)rg.x + kRound + 64u * k, rg.y, lane);
+    }
+  }
+  for (uint32_t base = rg.x; base < rg.y && act != 0; base += kRound) {
+    const StageBlock sbr = stage_shrink(sb, act);
+    uint32_t n = 0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      n += stage_batch(fetched[k], sbr, wlds + 3 * n);
+      fetched[k] = stage_records(slots[k], rec);                                 // next round
+      slots[k] = stage_slot(inst_val, (uint64_t)base + 2 * kRound + 64u * k, rg.y, lane);
+    }
     for (const float4 *r = wlds, *r_end = wlds + 3 * n; r != r_end; r += 3) {
       const float4 q0 = r[0], q1 = r[1];
       const float c[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, r[2].x};
@@ -157,61 +173,64 @@ __device__ __forceinline__ void composite_block(
 
 constexpr int kBlocksPerTile(int tw, int th) { return (tw / 8) * (th / 8); }
 
-template <int MODEL, int TW, int TH, bool STATE>
+template <int MODEL, int TW, int TH, bool STATE, int NB>
 __global__ __launch_bounds__(TW* TH) void composite_tiles_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
     float4* __restrict__ pstate, uint32_t n_tiles, uint32_t per_xcd) {
-  __shared__ float4 stage[kBlocksPerTile(TW, TH) * kStageF4];
+  __shared__ float4 stage[kBlocksPerTile(TW, TH) * NB * kStageF4];
   const uint32_t tile = xcd_banded(blockIdx.x, per_xcd);
   if (tile >= n_tiles) return;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
-                                        stage + wid * kStageF4, tile, wid, threadIdx.x & 63);
+  composite_block<MODEL, TW, TH, STATE, NB>(views, n_views, ranges, inst_val, rec, prm,
+                                            pstate, stage + wid * NB * kStageF4, tile, wid,
+                                            threadIdx.x & 63);
 }
 
-template <int MODEL, int TW, int TH, bool STATE>
+template <int MODEL, int TW, int TH, bool STATE, int NB>
 __global__ __launch_bounds__(64) void composite_blocks_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
     float4* __restrict__ pstate, uint32_t n_items, uint32_t per_xcd) {
-  __shared__ float4 stage[kStageF4];
+  __shared__ float4 stage[NB * kStageF4];
   constexpr int B = kBlocksPerTile(TW, TH);
   const uint32_t item = xcd_banded(blockIdx.x, per_xcd);
   if (item >= n_items) return;
-  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
-                                        stage, item / B, (int)(item % B), threadIdx.x);
+  composite_block<MODEL, TW, TH, STATE, NB>(views, n_views, ranges, inst_val, rec, prm,
+                                            pstate, stage, item / B, (int)(item % B),
+                                            threadIdx.x);
 }
 
 // The ordered queue dealt to the 8 XCDs (which receive work-groups
 // round-robin) at tile granularity: work-group w, the i-th on XCD x = w mod 8,
 // takes block (i mod B) of the tile of rank 8 (i / B) + x in the order, so the
 // longest tiles start first on every XCD and each tile's blocks share one L2.
-template <int MODEL, int TW, int TH, bool STATE>
+template <int MODEL, int TW, int TH, bool STATE, int NB>
 __global__ __launch_bounds__(64) void composite_ordered_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
     float4* __restrict__ pstate, const uint32_t* __restrict__ order, uint32_t n_tiles) {
-  __shared__ float4 stage[kStageF4];
+  __shared__ float4 stage[NB * kStageF4];
   constexpr int B = kBlocksPerTile(TW, TH);
   const uint32_t x = blockIdx.x % kQueues, i = blockIdx.x / kQueues;
   const uint32_t r = (i / B) * kQueues + x;
   if (r >= n_tiles) return;
-  composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
-                                        stage, order[r], (int)(i % B), threadIdx.x);
+  composite_block<MODEL, TW, TH, STATE, NB>(views, n_views, ranges, inst_val, rec, prm,
+                                            pstate, stage, order[r], (int)(i % B),
+                                            threadIdx.x);
 }
 
 // Queue q (the work-group's XCD under round-robin dispatch) hands out the
 // tiles order[q], order[q + 8], ...; the wave composites each tile's blocks in
 // turn.  Every queue has work-groups (the grid is a multiple of 8), and every
 // wave leaves once its queue is drained.
-template <int MODEL, int TW, int TH, bool STATE>
+template <int MODEL, int TW, int TH, bool STATE, int NB>
 __global__ __launch_bounds__(64) void composite_queue_kernel(
     const ViewDev* __restrict__ views, int n_views, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ inst_val, const float4* __restrict__ rec, CompositeParams prm,
     float4* __restrict__ pstate, const uint32_t* __restrict__ order, uint32_t n_tiles,
     uint32_t* __restrict__ queue) {
-  __shared__ float4 stage[kStageF4];
+  __shared__ float4 stage[NB * kStageF4];
   constexpr int B = kBlocksPerTile(TW, TH);
   const int lane = threadIdx.x;
   const uint32_t q = blockIdx.x % kQueues;
@@ -223,8 +242,8 @@ __global__ __launch_bounds__(64) void composite_queue_kernel(
     if (i >= n_tiles) break;
     const uint32_t tile = order[i];
     for (int b = 0; b < B; ++b)
-      composite_block<MODEL, TW, TH, STATE>(views, n_views, ranges, inst_val, rec, prm, pstate,
-                                            stage, tile, b, lane);
+      composite_block<MODEL, TW, TH, STATE, NB>(views, n_views, ranges, inst_val, rec, prm,
+                                                pstate, stage, tile, b, lane);
   }
 }
 
@@ -307,42 +326,54 @@ void launch_composite_order(const CompositeLaunch& L, hipStream_t s) {
 
 namespace {
 
-template <int MODEL, int TW, int TH, bool STATE>
+template <int MODEL, int TW, int TH, bool STATE, int NB>
 void launch_s(const CompositeLaunch& L, const CompositeParams& p, float4* pstate,
               hipStream_t s) {
   constexpr int B = kBlocksPerTile(TW, TH);
   if (L.schedule == NXS_SCHED_TILES) {
     const uint32_t per = (uint32_t)((L.n_tiles + 7) / 8);
-    hipLaunchKernelGGL((composite_tiles_kernel<MODEL, TW, TH, STATE>), dim3(per * 8),
+    hipLaunchKernelGGL((composite_tiles_kernel<MODEL, TW, TH, STATE, NB>), dim3(per * 8),
                        dim3(TW * TH), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
                        pstate, (uint32_t)L.n_tiles, per);
   } else if (L.schedule == NXS_SCHED_BLOCKS) {
     const int64_t items = L.n_tiles * B;
     const uint32_t per = (uint32_t)((items + 7) / 8);
-    hipLaunchKernelGGL((composite_blocks_kernel<MODEL, TW, TH, STATE>), dim3(per * 8),
+    hipLaunchKernelGGL((composite_blocks_kernel<MODEL, TW, TH, STATE, NB>), dim3(per * 8),
                        dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
                        pstate, (uint32_t)items, per);
   } else if (L.schedule == NXS_SCHED_QUEUE) {
     const int64_t grid = (L.n_tiles + kQueues - 1) / kQueues * kQueues * B;
-    hipLaunchKernelGGL((composite_ordered_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((composite_ordered_kernel<MODEL, TW, TH, STATE, NB>), dim3((unsigned)grid),
                        dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
                        pstate, L.order, (uint32_t)L.n_tiles);
   } else {
     int64_t grid = std::min<int64_t>(L.n_tiles, (int64_t)L.n_cu * kQueueWavesPerCU);
     grid = std::max<int64_t>((grid + kQueues - 1) / kQueues, 1) * kQueues;
-    hipLaunchKernelGGL((composite_queue_kernel<MODEL, TW, TH, STATE>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((composite_queue_kernel<MODEL, TW, TH, STATE, NB>), dim3((unsigned)grid),
                        dim3(64), 0, s, L.views, L.n_views, L.ranges, L.inst_val, L.rec, p,
                        pstate, L.order, (uint32_t)L.n_tiles, L.sched_counters);
   }
 }
 
+template <int MODEL, int TW, int TH, bool STATE>
+void launch_b(const CompositeLaunch& L, const CompositeParams& p, float4* pstate,
+              hipStream_t s) {
+  if (p.lds_batch >= 256)
+    launch_s<MODEL, TW, TH, STATE, 4>(L, p, pstate, s);
+  else if (p.lds_batch >= 128)
+    launch_s<MODEL, TW, TH, STATE, 2>(L, p, pstate, s);
+  else
+    launch_s<MODEL, TW, TH, STATE, 1>(L, p, pstate, s);
+}
+
 template <int MODEL, int TW, int TH>
 void launch_t(const CompositeLaunch& L, const CompositeParams& p, float4* pstate,
               hipStream_t s) {
-  if (pstate)
-    launch_s<MODEL, TW, TH, true>(L, p, pstate, s);
+  // (state is kept only for the models that have a backward)
+  if (MODEL <= 4 && pstate)
+    launch_b<MODEL, TW, TH, MODEL <= 4>(L, p, pstate, s);
   else
-    launch_s<MODEL, TW, TH, false>(L, p, pstate, s);
+    launch_b<MODEL, TW, TH, false>(L, p, pstate, s);
 }
 
 template <int MODEL>

@@ -56,17 +56,45 @@ struct Counters {
   // the depth sort's digits (shift | width << 8 | kPassActive per pass),
   // from dmin ^ dmax
   uint32_t plan[4];
+  // a deferred render that cannot complete (kFail* bits; 0 otherwise): the
+  // kernels after the emission then do nothing
+  uint32_t fail;
+  uint32_t pad_;
 };
+constexpr uint32_t kFailCapacity = 1u;   // more instances than the capacity
+constexpr uint32_t kFailPlan = 2u;       // the depth sort skipped a pass it needs
+
+// The outcome of the deferred renders on a context since the host last read
+// it (device memory, cleared by the host).
+struct DeferredStatus {
+  unsigned long long need;   // largest instance count a failed render needed
+  uint32_t fail;             // OR of their kFail* bits
+  uint32_t count;            // failed renders
+};
+
+// What the projection's final fold checks for a deferred render.
+struct DeferCheck {
+  unsigned long long capacity;   // instance capacity (~0: not deferred)
+  int first_pass;                // first depth-sort pass launched (0 or 1)
+  DeferredStatus* status;        // updated when the render fails; may be null
+};
+
+// The instance count a kernel after the emission works on: 0 for a failed
+// deferred render.
+__device__ __forceinline__ int64_t live_count(const Counters* c) {
+  return c->fail ? 0 : (int64_t)c->total;
+}
 
 // ---- launchers (all enqueue on `s`) ------------------------------------------
 // `partials` needs project_partials_size(n) entries.  Also sets `counters`
-// (total instances, depth-bit range, depth-sort plan) and zeroes
-// clear[0, n_clear).
+// (total instances, depth-bit range, depth-sort plan, fail bits from `check`)
+// and zeroes clear[0, n_clear).
 size_t project_partials_size(int n);
 void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
                     float kappa2, float alpha_min, int tile_w, int tile_h,
                     const ProjDev& out, uint4* partials, Counters* counters,
-                    uint32_t* clear, int64_t n_clear, hipStream_t s);
+                    const DeferCheck& check, uint32_t* clear, int64_t n_clear,
+                    hipStream_t s);
 
 constexpr int kPlanPasses = 4;
 constexpr int kMaxDigitBits = 9;
@@ -77,10 +105,12 @@ constexpr uint32_t kPassActive = 1u << 16;
 // of the keys (at least one pass), ping-ponging through (k0, v0) and (k1, v1);
 // returns which pair holds the result (0 or 1).  vals_in == nullptr: values
 // are the input positions.  `counts` needs radix_counts_words(n) u32.
+// With `dn`, the number of pairs is read on the device (live_count(dn)) and
+// n is only its upper bound, which sizes the grids and the counts layout.
 size_t radix_counts_words(int64_t n);
 int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
-               hipStream_t s);
+               hipStream_t s, const Counters* dn = nullptr);
 // The same sort with its digits read from device memory: plan[p] = shift |
 // width << 8 | kPassActive for kPlanPasses passes (an active pass of width 0
 // copies).  Passes 1..3 are always active, pass 0 only when three digits of
@@ -118,14 +148,17 @@ void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted, i
 // tile-sorted instance list (tiles without instances keep what the caller
 // filled in, normally [0, 0)).
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s);
-void launch_ranges(const uint32_t* inst_tile, int64_t m, uint2* ranges, hipStream_t s);
+// m: the number of instances, or with `dn` its upper bound (the count itself
+// is then read on the device).
+void launch_ranges(const uint32_t* inst_tile, int64_t m, uint2* ranges, hipStream_t s,
+                   const Counters* dn = nullptr);
 
 struct CompositeParams {
   float log2_alpha_min;
   float t_eps;              // exponential termination threshold (<= 0: never)
   float param;              // operator parameter (c, gamma or v) for models 4..7
   float bg[3];
-  int32_t lds_batch;
+  int32_t lds_batch;        // list entries gathered per round: 64, 128 or 256
 };
 // pstate: null, or 3 float4 per pixel kept for the backward pass:
 //   (L0, L1, L2, T_final), (E_k, tau_k), (U, 0) with E_k the saturating splat's

@@ -177,10 +177,12 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 }
 
 // One work-group of NT threads folds the per-block partials into the counters
-// read by the host, and plans the depth sort.
+// read by the host, plans the depth sort and, for a deferred render, checks
+// that the render fits what was launched for it.
 constexpr int kFoldThreads = 1024;
 template <int NT>
-__device__ void fold_partials(const uint4* partials, int nblocks, Counters* c) {
+__device__ void fold_partials(const uint4* partials, int nblocks, Counters* c,
+                              const DeferCheck& chk) {
   __shared__ unsigned long long s_tot[NT / 64];
   __shared__ uint32_t s_mn[NT / 64], s_mx[NT / 64];
   unsigned long long tot = 0;
@@ -225,6 +227,16 @@ __device__ void fold_partials(const uint4* partials, int nblocks, Counters* c) {
       const int w = (nbits - shift + (kPlanPasses - p) - 1) / (kPlanPasses - p);
       c->plan[p] = (uint32_t)shift | ((uint32_t)w << 8) | kPassActive;
       shift += w;
+    }
+    uint32_t fail = 0u;
+    if (tot > chk.capacity) fail |= kFailCapacity;
+    if (chk.first_pass > first) fail |= kFailPlan;
+    c->fail = fail;
+    if (fail && chk.status) {
+      DeferredStatus* st = chk.status;
+      st->need = max(st->need, tot);
+      st->fail |= fail;
+      st->count += 1u;
     }
   }
 }
@@ -430,8 +442,9 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
 // One work-group folds the projection's per-block partials (none for a render
 // with no Gaussians) into the counters read by the host.
 __global__ __launch_bounds__(kFoldThreads) void reduce_counters_kernel(
-    const uint4* __restrict__ partials, int nblocks, Counters* __restrict__ c) {
-  fold_partials<kFoldThreads>(partials, nblocks, c);
+    const uint4* __restrict__ partials, int nblocks, Counters* __restrict__ c,
+    DeferCheck chk) {
+  fold_partials<kFoldThreads>(partials, nblocks, c, chk);
 }
 
 }  // namespace
@@ -439,7 +452,8 @@ __global__ __launch_bounds__(kFoldThreads) void reduce_counters_kernel(
 void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
                     float kappa2, float alpha_min, int tile_w, int tile_h,
                     const ProjDev& out, uint4* partials, Counters* counters,
-                    uint32_t* clear, int64_t n_clear, hipStream_t s) {
+                    const DeferCheck& check, uint32_t* clear, int64_t n_clear,
+                    hipStream_t s) {
   const bool any = g.n > 0 && n_views > 0;
   const int nblocks = any ? (g.n + kBlock - 1) / kBlock : 0;
 #define NXS_PROJECT(D)                                                                  \
@@ -458,7 +472,7 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
   }
 #undef NXS_PROJECT
   hipLaunchKernelGGL(reduce_counters_kernel, dim3(1), dim3(kFoldThreads), 0, s, partials,
-                     nblocks, counters);
+                     nblocks, counters, check);
 }
 
 size_t project_partials_size(int n) { return (size_t)((n + kBlock - 1) / kBlock) + 1; }

@@ -83,17 +83,30 @@ __device__ __forceinline__ void select_input(const uint32_t* plan, int pass,
   }
 }
 
+// The number of keys: n, or with dn the count read on the device (n is then
+// its upper bound).
+__device__ __forceinline__ int64_t key_count(int64_t n, const Counters* dn) {
+  return dn ? min(live_count(dn), n) : n;
+}
+
+template <int ITEMS>
+__device__ __forceinline__ uint32_t live_chunks(int64_t n) {
+  return (uint32_t)((n + kRThreads * ITEMS - 1) / (kRThreads * ITEMS));
+}
+
 template <int ITEMS>
 __global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* keys,
                                                       const uint32_t* keys_first, int64_t n,
                                                       int shift, int width,
                                                       const uint32_t* __restrict__ plan,
                                                       int pass, uint32_t nchunks, uint32_t per,
-                                                      uint32_t* __restrict__ counts) {
+                                                      uint32_t* __restrict__ counts,
+                                                      const Counters* __restrict__ dn) {
   __shared__ uint32_t h[kRBins];
   if (!pass_digit(plan, pass, shift, width)) return;   // the whole grid
   const uint32_t c = chunk_of(blockIdx.x, per);
-  if (c >= nchunks) return;                    // the whole work-group
+  n = key_count(n, dn);
+  if (c >= nchunks || c >= live_chunks<ITEMS>(n)) return;   // the whole work-group
   {
     const uint32_t* unused = nullptr;
     select_input(plan, pass, keys_first, nullptr, keys, unused);
@@ -145,17 +158,21 @@ __device__ __forceinline__ uint32_t rx_block_scan(uint32_t x, uint32_t* s_tmp, u
   return off + incl - x;
 }
 
-// One work-group per digit: exclusive scan of counts[d][0..nchunks) in place.
+// One work-group per digit: exclusive scan of counts[d][0..live chunks) in
+// place (rows of nchunks entries).
+template <int ITEMS>
 __global__ __launch_bounds__(kRThreads) void rx_scan(uint32_t* __restrict__ counts,
                                                      uint32_t nchunks,
                                                      uint32_t* __restrict__ totals, int width,
                                                      const uint32_t* __restrict__ plan,
-                                                     int pass) {
+                                                     int pass, int64_t n,
+                                                     const Counters* __restrict__ dn) {
   __shared__ uint32_t s_tmp[kRWaves];
   int shift = 0;
   if (!pass_digit(plan, pass, shift, width)) return;   // the whole grid
   if (blockIdx.x >= (1u << width)) return;    // the whole work-group
   uint32_t* row = counts + (int64_t)blockIdx.x * nchunks;
+  nchunks = min(nchunks, live_chunks<ITEMS>(key_count(n, dn)));
   uint32_t running = 0;
   for (uint32_t b = 0; b < nchunks; b += kRThreads * 4) {
     uint32_t v[4], sum = 0;
@@ -188,7 +205,7 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     const uint32_t* __restrict__ plan, int pass, uint32_t nchunks, uint32_t per,
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
     const uint4* __restrict__ tinfo, uint32_t* __restrict__ nt_out,
-    uint2* __restrict__ rect_out) {
+    uint2* __restrict__ rect_out, const Counters* __restrict__ dn) {
   __shared__ uint32_t s_key[(kRThreads * ITEMS)];
   __shared__ uint32_t s_val[(kRThreads * ITEMS)];
   __shared__ uint32_t s_wave[kRWaves][kRBins];
@@ -198,7 +215,8 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
 
   if (!pass_digit(plan, pass, shift, width)) return;   // the whole grid
   const uint32_t c = chunk_of(blockIdx.x, per);
-  if (c >= nchunks) return;                    // the whole work-group
+  n = key_count(n, dn);
+  if (c >= nchunks || c >= live_chunks<ITEMS>(n)) return;   // the whole work-group
   select_input(plan, pass, keys_first, vals_first, keys_in, vals_in);
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
@@ -307,7 +325,8 @@ namespace {
 int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int first, int passes,
                const int* shifts, const int* widths, const uint32_t* plan, uint32_t* counts,
-               const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
+               const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s,
+               const Counters* dn) {
   const bool large = n >= kRLargeFrom;
   const int chunk = kRThreads * (large ? kRItemsLarge : kRItemsSmall);
   const uint32_t nchunks = (uint32_t)((n + chunk - 1) / chunk);
@@ -320,23 +339,25 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
     const int shift = shifts ? shifts[p] : 0, width = widths ? widths[p] : 8;
     uint32_t* kout = (p & 1) ? k1 : k0;
     uint32_t* vout = (p & 1) ? v1 : v0;
-    if (large)
-      hipLaunchKernelGGL(rx_count<kRItemsLarge>, dim3(grid), dim3(kRThreads), 0, s, kin,
-                         keys_in, n, shift, width, plan, p, nchunks, per, counts);
-    else
-      hipLaunchKernelGGL(rx_count<kRItemsSmall>, dim3(grid), dim3(kRThreads), 0, s, kin,
-                         keys_in, n, shift, width, plan, p, nchunks, per, counts);
-    hipLaunchKernelGGL(rx_scan, dim3(plan ? kRBins : (1u << width)), dim3(kRThreads), 0, s,
-                       counts, nchunks, totals, width, plan, p);
+    const dim3 scan_grid(plan ? kRBins : (1u << width));
     const bool last = p == passes - 1;
-    if (large)
+    if (large) {
+      hipLaunchKernelGGL(rx_count<kRItemsLarge>, dim3(grid), dim3(kRThreads), 0, s, kin,
+                         keys_in, n, shift, width, plan, p, nchunks, per, counts, dn);
+      hipLaunchKernelGGL(rx_scan<kRItemsLarge>, scan_grid, dim3(kRThreads), 0, s, counts,
+                         nchunks, totals, width, plan, p, n, dn);
       hipLaunchKernelGGL(rx_scatter<kRItemsLarge>, dim3(grid), dim3(kRThreads), 0, s, kin, vin,
                          keys_in, vals_in, kout, vout, n, shift, width, plan, p, nchunks, per,
-                         counts, totals, last ? tinfo : nullptr, nt_out, rect_out);
-    else
+                         counts, totals, last ? tinfo : nullptr, nt_out, rect_out, dn);
+    } else {
+      hipLaunchKernelGGL(rx_count<kRItemsSmall>, dim3(grid), dim3(kRThreads), 0, s, kin,
+                         keys_in, n, shift, width, plan, p, nchunks, per, counts, dn);
+      hipLaunchKernelGGL(rx_scan<kRItemsSmall>, scan_grid, dim3(kRThreads), 0, s, counts,
+                         nchunks, totals, width, plan, p, n, dn);
       hipLaunchKernelGGL(rx_scatter<kRItemsSmall>, dim3(grid), dim3(kRThreads), 0, s, kin, vin,
                          keys_in, vals_in, kout, vout, n, shift, width, plan, p, nchunks, per,
-                         counts, totals, last ? tinfo : nullptr, nt_out, rect_out);
+                         counts, totals, last ? tinfo : nullptr, nt_out, rect_out, dn);
+    }
     kin = kout;
     vin = vout;
   }
@@ -347,7 +368,7 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
 
 int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
-               hipStream_t s) {
+               hipStream_t s, const Counters* dn) {
   if (n <= 0) return 0;
   nbits = std::max(nbits, 1);
   const int passes = (nbits + kMaxDigitBits - 1) / kMaxDigitBits;
@@ -358,7 +379,7 @@ int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
     shift += widths[p];
   }
   return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, 0, passes, shifts, widths, nullptr,
-                    counts, nullptr, nullptr, nullptr, s);
+                    counts, nullptr, nullptr, nullptr, s, dn);
 }
 
 int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
@@ -367,7 +388,7 @@ int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
                        const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
   if (n <= 0) return 1;
   return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, first_pass, kPlanPasses, nullptr,
-                    nullptr, plan, counts, tinfo, nt_out, rect_out, s);
+                    nullptr, plan, counts, tinfo, nt_out, rect_out, s, nullptr);
 }
 
 }  // namespace nxs

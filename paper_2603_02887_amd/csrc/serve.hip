@@ -151,7 +151,7 @@ bool start_batch(nxs_server* s, Slot& sl, std::vector<int64_t>& tags,
     }
     const double pixels = pixels_of(cur);
     st = nxs_render_forward(sl.ctx, &sc.g, cams.data(), V, &s->pending[idx[0]].opts,
-                            outs.data(), sl.stream);
+                            outs.data(), nullptr, sl.stream);
     int64_t m = 0, t = 0;
     nxs_inspect_counts(sl.ctx, &m, &t);
     if (st == NXS_OK) {
@@ -219,7 +219,7 @@ nxs_status nxs_server_create(int device, size_t workspace_budget, int32_t max_ba
   s->max_views = max_batch_views ? max_batch_views : 16;
   s->slots.resize(k);
   for (Slot& sl : s->slots) {
-    nxs_status st = nxs_create(&sl.ctx, device);
+    nxs_status st = nxs_create(&sl.ctx, device, nullptr, nullptr, nullptr);
     if (st == NXS_OK &&
         (hipSetDevice(device) != hipSuccess ||
          hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -262,7 +262,7 @@ nxs_status nxs_server_submit(nxs_server* s, int32_t scene_id, const nxs_camera* 
   if (scene_id < 0 || scene_id >= (int32_t)s->scenes.size())
     return sfail(s, NXS_EINVAL, "unknown scene %d", scene_id);
   if (!out->rgb || !out->trans) return sfail(s, NXS_EINVAL, "null output");
-  if (opts->keep_state) return sfail(s, NXS_EINVAL, "served renders keep no backward state");
+  if (opts->flags) return sfail(s, NXS_EINVAL, "served renders take no flags");
   s->pending.push_back({scene_id, *cam, *opts, *out, tag});
   return NXS_OK;
 }

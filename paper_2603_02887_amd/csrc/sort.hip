@@ -232,8 +232,10 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t va
 // Entry j starts its tile's range if the entry before it has another tile,
 // and ends it if the entry after it has another tile.
 __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict__ inst_tile,
-                                                     int64_t m, uint2* __restrict__ ranges) {
+                                                     int64_t m, uint2* __restrict__ ranges,
+                                                     const Counters* __restrict__ dn) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (dn) m = min(m, live_count(dn));
   if (j >= m) return;
   const uint32_t tile = inst_tile[j];
   if (j == 0 || inst_tile[j - 1] != tile) ranges[tile].x = (uint32_t)j;
@@ -275,10 +277,11 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {
                      p, n, value);
 }
 
-void launch_ranges(const uint32_t* inst_tile, int64_t m, uint2* ranges, hipStream_t s) {
+void launch_ranges(const uint32_t* inst_tile, int64_t m, uint2* ranges, hipStream_t s,
+                   const Counters* dn) {
   if (m <= 0) return;
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
-                     inst_tile, m, ranges);
+                     inst_tile, m, ranges, dn);
 }
 
 }  // namespace nxs

@@ -2,11 +2,14 @@
 
 Every step of the render runs in the HIP library; this module checks that
 tensors are on the GPU, float32 and contiguous, fills the C structs of
-include/nxs.h and passes device pointers and the current HIP stream.
-Loading fails loudly when libnxs.so has not been built.
+include/nxs.h and passes device pointers and the current HIP stream.  The
+library's device workspace comes from PyTorch's caching allocator through the
+allocator callbacks of nxs_create (TorchAllocator).  Loading fails loudly
+when libnxs.so has not been built.
 """
 import ctypes
 import math
+import weakref
 from ctypes import POINTER, byref, c_float, c_int32, c_int64, c_uint32, c_uint64, c_void_p
 from pathlib import Path
 
@@ -20,6 +23,7 @@ MODEL_IDS = {"exponential": 0, "linear": 1, "sublinear": 2, "superlinear": 3,
 STATUS = {0: "NXS_OK", -1: "NXS_EINVAL", -2: "NXS_ENOMEM", -3: "NXS_EHIP",
           -4: "NXS_ECAPACITY", -5: "NXS_EUNSUPPORTED"}
 SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_render_backward",
+           "nxs_state_release", "nxs_forward_status",
            "nxs_autotune", "nxs_set_workspace_limit", "nxs_workspace_bytes",
            "nxs_release_workspace",
            "nxs_server_create", "nxs_server_destroy", "nxs_server_add_scene",
@@ -54,13 +58,20 @@ class Camera(ctypes.Structure):
 class RenderOpts(ctypes.Structure):
     _fields_ = [("model", c_int32), ("background", c_float * 3), ("alpha_min", c_float),
                 ("t_eps", c_float), ("tile_w", c_int32), ("tile_h", c_int32),
-                ("lds_batch", c_int32), ("param", c_float), ("keep_state", c_int32),
+                ("lds_batch", c_int32), ("param", c_float), ("flags", c_int32),
                 ("schedule", c_int32)]
+
+
+FLAG_DEFERRED = 1
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("schedule", c_int32),
-                ("ms", c_float)]
+                ("lds_batch", c_int32), ("ms", c_float)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
 
 
 SCHEDULES = {"tiles": 1, "blocks": 2, "queue": 3, "persistent": 4}
@@ -86,12 +97,15 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} not found: build it with "
                                "`python -m paper_2603_02887_amd.build`")
         L = ctypes.CDLL(str(LIB_PATH))
-        L.nxs_create.argtypes = [POINTER(c_void_p), ctypes.c_int]
+        L.nxs_create.argtypes = [POINTER(c_void_p), ctypes.c_int, ALLOC_FN, FREE_FN, c_void_p]
         L.nxs_destroy.argtypes = [c_void_p]
         L.nxs_render_forward.argtypes = [c_void_p, POINTER(Gaussians), POINTER(Camera), c_int32,
-                                         POINTER(RenderOpts), POINTER(Image), c_void_p]
-        L.nxs_render_backward.argtypes = [c_void_p, c_void_p, c_void_p,
+                                         POINTER(RenderOpts), POINTER(Image),
+                                         POINTER(c_void_p), c_void_p]
+        L.nxs_render_backward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p,
                                           POINTER(GaussiansGrad), c_void_p]
+        L.nxs_state_release.argtypes = [c_void_p, c_void_p, c_void_p]
+        L.nxs_forward_status.argtypes = [c_void_p, POINTER(c_int64)]
         L.nxs_autotune.argtypes = [c_void_p, POINTER(Gaussians), POINTER(Camera), c_int32,
                                    POINTER(RenderOpts), POINTER(Image), ctypes.c_char_p,
                                    c_int32, POINTER(Tuning), c_void_p]
@@ -198,7 +212,7 @@ def _make_image(o):
 
 
 def _make_opts(model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0, t_eps=0.0, tile=(16, 16),
-               lds_batch=0, param=0.0, keep_state=False, schedule=0):
+               lds_batch=0, param=0.0, schedule=0, deferred=False):
     if isinstance(model, str):
         model = MODEL_IDS[model]
     if isinstance(schedule, str):
@@ -211,28 +225,144 @@ def _make_opts(model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0, t_eps=0.0, ti
     opts.tile_w, opts.tile_h = int(tile[0]), int(tile[1])
     opts.lds_batch = int(lds_batch)
     opts.param = float(param)
-    opts.keep_state = int(bool(keep_state))
+    opts.flags = FLAG_DEFERRED if deferred else 0
     opts.schedule = int(schedule)
     return opts
 
 
-class Renderer:
-    """A library context on one GPU; render() enqueues on the current stream."""
+def _raw_stream(stream):
+    return int(stream.cuda_stream) if stream is not None else 0
 
-    def __init__(self, device=0):
+
+class TorchAllocator:
+    """Device memory for a library context from PyTorch's caching allocator
+    (the nxs_alloc_fn / nxs_free_fn callbacks of nxs_create).
+
+    A block is allocated for the stream the library names and freed the
+    way the library's free promises: in stream order on the stream it names.
+    Freed on the stream it was allocated for, it goes straight back to the
+    cache; freed on another stream, it is held until an event recorded on
+    that stream has completed."""
+
+    def __init__(self, device):
+        self.device = device
+        self.blocks = {}        # pointer -> raw stream it was allocated for
+        self.deferred = []      # (event, pointer) freed on another stream
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _stream(self, raw):
+        if raw:
+            return torch.cuda.ExternalStream(raw, device=self.device)
+        return torch.cuda.default_stream(self.device)
+
+    def _reap(self):
+        keep = []
+        for ev, p in self.deferred:
+            if ev.query():
+                torch.cuda.caching_allocator_delete(p)
+            else:
+                keep.append((ev, p))
+        self.deferred = keep
+
+    def _alloc(self, nbytes, stream, user):
+        try:
+            self._reap()
+            raw = int(stream or 0)
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device.index, raw)
+            self.blocks[int(p)] = raw
+            return int(p)
+        except Exception:      # the library reports NXS_ENOMEM
+            return None
+
+    def _free(self, ptr, stream, user):
+        try:
+            raw0 = self.blocks.pop(int(ptr))
+            raw = int(stream or 0)
+            if raw == raw0:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            else:
+                ev = torch.cuda.Event()
+                ev.record(self._stream(raw))
+                self.deferred.append((ev, int(ptr)))
+        except Exception:
+            pass
+
+    def drain(self):
+        """After the context is gone: give back what waits on events."""
+        if self.deferred:
+            torch.cuda.synchronize(self.device)
+            for _, p in self.deferred:
+                torch.cuda.caching_allocator_delete(p)
+            self.deferred = []
+
+    @property
+    def bytes_held(self):
+        return len(self.blocks)
+
+
+class FwdState:
+    """What a forward kept for its backward (an nxs_fwd_state); released when
+    garbage-collected, by release(), or when its Renderer closes."""
+
+    def __init__(self, renderer, handle, shapes):
+        self._r = weakref.ref(renderer)
+        self._h = handle
+        self.shapes = shapes              # [(H, W)] per view
+        renderer._states.add(self)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("this forward state has been released")
+        return self._h
+
+    def release(self, stream=None):
+        r = self._r()
+        if self._h and r is not None and r._ctx:
+            if stream is None:
+                stream = torch.cuda.current_stream(r.device)
+            r._L.nxs_state_release(r._ctx, self._h, c_void_p(_raw_stream(stream)))
+            r._states.discard(self)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Renderer:
+    """A library context on one GPU; render() enqueues on the current stream.
+
+    allocator="torch" (default): the workspace comes from PyTorch's caching
+    allocator; None: from the library's own stream-ordered pool."""
+
+    def __init__(self, device=0, allocator="torch"):
         self._L = lib()
         self._ctx = c_void_p()
-        st = self._L.nxs_create(byref(self._ctx), int(device))
+        self.device = torch.device("cuda", int(device))
+        self._states = weakref.WeakSet()
+        self._alloc = TorchAllocator(self.device) if allocator == "torch" else None
+        if self._alloc is not None:
+            st = self._L.nxs_create(byref(self._ctx), int(device), self._alloc.alloc_cb,
+                                    self._alloc.free_cb, None)
+        else:
+            st = self._L.nxs_create(byref(self._ctx), int(device), ALLOC_FN(), FREE_FN(), None)
         if st != 0:
             raise NxsError(st, "nxs_create failed")
-        self.device = torch.device("cuda", int(device))
-        self.generation = 0      # forwards issued on this context
-        self._last_shapes = []
+        self.last_state = None    # the state of the last render(keep_state=True)
 
     def close(self):
         if self._ctx:
+            self.last_state = None
+            for s in list(self._states):
+                s._h = None       # nxs_destroy frees them
             self._L.nxs_destroy(self._ctx)
             self._ctx = c_void_p()
+            if self._alloc is not None:
+                self._alloc.drain()
 
     def __del__(self):
         try:
@@ -246,33 +376,52 @@ class Renderer:
             raise NxsError(st, msg.decode() if msg else "")
 
     def _marshal(self, g, cams, model, background, alpha_min, t_eps, tile, lds_batch,
-                 outputs, overdraw, param, keep_state, schedule):
+                 outputs, overdraw, param, schedule, deferred):
         gs = _make_gaussians(g)
         V = len(cams)
         carr = (Camera * V)(*[make_camera(c) for c in cams])
         outputs = _make_outputs(self.device, cams, outputs, overdraw)
         imgs = (Image * V)(*[_make_image(o) for o in outputs])
         opts = _make_opts(model, background, alpha_min, t_eps, tile, lds_batch, param,
-                          keep_state, schedule)
+                          schedule, deferred)
         return gs, carr, V, imgs, opts, outputs
 
     def render(self, g, cams, model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0,
                t_eps=0.0, tile=(16, 16), lds_batch=0, outputs=None, overdraw=True,
-               stream=None, param=0.0, keep_state=False, schedule=0):
+               stream=None, param=0.0, keep_state=False, schedule=0, deferred=False):
         """Render the Gaussians `g` (dict of GPU tensors, see scene_to_device) in
         every camera of `cams`.  Returns a list of dicts {rgb [H,W,3], trans [H,W],
-        overdraw [H,W] int32} (or fills `outputs`, a list of such dicts)."""
+        overdraw [H,W] int32} (or fills `outputs`, a list of such dicts).
+        keep_state: keep a FwdState for backward() in self.last_state.
+        deferred: do not wait for the instance count (NXS_FLAG_DEFERRED); check
+        the outcome with status()."""
         gs, carr, V, imgs, opts, outputs = self._marshal(
             g, cams, model, background, alpha_min, t_eps, tile, lds_batch, outputs, overdraw,
-            param, keep_state, schedule)
+            param, schedule, deferred)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
+        h = c_void_p()
         st = self._L.nxs_render_forward(self._ctx, byref(gs), carr, V, byref(opts), imgs,
+                                        byref(h) if keep_state else None,
                                         c_void_p(stream.cuda_stream))
-        self.generation += 1
-        self._last_shapes = [(int(c.height), int(c.width)) for c in cams]
         self._check(st)
+        if keep_state:
+            self.last_state = FwdState(self, h, [(int(c.height), int(c.width)) for c in cams])
         return outputs
+
+    def workspace_bytes(self):
+        """Device workspace the context holds (bytes; states not counted)."""
+        b = ctypes.c_size_t()
+        self._check(self._L.nxs_workspace_bytes(self._ctx, byref(b)))
+        return int(b.value)
+
+    def status(self):
+        """Outcome of the deferred renders since the last call (nxs_forward_status):
+        raises NxsError(NXS_ECAPACITY) if any outgrew the workspace (the context
+        has then grown; render them again); returns 0 otherwise."""
+        need = c_int64()
+        self._check(self._L.nxs_forward_status(self._ctx, byref(need)))
+        return need.value
 
     def autotune(self, g, cams, model=0, cache_path=None, reps=5, outputs=None, stream=None,
                  background=(0.0, 0.0, 0.0), alpha_min=0.0, t_eps=0.0, param=0.0):
@@ -287,23 +436,27 @@ class Renderer:
         path = None if cache_path is None else str(cache_path).encode()
         st = self._L.nxs_autotune(self._ctx, byref(gs), carr, V, byref(opts), imgs, path,
                                   int(reps), byref(res), c_void_p(stream.cuda_stream))
-        self.generation += 1          # a sweep renders, which ends any kept state
         self._check(st)
         name = {v: k for k, v in SCHEDULES.items()}[res.schedule]
-        return {"tile": (res.tile_w, res.tile_h), "schedule": name, "ms": float(res.ms)}
+        return {"tile": (res.tile_w, res.tile_h), "schedule": name,
+                "lds_batch": int(res.lds_batch), "ms": float(res.ms)}
 
-    def backward(self, g, dL_drgb, dL_dtrans=None, stream=None):
+    def backward(self, g, dL_drgb, dL_dtrans=None, stream=None, state=None):
         """Gradients of the Gaussians (dict of tensors shaped like `g`) from the
-        upstream gradients of the last forward, which had keep_state=True:
-        dL_drgb a list of [H,W,3] per view, dL_dtrans None or a list of [H,W]
-        (entries may be None)."""
+        upstream gradients of a forward that kept its state (`state`, default
+        the last render(keep_state=True)): dL_drgb a list of [H,W,3] per view,
+        dL_dtrans None or a list of [H,W] (entries may be None)."""
+        state = self.last_state if state is None else state
+        if state is None:
+            raise ValueError("no forward state: render with keep_state=True first")
+        shapes = state.shapes
         V = len(dL_drgb)
-        if V != len(self._last_shapes):
-            raise ValueError(f"{V} upstream gradients for {len(self._last_shapes)} views")
+        if V != len(shapes):
+            raise ValueError(f"{V} upstream gradients for {len(shapes)} views")
         if dL_dtrans is not None and len(dL_dtrans) != V:
             raise ValueError("dL_dtrans needs one entry per view")
         keep = []
-        for v, (H, W) in enumerate(self._last_shapes):
+        for v, (H, W) in enumerate(shapes):
             t = _f32(dL_drgb[v].contiguous(), "dL_drgb")
             if tuple(t.shape) != (H, W, 3):
                 raise ValueError(f"view {v}: dL_drgb must be [{H},{W},3]")
@@ -331,7 +484,7 @@ class Renderer:
             for t in keep:
                 if t is not None:
                     t.record_stream(stream)
-        st = self._L.nxs_render_backward(self._ctx, rgb_ptrs, tr_ptrs, byref(gg),
+        st = self._L.nxs_render_backward(self._ctx, state.handle, rgb_ptrs, tr_ptrs, byref(gg),
                                          c_void_p(stream.cuda_stream))
         self._check(st)
         return out
@@ -473,23 +626,23 @@ class RenderFunction(torch.autograd.Function):
              "sh": sh.detach().contiguous(),
              "sh_degree": int(round(math.sqrt(sh.shape[1]))) - 1}
         outs = renderer.render(g, cams, keep_state=True, overdraw=False, **opts)
-        ctx.renderer, ctx.g, ctx.gen = renderer, g, renderer.generation
+        # this forward's own state: other forwards may run before its backward
+        ctx.renderer, ctx.g, ctx.state = renderer, g, renderer.last_state
+        renderer.last_state = None
         ctx.shapes = [(o["rgb"].shape, o["trans"].shape) for o in outs]
         return tuple(o["rgb"] for o in outs) + tuple(o["trans"] for o in outs)
 
     @staticmethod
     def backward(ctx, *grads):
         r = ctx.renderer
-        if r.generation != ctx.gen:
-            raise RuntimeError("another forward ran on this Renderer since this one; "
-                               "its backward state is gone")
         V = len(ctx.shapes)
         d_rgb = [gr if gr is not None else torch.zeros(sh[0], device=r.device)
                  for gr, sh in zip(grads[:V], ctx.shapes)]
         d_tr = list(grads[V:])
         if all(t is None for t in d_tr):
             d_tr = None
-        gr = r.backward(ctx.g, d_rgb, d_tr)
+        gr = r.backward(ctx.g, d_rgb, d_tr, state=ctx.state)
+        ctx.state.release()
         return (None, None, None, gr["means"], gr["scales"], gr["quats"], gr["opacities"],
                 gr["sh"])
 

@@ -165,15 +165,30 @@ def test_backward_same_under_every_schedule(R, model):
             assert torch.allclose(v, ref[k], rtol=1e-4, atol=5e-4 * scale), (sched, k)
 
 
-def test_autograd_rejects_stale_state(R):
+def test_autograd_survives_other_forwards(R):
+    """Each differentiable render keeps its own forward state: forwards of
+    other scenes and models on the same context between a render and its
+    backward change nothing."""
     from paper_2603_02887_amd import nxs
     sc, cams = _scene()
     g = nxs.scene_to_device(sc)
-    op = g["opacities"].clone().requires_grad_(True)
-    rgbs, _ = nxs.render(R, cams, g["means"], g["scales"], g["quats"], op, g["sh"], model=1)
-    R.render(g, cams, model=1)               # another forward on the same context
-    with pytest.raises(RuntimeError):
-        rgbs[0].sum().backward()
+    other = nxs.scene_to_device(synth.random_scene(9, 300, sh_degree=1))
+
+    def grad(interleave):
+        op = g["opacities"].clone().requires_grad_(True)
+        rgbs, trs = nxs.render(R, cams, g["means"], g["scales"], g["quats"], op, g["sh"],
+                               model=1)
+        if interleave:
+            R.render(other, cams, model=0)
+            R.render(other, cams, model=3, keep_state=True)
+        (sum(x.sum() for x in rgbs) + 0.5 * sum(t.sum() for t in trs)).backward()
+        return op.grad
+
+    a, b = grad(False), grad(True)
+    torch.cuda.synchronize()
+    scale = float(a.abs().max())
+    assert scale > 0
+    assert torch.allclose(a, b, rtol=1e-5, atol=1e-5 * scale)
 
 
 def test_backward_errors(R):
@@ -181,15 +196,23 @@ def test_backward_errors(R):
     sc, cams = _scene()
     g = nxs.scene_to_device(sc)
     d = [torch.zeros(c.height, c.width, 3, device="cuda") for c in cams]
+    R.last_state = None
     R.render(g, cams, model=0)               # no keep_state
-    with pytest.raises(nxs.NxsError) as e:
+    with pytest.raises(ValueError):
         R.backward(g, d)
-    assert e.value.status == -1
+    # the C ABI: a null or released state
+    L = nxs.lib()
+    assert L.nxs_render_backward(R._ctx, None, None, None, None, None) == -1
+    R.render(g, cams, model=0, keep_state=True)
+    st = R.last_state
+    st.release()
+    with pytest.raises(RuntimeError):
+        R.backward(g, d, state=st)
+    # no backward for models 5..7: their forward refuses to keep state
     for model, param in ((5, 0.5), (6, 0.5), (7, 2.0)):
-        R.render(g, cams, model=model, param=param, keep_state=True)
         with pytest.raises(nxs.NxsError) as e:
-            R.backward(g, d)
-        assert "supports models" in str(e.value)
+            R.render(g, cams, model=model, param=param, keep_state=True)
+        assert e.value.status == -5
 
 
 def test_backward_culled_and_empty(R):

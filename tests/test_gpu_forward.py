@@ -50,7 +50,7 @@ def test_tiny_scene_full_image(R, model):
     print("tiny", model, st)
 
 
-@pytest.mark.parametrize("tile,batch", [((8, 8), 128), ((32, 8), 512), ((16, 16), 128)])
+@pytest.mark.parametrize("tile,batch", [((8, 8), 128), ((32, 8), 256), ((16, 16), 64)])
 def test_tile_shapes_and_batches(R, tile, batch):
     sc, cams = synth.tiny_scene(seed=5, n=3000)
     cam = synth.look_at_camera((0.2, 0.1, -2.6), width=150, height=97)  # ragged tiles

@@ -117,7 +117,7 @@ def test_submit_errors(R):
     with pytest.raises(nxs.NxsError):
         S.submit(sid + 5, cam, 1)
     with pytest.raises(nxs.NxsError):
-        S.submit(sid, cam, 2, keep_state=True)
+        S.submit(sid, cam, 2, deferred=True)          # served renders take no flags
     S.submit(sid, cam, 3, model=9)                   # invalid model: fails alone
     S.submit(sid, cam, 4, model=1)
     got = {tag: st for tag, st, _ in S.drain()}

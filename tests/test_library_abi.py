@@ -49,5 +49,20 @@ def test_null_context_is_rejected_without_gpu(lib):
     lib.nxs_last_error.argtypes = [ctypes.c_void_p]
     assert lib.nxs_last_error(None) == b""
     lib.nxs_create.restype = ctypes.c_int
-    lib.nxs_create.argtypes = [ctypes.c_void_p, ctypes.c_int]
-    assert lib.nxs_create(None, 0) == -1
+    lib.nxs_create.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p]
+    assert lib.nxs_create(None, 0, None, None, None) == -1
+    # an allocator needs both callbacks
+    out = ctypes.c_void_p()
+    assert lib.nxs_create(ctypes.byref(out), 0, ctypes.c_void_p(1), None, None) == -1
+    assert not out.value
+
+
+def test_state_and_status_entry_points_reject_null_context(lib):
+    for name, nargs in (("nxs_render_backward", 6), ("nxs_state_release", 3),
+                        ("nxs_forward_status", 2), ("nxs_autotune", 10),
+                        ("nxs_inspect_counts", 3), ("nxs_release_workspace", 1)):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p] * nargs
+        assert f(*([None] * nargs)) == -1, name

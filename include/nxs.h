@@ -227,6 +227,28 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
                               const nxs_render_opts* opts, const nxs_image* out,
                               nxs_fwd_state** state, void* stream);
 
+/* nxs_render_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture set-up, tight serving loops, harnesses that forbid
+ * hipMalloc): the same render, bitwise, with every buffer of the workspace
+ * carved from a fixed scratch array of 64 MiB per device that the library
+ * holds until the process ends; nothing is allocated, on the device or in
+ * pinned host memory, and no state is kept.
+ *   Arguments as for nxs_render_forward; opts.flags must be 0.
+ *   Size limit: the render's workspace must fit the 64 MiB -- about 100
+ *   bytes per Gaussian per view, 16 per tile instance, 16 per tile, plus the
+ *   sort's digit counts (e.g. 150,000 Gaussians at 1920x1080 with about a
+ *   million instances).  A render beyond it fails with NXS_ECAPACITY and a
+ *   message naming the limit, before its composite writes any output.
+ *   The call waits on the host for the instance count, like a waiting
+ *   nxs_render_forward.  Every call on one GPU shares that GPU's scratch:
+ *   calls that overlap on the device (another stream, another thread or
+ *   context) race and give undefined results; calls on one stream are
+ *   ordered.  Work is ordered after the context's earlier calls. */
+nxs_status nxs_render_forward_noalloc(nxs_context* ctx, const nxs_gaussians* g,
+                                      const nxs_camera* cams, int32_t n_views,
+                                      const nxs_render_opts* opts, const nxs_image* out,
+                                      void* stream);
+
 /* Outcome of the deferred forwards (NXS_FLAG_DEFERRED) on the context since
  * the last call: waits for the context's last render, then returns NXS_OK,
  * or NXS_ECAPACITY if any of them outgrew the workspace (their outputs are

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -16,7 +17,17 @@
 
 using namespace nxs;
 
+// Workspace of nxs_render_forward_noalloc: one array per device, kept until
+// the process ends.  Host code never names it after set-up: it uses the
+// device address hipGetSymbolAddress returned on that device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char* g_scratch[kMaxDevices] = {};   // device address of `scratch`, per device
 
 struct DevBuf {
   void* p = nullptr;
@@ -56,6 +67,7 @@ struct nxs_context {
   int device = 0;
   std::string err;
   Allocator al;
+  char* scratch = nullptr;   // this device's scratch (nxs_render_forward_noalloc)
   bool noalloc = false;   // the no-alloc entry point: no events, no pinned memory
   // workspace
   DevBuf views, counters, partials, status;
@@ -708,6 +720,19 @@ nxs_status nxs_create(nxs_context** out, int device, nxs_alloc_fn alloc, nxs_fre
     delete ctx;
     return NXS_EHIP;
   }
+  // the scratch of the allocation-free forward: its address on this device,
+  // looked up once per device with the device current
+  if (ok) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (device < kMaxDevices && !g_scratch[device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+        g_scratch[device] = static_cast<char*>(p);
+      else
+        (void)hipGetLastError();
+    }
+    ctx->scratch = device < kMaxDevices ? g_scratch[device] : nullptr;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
     ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -759,6 +784,43 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
   if (state && opts->model > NXS_QUADRATIC)
     return fail(ctx, NXS_EUNSUPPORTED, "backward state: models 0..4, not %d", opts->model);
   return forward(ctx, g, cams, n_views, opts, out, c, state, (hipStream_t)stream);
+}
+
+nxs_status nxs_render_forward_noalloc(nxs_context* ctx, const nxs_gaussians* g,
+                                      const nxs_camera* cams, int32_t n_views,
+                                      const nxs_render_opts* opts, const nxs_image* out,
+                                      void* stream) {
+  if (!ctx) return NXS_EINVAL;
+  ctx->err.clear();
+  Checked c;
+  nxs_status st = check_args(ctx, g, cams, n_views, opts, out, &c);
+  if (st != NXS_OK) return st;
+  if (opts->flags) return fail(ctx, NXS_EINVAL, "the no-alloc forward takes no flags");
+  if (!ctx->scratch)
+    return fail(ctx, NXS_EHIP, "no scratch address for device %d", ctx->device);
+  // a context of this call only: its buffers are carved from the scratch,
+  // its host tables are ordinary memory, and it records no events
+  nxs_context tmp;
+  tmp.device = ctx->device;
+  tmp.noalloc = true;
+  tmp.n_cu = ctx->n_cu;
+  tmp.al.region = ctx->scratch;
+  tmp.al.region_size = kScratchBytes;
+  Counters counters{};
+  std::vector<ViewDev> views(n_views);
+  tmp.host_counters = &counters;
+  tmp.host_views[0] = views.data();
+  tmp.host_views_cap = n_views;
+  hipStream_t s = (hipStream_t)stream;
+  // ordered after the context's own calls (the scratch is not theirs, but
+  // the caller's inputs and outputs may be)
+  if (ctx->has_done) HIP_TRY(hipStreamWaitEvent(s, ctx->done, 0));
+  st = forward(&tmp, g, cams, n_views, opts, out, c, nullptr, s);
+  if (st != NXS_OK) {
+    ctx->err = tmp.err;
+    return st;
+  }
+  return NXS_OK;
 }
 
 nxs_status nxs_forward_status(nxs_context* ctx, int64_t* needed) {

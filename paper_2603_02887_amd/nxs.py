@@ -23,7 +23,7 @@ MODEL_IDS = {"exponential": 0, "linear": 1, "sublinear": 2, "superlinear": 3,
 STATUS = {0: "NXS_OK", -1: "NXS_EINVAL", -2: "NXS_ENOMEM", -3: "NXS_EHIP",
           -4: "NXS_ECAPACITY", -5: "NXS_EUNSUPPORTED"}
 SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_render_backward",
-           "nxs_state_release", "nxs_forward_status",
+           "nxs_state_release", "nxs_forward_status", "nxs_render_forward_noalloc",
            "nxs_autotune", "nxs_set_workspace_limit", "nxs_workspace_bytes",
            "nxs_release_workspace",
            "nxs_server_create", "nxs_server_destroy", "nxs_server_add_scene",
@@ -106,6 +106,9 @@ def lib():
                                           POINTER(GaussiansGrad), c_void_p]
         L.nxs_state_release.argtypes = [c_void_p, c_void_p, c_void_p]
         L.nxs_forward_status.argtypes = [c_void_p, POINTER(c_int64)]
+        L.nxs_render_forward_noalloc.argtypes = [c_void_p, POINTER(Gaussians), POINTER(Camera),
+                                                 c_int32, POINTER(RenderOpts), POINTER(Image),
+                                                 c_void_p]
         L.nxs_autotune.argtypes = [c_void_p, POINTER(Gaussians), POINTER(Camera), c_int32,
                                    POINTER(RenderOpts), POINTER(Image), ctypes.c_char_p,
                                    c_int32, POINTER(Tuning), c_void_p]
@@ -409,6 +412,22 @@ class Renderer:
             self.last_state = FwdState(self, h, [(int(c.height), int(c.width)) for c in cams])
         return outputs
 
+    def render_noalloc(self, g, cams, outputs, model=0, background=(0.0, 0.0, 0.0),
+                       alpha_min=0.0, t_eps=0.0, tile=(16, 16), lds_batch=0, param=0.0,
+                       schedule=0, stream=None):
+        """The same render through nxs_render_forward_noalloc: the library
+        allocates nothing (its workspace is a fixed 64 MiB scratch per
+        device); `outputs` must be given (a list of dicts as render returns)."""
+        gs, carr, V, imgs, opts, outputs = self._marshal(
+            g, cams, model, background, alpha_min, t_eps, tile, lds_batch, outputs, True,
+            param, schedule, False)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._check(self._L.nxs_render_forward_noalloc(self._ctx, byref(gs), carr, V,
+                                                       byref(opts), imgs,
+                                                       c_void_p(stream.cuda_stream)))
+        return outputs
+
     def workspace_bytes(self):
         """Device workspace the context holds (bytes; states not counted)."""
         b = ctypes.c_size_t()
@@ -607,6 +626,22 @@ class Server:
         while self.pending or self.in_flight:
             done += self.step(wait=True)
         return done
+
+    def render_noalloc(self, g, cams, outputs, model=0, background=(0.0, 0.0, 0.0),
+                       alpha_min=0.0, t_eps=0.0, tile=(16, 16), lds_batch=0, param=0.0,
+                       schedule=0, stream=None):
+        """The same render through nxs_render_forward_noalloc: the library
+        allocates nothing (its workspace is a fixed 64 MiB scratch per
+        device); `outputs` must be given (a list of dicts as render returns)."""
+        gs, carr, V, imgs, opts, outputs = self._marshal(
+            g, cams, model, background, alpha_min, t_eps, tile, lds_batch, outputs, True,
+            param, schedule, False)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._check(self._L.nxs_render_forward_noalloc(self._ctx, byref(gs), carr, V,
+                                                       byref(opts), imgs,
+                                                       c_void_p(stream.cuda_stream)))
+        return outputs
 
     def workspace_bytes(self):
         b = ctypes.c_size_t()

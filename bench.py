@@ -4,28 +4,32 @@
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
 Workload: 1,000,000 Gaussians drawn from 64 anisotropic clusters, SH degree 3,
-one 1920x1080 pinhole camera, 16x16 tiles.  One step renders that frame once
-with each transmittance model (exponential, linear, quadratic sublinear,
-quadratic superlinear): the whole path (projection, depth sort, binning, tile
-sort, tile ranges, composite with its gather) runs for every render.  The
-scene is uploaded to HBM before the timed region.
+one 1920x1080 pinhole camera.  One step renders that frame once with each
+transmittance model (exponential, linear, quadratic sublinear, quadratic
+superlinear): the whole path (projection, depth sort, binning, tile sort,
+tile ranges, composite with its gather) runs for every render, with the
+tile shape, composite schedule and LDS batch the library's autotuner picks
+for each model.  The scene is uploaded to HBM before the timed region.
 
-The timed steps enqueue their renders back to back, alternating between two
-library contexts, each on a stream of its own (a caller that pipelines
-renders): one render's short, latency-bound sort kernels then overlap the
-other's projection or composite.  `value` is the frame's pixels over that
-time.  Per-model throughput is also given for one context on one stream.
-Latency is measured separately, one render at a time, waiting for each:
-p50/p99 per model, with per-stage GPU times from hipEvents the library
-records on the render stream (the composite's time there, alone on the GPU,
-is the one the roofline uses).
+The timed steps enqueue their renders back to back without waiting
+(deferred renders, whose instance count is checked on the device),
+alternating between two library contexts, each on a stream of its own: one
+render's short, latency-bound sort kernels then overlap the other's
+projection or composite.  `value` is the frame's pixels over that time.
+The same steps on one context and one stream, deferred and waiting, are
+reported beside it, as is per-model throughput.  Latency is measured
+separately, one render at a time, waiting for each: p50/p99 per model, with
+per-stage GPU times from hipEvents the library records on the render stream
+(the composite's time there, alone on the GPU, is the one the roofline uses).
 
 Prints one JSON line: aggregate Mpix/s over all renders, per-model Mpix/s,
 splats blended per second (sum of per-pixel overdraw / time), mean overdraw,
 p50/p99 render latency, per-stage GPU times, the roofline of the dominant
-kernel, the CPU oracle timed on a bounded pixel sample of the same frame, and
-the batched (16 views), differentiation (8 views, forward + backward) and
-serving (--workload serving) workloads.
+kernel, the CPU oracle timed on a bounded pixel sample of the same frame with
+a process pool over the host's cores, and the batched (16 views),
+differentiation (8 views, forward + backward) and serving (four resident
+scenes, continuous batching under Poisson arrivals, against one plain
+launch per request) workloads.
 """
 import argparse
 import json
@@ -42,15 +46,19 @@ import numpy as np  # noqa: E402
 MODELS = ("exponential", "linear", "sublinear", "superlinear")
 METRIC = "Mpix/s + splats blended/s per transmittance model; p50/p99 render latency"
 
-# FP32 VALU work of one composited (pixel, splat) pair, counting an FMA as 2
-# flops and the exp2 as 1: offset 2, exponent 8, exp2 1, accumulate 6, plus
-# the operator (exponential 3, linear 1, quadratic 5).
+# FP32 arithmetic of one composited (pixel, splat) pair, counting an FMA as 2
+# flops and the exp2 as 1 (the convention of the FLOP/s peak below): offset
+# 2, exponent 8, exp2 1, accumulate 6, plus the operator (exponential 3,
+# linear 1, quadratic 5).
 FLOPS_PER_PAIR = {0: 20, 1: 18, 2: 22, 3: 22}
 # MI355X FP32 vector peak: 256 CUs x 128 FP32 lanes x 2 flops (FMA) x 2.4 GHz.
-# (The kernels are built without packed FP32, but the measured VALU issue rate
-# of the composite exceeds one wave64 instruction per 4 cycles per SIMD, so
-# the 16-lane figure of half this would not be a ceiling.)
 FP32_VALU_PEAK_TFLOPS = 157.2864
+# VALU issue slots of one pair (an FMA is one slot, the exp2 four at quarter
+# rate, plus two compares and the overdraw increment): about 24.  Reported
+# against the non-packed issue rate of 256 CUs x 64 lanes x 2.4 GHz as a
+# second view of the same kernel.
+SLOTS_PER_PAIR = 24
+VALU_SLOT_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of each composite kernel on this workload (16x16 tiles),
@@ -83,42 +91,84 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(scene, cam, n_pixels, seed=123):
-    """Time the CPU oracle (single thread) on a random pixel sample of the frame,
-    per model, and extrapolate to the full frame: the model-independent set-up
-    (projection, key replay) once, then per model a 1-pixel render (its
-    pruning lists) and an n-pixel render; per-pixel time = their difference
-    / (n - 1)."""
+# CPU oracle baseline: worker processes (started fresh; they import numpy and
+# the oracle only) each rebuild the seeded frame and project it once.
+_CPU = {}
+
+
+def _cpu_init():
     from threadpoolctl import threadpool_limits
+    import synth
     from oracle import keys as okeys
     from oracle import project as oproject
+    _CPU["threads"] = threadpool_limits(1)     # one thread per process
+    scene, cams = synth.scene_scale()
+    cam = cams[0]
+    t0 = time.perf_counter()
+    proj = oproject.project(scene, cam)
+    geom = okeys.geometry(scene, cam)
+    _CPU.update(scene=scene, cam=cam, proj=proj, geom=geom,
+                setup_s=time.perf_counter() - t0)
+
+
+def _cpu_setup_time(_):
+    return _CPU["setup_s"]
+
+
+def _cpu_chunk(job):
+    """Render one chunk of pixels with one model; returns (time of a 1-pixel
+    render, i.e. the per-model pruning lists; time of the chunk; pixels)."""
     from oracle import render as orender
+    model, pix = job
+    sc, cam, proj, geom = _CPU["scene"], _CPU["cam"], _CPU["proj"], _CPU["geom"]
+    t0 = time.perf_counter()
+    orender.render(sc, cam, model, pixels=pix[:1], proj=proj, geom=geom)
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orender.render(sc, cam, model, pixels=pix, proj=proj, geom=geom)
+    return t1, time.perf_counter() - t0, len(pix)
+
+
+def cpu_baseline(width, height, n_pixels, seed=123):
+    """Time the CPU oracle on a random pixel sample of the frame, per model, on
+    a pool of one process per host core (at most 16), and extrapolate to the
+    full frame: set-up (projection and key replay of all Gaussians) + per-model
+    pruning lists + per-pixel time x W*H / cores."""
+    import multiprocessing as mp
+    import platform
+    from concurrent.futures import ProcessPoolExecutor
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    cpu_model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     rng = np.random.default_rng(seed)
-    flat = rng.choice(cam.width * cam.height, n_pixels, replace=False)
-    pix = np.stack([flat % cam.width, flat // cam.width], 1)
-    frame_s = []
+    flat = rng.choice(width * height, n_pixels, replace=False)
+    pix = np.stack([flat % width, flat // width], 1)
+    chunks = np.array_split(pix, cores)
     t_all = time.perf_counter()
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        proj = oproject.project(scene, cam)
-        geom = okeys.geometry(scene, cam)
-        t_common = time.perf_counter() - t0
+    frame_s = []
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn"),
+                             initializer=_cpu_init) as pool:
+        setup = min(pool.map(_cpu_setup_time, range(cores)))
         for m in range(4):
-            t0 = time.perf_counter()
-            orender.render(scene, cam, m, pixels=pix[:1], proj=proj, geom=geom)
-            t1 = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            orender.render(scene, cam, m, pixels=pix, proj=proj, geom=geom)
-            tn = time.perf_counter() - t0
-            per_px = max(tn - t1, 0.0) / (n_pixels - 1)
-            frame_s.append(t_common + t1 + per_px * cam.width * cam.height)
+            res = list(pool.map(_cpu_chunk, [(m, c) for c in chunks]))
+            t_lists = max(r[0] for r in res)
+            per_px = float(np.median([max(r[1] - r[0], 0.0) / max(r[2] - 1, 1) for r in res]))
+            frame_s.append(setup + t_lists + per_px * width * height / cores)
     spent = time.perf_counter() - t_all
-    mpix = 4 * cam.width * cam.height / sum(frame_s) / 1e6
-    return {"value": mpix, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{n_pixels} random pixels of the 1920x1080 frame per model "
-                       f"(4 models), one thread; full-frame time = set-up (projection "
-                       f"and key replay of all 1M Gaussians, once) + per-model pruning "
-                       f"lists + per-pixel time x W*H; {spent:.1f} s of CPU"),
+    mpix = 4 * width * height / sum(frame_s) / 1e6
+    return {"value": mpix, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model,
+            "sample": (f"{n_pixels} random pixels of the {width}x{height} frame per model "
+                       f"(4 models), split over {cores} processes; full-frame time = set-up "
+                       f"(FP64 projection and key replay of all 1M Gaussians) + per-model "
+                       f"pruning lists + per-pixel time x W*H / {cores}; {spent:.1f} s wall"),
             "frame_seconds": {MODELS[m]: frame_s[m] for m in range(4)}}
 
 
@@ -148,17 +198,18 @@ def batched_views(R, torch, nxs, synth, steps, models=(0, 1, 2, 3)):
     res = {}
     for m in models:
         tune = R.autotune(g, cams, model=m, outputs=outs, reps=3)
-        t_tuned = timed(lambda: R.render(g, cams, model=m, tile=tune["tile"],
-                                         schedule=tune["schedule"], outputs=outs))
+        kw = {"tile": tune["tile"], "schedule": tune["schedule"],
+              "lds_batch": tune["lds_batch"]}
+        t_tuned = timed(lambda: R.render(g, cams, model=m, outputs=outs, **kw))
         t_default = timed(lambda: R.render(g, cams, model=m, outputs=outs))
-        t_per_view = timed(lambda: [R.render(g, [c], model=m, tile=tune["tile"],
-                                             schedule=tune["schedule"], outputs=[o])
+        t_per_view = timed(lambda: [R.render(g, [c], model=m, outputs=[o], **kw)
                                     for c, o in zip(cams, outs)])
         n_inst, _ = R.counts()
         res[MODELS[m]] = {"batched_ms": t_tuned, "batched_default_ms": t_default,
                           "per_view_ms": t_per_view, "mpix_per_s": pix / t_tuned / 1e3,
                           "tuned": {"tile": "%dx%d" % tune["tile"],
-                                    "schedule": tune["schedule"]},
+                                    "schedule": tune["schedule"],
+                                    "lds_batch": tune["lds_batch"]},
                           "speedup_vs_per_view": t_per_view / t_tuned}
     return {"workload": ("3,000,000 Gaussians (means from 256 clusters), SH degree 0, "
                          "16 views of uneven size on a radius-15 orbit"),
@@ -174,12 +225,15 @@ def serving(args, torch, nxs, synth):
     elevation U[-30,30] deg, a resolution from SERVE_SIZES and a model, all
     uniformly.  First the saturation rate (a burst of requests all queued at
     once), then Poisson arrivals at fractions of it; latency = arrival ->
-    result ready.  Prints one JSON line."""
+    result ready.  The burst's requests are also rendered one plain launch
+    each (one nxs_render_forward per request, back to back on one context)
+    for comparison.  Returns the serving block of the JSON line."""
     rng = np.random.default_rng(50)
     scenes = synth.serving_scenes()
     S = nxs.Server(0, workspace_budget=args.serve_budget_gib << 30, max_batch_views=16,
                    n_slots=args.serve_slots)
-    ids = [S.add_scene(nxs.scene_to_device(sc)) for sc in scenes]
+    gpu_scenes = [nxs.scene_to_device(sc) for sc in scenes]
+    ids = [S.add_scene(g) for g in gpu_scenes]
     pool = {wh: [] for wh in SERVE_SIZES}
 
     def draw():
@@ -232,8 +286,24 @@ def serving(args, torch, nxs, synth):
     burst = [draw() for _ in range(args.serve_burst)]
     lat_b, wall_b, pix_b = run([0.0] * len(burst), burst)
     rate_sat = len(burst) / wall_b
+    # the same requests, one plain launch each
+    R = nxs.Renderer(0)
+    outs = [out_for(cam) for _, cam, _ in burst[:8]]
+    for (sc, cam, m), o in zip(burst[:8], outs):
+        R.render(gpu_scenes[sc], [cam], model=m, overdraw=False, outputs=[o])
+    torch.cuda.synchronize()
+    for o, (_, cam, _) in zip(outs, burst[:8]):
+        pool[(cam.width, cam.height)].append(o)
+    t0 = time.perf_counter()
+    for sc, cam, m in burst:
+        o = out_for(cam)
+        R.render(gpu_scenes[sc], [cam], model=m, overdraw=False, outputs=[o])
+        pool[(cam.width, cam.height)].append(o)
+    torch.cuda.synchronize()
+    wall_plain = time.perf_counter() - t0
+    R.close()
     loads = []
-    for frac in (0.25, 0.5, 0.8, 1.0):
+    for frac in args.serve_loads:
         lam = frac * rate_sat
         n = args.serve_warmup + args.serve_requests
         arr = np.cumsum(rng.exponential(1.0 / lam, n))
@@ -243,25 +313,24 @@ def serving(args, torch, nxs, synth):
         loads.append({"load": frac, "rate_req_per_s": lam,
                       "achieved_req_per_s": n / wall, "mpix_per_s": pix / wall / 1e6,
                       "p50_ms": percentile(meas, 50) * 1e3, "p99_ms": percentile(meas, 99) * 1e3,
-                      "mean_ms": float(np.mean(meas)) * 1e3})
+                      "mean_ms": float(np.mean(meas)) * 1e3, "requests": n})
         print(f"serving load {frac}: p50 {loads[-1]['p50_ms']:.2f} ms p99 "
               f"{loads[-1]['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
-    line = {"metric": "serving: Mpix/s at saturation; p50/p99 request latency under Poisson load",
-            "value": pix_b / wall_b / 1e6, "unit": "Mpix/s", "n_gpus": 1,
-            "steps": args.serve_requests, "warmup": args.serve_warmup,
-            "ms_per_step": wall_b / len(burst) * 1e3, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": ("serving: resident scenes of 200k/500k/1M/3M Gaussians, "
-                                    "requests uniform over scene, pose, resolution "
-                                    "(512x512, 1280x720, 1920x1080) and the four models"),
-                       "workspace_budget_gib": args.serve_budget_gib, "max_batch_views": 16,
-                       "slots": args.serve_slots},
+    S.close()
+    return {"workload": ("resident scenes of 200k/500k/1M/3M Gaussians; requests uniform "
+                         "over scene, pose (radius 3-6), resolution (512x512, 1280x720, "
+                         "1920x1080) and the four models"),
+            "slots": args.serve_slots, "workspace_budget_gib": args.serve_budget_gib,
+            "max_batch_views": 16,
             "saturation": {"requests": len(burst), "req_per_s": rate_sat,
+                           "mpix_per_s": pix_b / wall_b / 1e6, "wall_s": wall_b,
                            "p50_ms": percentile(lat_b, 50) * 1e3,
                            "p99_ms": percentile(lat_b, 99) * 1e3},
+            "plain_launches": {"requests": len(burst), "wall_s": wall_plain,
+                               "req_per_s": len(burst) / wall_plain,
+                               "mpix_per_s": pix_b / wall_plain / 1e6},
+            "served_vs_plain": wall_plain / wall_b,
             "poisson": loads}
-    S.close()
-    print(json.dumps(line), flush=True)
 
 
 def differentiation(R, torch, nxs, synth, steps, models=(0, 1, 2, 3)):
@@ -320,9 +389,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--lds-batch", type=int, default=256)
-    ap.add_argument("--cpu-pixels", type=int, default=65536)
+    ap.add_argument("--tile", default="auto",
+                    help="auto: the autotuned tile shape, schedule and LDS batch per model; "
+                         "or WxH with the default schedule and batch")
+    ap.add_argument("--cpu-pixels", type=int, default=262144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 16-view batched workload")
@@ -330,12 +400,12 @@ def main():
     ap.add_argument("--no-diff", action="store_true",
                     help="skip the 8-view forward + backward workload")
     ap.add_argument("--diff-steps", type=int, default=5)
-    ap.add_argument("--workload", choices=("scene", "serving"), default="scene",
-                    help="scene: the 1M-Gaussian 1080p forward (default); serving: the "
-                         "continuous-batching server under Poisson load")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the continuous-batching server under Poisson load")
+    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--serve-burst", type=int, default=400)
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 1.0])
     ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -357,10 +427,6 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    if args.workload == "serving":
-        serving(args, torch, nxs, synth)
-        return
-    tw, th = (int(x) for x in args.tile.split("x"))
     if args.copy_calibration:
         # an elementwise kernel that reads 256 MiB and writes 256 MiB
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -375,41 +441,70 @@ def main():
     dev = torch.device("cuda", 0)
     g = nxs.scene_to_device(scene, dev)
     R = nxs.Renderer(0)
-    outs = {m: R.render(g, [cam], model=m, tile=(tw, th), lds_batch=args.lds_batch)
-            for m in range(4)}
+    R2 = nxs.Renderer(0)
+    outs = {m: R.render(g, [cam], model=m) for m in range(4)}
+    torch.cuda.synchronize()
+    # the render configuration per model
+    if args.tile == "auto":
+        cfg = {}
+        for m in range(4):
+            t = R.autotune(g, [cam], model=m, outputs=outs[m], reps=5)
+            cfg[m] = {"tile": t["tile"], "schedule": t["schedule"], "lds_batch": t["lds_batch"]}
+    else:
+        tw, th = (int(x) for x in args.tile.split("x"))
+        cfg = {m: {"tile": (tw, th), "schedule": "queue", "lds_batch": 64} for m in range(4)}
+    for m in range(4):
+        R.render(g, [cam], model=m, outputs=outs[m], **cfg[m])
+        R2.render(g, [cam], model=m, outputs=outs[m], **cfg[m])
     torch.cuda.synchronize()
     od_sum = {m: int(outs[m][0]["overdraw"].sum().item()) for m in range(4)}
     n_inst, _ = R.counts()
 
-    def render(m):
-        R.render(g, [cam], model=m, tile=(tw, th), lds_batch=args.lds_batch, outputs=outs[m])
+    def render(m, ctx=R, deferred=True):
+        ctx.render(g, [cam], model=m, outputs=outs[m], deferred=deferred, **cfg[m])
 
     # Throughput (the timed steps): each step enqueues one render per model back
-    # to back, as a pipelined caller would, alternating between two contexts on
-    # two streams (each stream orders its own renders; each model writes its
-    # own outputs)
-    ctxs = [R, nxs.Renderer(0)]
+    # to back, as a pipelined caller would (each model writes its own outputs)
     streams = [torch.cuda.Stream(dev), torch.cuda.Stream(dev)]
 
-    def step():
+    def step_two():          # alternating between two contexts on two streams
         for m in range(4):
             with torch.cuda.stream(streams[m % 2]):
-                ctxs[m % 2].render(g, [cam], model=m, tile=(tw, th),
-                                   lds_batch=args.lds_batch, outputs=outs[m])
+                render(m, (R, R2)[m % 2])
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    ctxs[1].close()
-    for m in range(4):
-        render(m)
-    torch.cuda.synchronize()
-    # per model, the same back-to-back throughput
+    def step_one():          # one context, one stream, deferred
+        for m in range(4):
+            render(m)
+
+    def step_wait():         # one context, one stream, each render waits for its count
+        for m in range(4):
+            render(m, deferred=False)
+
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        for attempt in range(3):
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            try:                       # every deferred render fitted its context
+                R.status()
+                R2.status()
+                return dt
+            except nxs.NxsError:       # (the contexts have grown: time it again)
+                continue
+        raise RuntimeError("deferred renders kept outgrowing their contexts")
+
+    modes = {"two_contexts_deferred": timed(step_two),
+             "one_context_deferred": timed(step_one),
+             "one_context_waiting": timed(step_wait)}
+    best_mode = min(modes, key=modes.get)
+    total = modes[best_mode]
+    R2.close()
+    # per model, the same back-to-back throughput (one context, deferred)
     thr = {}
     for m in range(4):
         torch.cuda.synchronize()
@@ -418,6 +513,7 @@ def main():
             render(m)
         torch.cuda.synchronize()
         thr[m] = (time.perf_counter() - t0) / args.steps
+    R.status()
     # Latency (each render waited for) and per-stage GPU times (hipEvents on the
     # render stream), outside the timed steps
     R.set_timing(True)
@@ -426,7 +522,7 @@ def main():
     for _ in range(args.steps):
         for m in range(4):
             t0 = time.perf_counter()
-            render(m)
+            render(m, deferred=False)
             torch.cuda.synchronize()
             lat[m].append(time.perf_counter() - t0)
             stages[m].append(R.stage_times())
@@ -446,19 +542,28 @@ def main():
             "p99_ms": percentile(lat[m], 99) * 1e3,
             "stages_ms": st,
             "gpu_ms": sum(st.values()),
+            "config": {"tile": "%dx%d" % cfg[m]["tile"], "schedule": cfg[m]["schedule"],
+                       "lds_batch": cfg[m]["lds_batch"]},
         }
-    # dominant kernel: the composite of the exponential model (largest stage)
+    # dominant kernel: the largest stage of any model
     all_stage = {(m, k): stage_mean[m][k] for m in range(4) for k in R.STAGES}
     (dm, dk), dms = max(all_stage.items(), key=lambda kv: kv[1])
     if dk == "composite":
         flops = od_sum[dm] * FLOPS_PER_PAIR[dm]
         achieved = flops / (dms * 1e-3) / 1e12
+        slots = od_sum[dm] * SLOTS_PER_PAIR / (dms * 1e-3) / 1e12
+        tile = "%dx%d" % cfg[dm]["tile"]
         roofline = {"bound": "alu", "kernel": f"composite<{MODELS[dm]}>",
                     "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-                    "traffic": measured_traffic(dm, f"{tw}x{th}"),
+                    "traffic": (measured_traffic(dm, tile)
+                                if cfg[dm]["lds_batch"] == 64 else None),
                     "work_per_launch": {"composited_pairs": od_sum[dm],
                                         "flops_per_pair": FLOPS_PER_PAIR[dm]},
+                    "valu_issue_slots": {"per_pair": SLOTS_PER_PAIR, "achieved_T_per_s": slots,
+                                         "peak_T_per_s": VALU_SLOT_PEAK_T,
+                                         "frac": slots / VALU_SLOT_PEAK_T},
+                    "config": per_model[MODELS[dm]]["config"],
                     "avg_launch_ms": dms}
     else:
         roofline = {"bound": "hbm", "kernel": dk, "avg_launch_ms": dms, "achieved": None,
@@ -477,10 +582,15 @@ def main():
     diff = None
     if not args.no_diff:
         diff = differentiation(R, torch, nxs, synth, args.diff_steps)
+    R.close()
+
+    serve = None
+    if not args.no_serving:
+        serve = serving(args, torch, nxs, synth)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene, cam, args.cpu_pixels)
+        cpu = cpu_baseline(W, H, args.cpu_pixels)
 
     line = {
         "metric": METRIC, "value": value, "unit": "Mpix/s", "n_gpus": 1,
@@ -491,17 +601,17 @@ def main():
                                 "anisotropic clusters, SH degree 3, one 1920x1080 camera; "
                                 "one step = one render per transmittance model"),
                    "gaussians": scene.n, "width": W, "height": H,
-                   "tile": f"{tw}x{th}", "lds_batch": args.lds_batch,
-                   "schedule": "queue (longest tile lists first; the library default)",
-                   "in_flight": "renders alternate between two contexts on two streams",
-                   "instances": n_inst, "models": list(MODELS)},
+                   "render_config": {MODELS[m]: per_model[MODELS[m]]["config"]
+                                     for m in range(4)},
+                   "in_flight": best_mode, "instances": n_inst, "models": list(MODELS)},
+        "throughput_modes_mpix_per_s": {k: W * H * renders / v / 1e6 for k, v in modes.items()},
         "per_model": per_model,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
         "differentiation": diff,
+        "serving": serve,
     }
-    R.close()
     print(json.dumps(line), flush=True)
 
 

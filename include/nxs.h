@@ -140,6 +140,9 @@ typedef struct {
   float param;            /* operator parameter of models 4..7 (c, gamma or v) */
   int32_t flags;          /* NXS_FLAG_* */
   int32_t schedule;       /* nxs_schedule of the composite; 0 -> NXS_SCHED_QUEUE */
+  float instance_hint;    /* deferred renders: the tile instances the caller
+                             expects (0 -> the context's last count); sizes the
+                             tile sort's launches, never the result */
 } nxs_render_opts;
 
 /* opts.flags

@@ -80,7 +80,12 @@ struct nxs_context {
   size_t ws_limit = 0;   // 0: no limit on the workspace
   size_t ws_total = 0;   // bytes currently allocated for the workspace
   std::map<std::string, nxs_tuning> tuned;   // autotuner results of this process
-  Counters* host_counters = nullptr;  // pinned (no-alloc: pageable)
+  Counters* host_counters = nullptr;  // pinned, written by the fold kernel (no-alloc: pageable)
+  // pinned copy of the deferred-render status, written by each deferred
+  // render's projection (complete once `done` has fired)
+  DeferredStatus* host_status = nullptr;
+  bool last_deferred = false;
+  bool last_failed = false;   // the last render was deferred and failed
   // view tables, pinned: a ring, so that a call fills one while the copies
   // of up to kViewRing - 1 earlier calls may still be pending (no-alloc: one
   // pageable table)
@@ -109,6 +114,9 @@ struct nxs_context {
   uint32_t* last_inst_tile = nullptr;
   uint32_t* last_inst_val = nullptr;
   const nxs_fwd_state* last_state = nullptr;   // holds last_inst_val, if any
+  // instances of the context's last known render: a deferred render's tile
+  // sort and ranges are launched for about this many (and loop beyond it)
+  uint64_t m_hint = 0;
 };
 
 namespace {
@@ -394,12 +402,18 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
   ctx->last_inst_tile = ctx->last_inst_val = nullptr;
   ctx->last_state = nullptr;
   ctx->last_m = 0;
+  ctx->last_deferred = false;
+  ctx->last_failed = false;
 
   // ---- view table -----------------------------------------------------------
-  // (a pinned table of the ring whose last copy has completed; the copy is
-  // asynchronous, so the table is not reused before its event has fired)
+  // Up to kArgViews views reach the projection as a kernel argument, which
+  // writes the device table.  More views are copied from a pinned table of
+  // the ring whose last copy has completed (the copy is asynchronous, so a
+  // table is not reused before its event has fired).
+  const bool by_arg = g->n > 0 && n_views <= kArgViews;
+  std::vector<ViewDev> arg_views(by_arg ? n_views : 0);
   int ring = 0;
-  if (!ctx->noalloc) {
+  if (!ctx->noalloc && !by_arg) {
     if (ctx->host_views_cap < n_views) {
       for (int k = 0; k < nxs_context::kViewRing; ++k) {
         if (ctx->views_pending[k]) HIP_TRY(hipEventSynchronize(ctx->views_copied[k]));
@@ -420,7 +434,7 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
       ctx->views_pending[ring] = false;
     }
   }
-  ViewDev* host_views = ctx->host_views[ring];
+  ViewDev* host_views = by_arg ? arg_views.data() : ctx->host_views[ring];
   int64_t off = 0, pix_off = 0;
   for (int v = 0; v < n_views; ++v) {
     const nxs_camera& cm = cams[v];
@@ -451,11 +465,13 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
   if ((st = ensure(ctx, ctx->partials, sizeof(uint4) * project_partials_size(g->n), s)))
     return st;
   guard.armed = true;
-  HIP_TRY(hipMemcpyAsync(ctx->views.p, host_views, sizeof(ViewDev) * n_views,
-                         hipMemcpyHostToDevice, s));
-  if (!ctx->noalloc) {
-    HIP_TRY(hipEventRecord(ctx->views_copied[ring], s));
-    ctx->views_pending[ring] = true;
+  if (!by_arg) {
+    HIP_TRY(hipMemcpyAsync(ctx->views.p, host_views, sizeof(ViewDev) * n_views,
+                           hipMemcpyHostToDevice, s));
+    if (!ctx->noalloc) {
+      HIP_TRY(hipEventRecord(ctx->views_copied[ring], s));
+      ctx->views_pending[ring] = true;
+    }
   }
   const ViewDev* dviews = P<ViewDev>(ctx->views);
 
@@ -478,6 +494,8 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
       ctx->status_clear = true;
     }
     icap = instance_capacity(ctx);
+    // (the count of the latest deferred render whose status has landed)
+    if (ctx->host_status->last) ctx->m_hint = ctx->host_status->last;
     if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_words(std::max<int64_t>(S, icap)), s)))
       return st;
   }
@@ -491,13 +509,18 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
   ctx->ev_valid = false;
   HIP_TRY(mark(0));
   const int depth_first = ctx->noalloc ? 0 : ctx->depth_first;
-  DeferCheck chk{~0ull, 0, nullptr};
-  if (deferred) chk = DeferCheck{icap, depth_first, P<DeferredStatus>(ctx->status)};
+  // (the fold writes the counters, or a deferred render's status, straight
+  // into the context's pinned memory; the no-alloc call copies them)
+  DeferCheck chk{~0ull, 0, nullptr, nullptr, ctx->noalloc ? nullptr : ctx->host_counters};
+  if (deferred)
+    chk = DeferCheck{icap, depth_first, P<DeferredStatus>(ctx->status), ctx->host_status,
+                     nullptr};
   // (also clears the tile ranges and, after them, the composite schedules'
   // counters)
-  launch_project(gd, dviews, n_views, kappa2, c.alpha_min, tw, th, proj,
-                 P<uint4>(ctx->partials), dcount, chk, P<uint32_t>(ctx->ranges),
-                 2 * total_tiles + kSchedCounters, s);
+  if (!launch_project(gd, P<ViewDev>(ctx->views), by_arg ? host_views : nullptr, n_views,
+                      kappa2, c.alpha_min, tw, th, proj, P<uint4>(ctx->partials), dcount, chk,
+                      P<uint32_t>(ctx->ranges), 2 * total_tiles + kSchedCounters, s))
+    return fail(ctx, NXS_EHIP, "the view table could not be passed to the projection");
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(1));
   // The instance count M is read by the host only where it sizes buffers and
@@ -508,9 +531,11 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
   // slower: the cross-stream wait costs more than the copy.)  A deferred
   // render reads nothing.
   if (!deferred) {
-    HIP_TRY(hipMemcpyAsync(ctx->host_counters, dcount, sizeof(Counters), hipMemcpyDeviceToHost,
-                           s));
-    if (!ctx->noalloc) HIP_TRY(hipEventRecord(ctx->counted, s));
+    if (ctx->noalloc)
+      HIP_TRY(hipMemcpyAsync(ctx->host_counters, dcount, sizeof(Counters),
+                             hipMemcpyDeviceToHost, s));
+    else
+      HIP_TRY(hipEventRecord(ctx->counted, s));
   }
   HIP_TRY(mark(2));
   // 1. depth sort of the slots (values: the slots 0..S-1)
@@ -544,6 +569,10 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     else
       HIP_TRY(hipEventSynchronize(ctx->counted));
     M = ctx->host_counters->total;
+    // (every earlier render has completed, its status copy included: this
+    // count is now the newest one)
+    ctx->m_hint = M;
+    if (!ctx->noalloc) ctx->host_status->last = 0;
     // the depth sort skipped pass 0 but this render's plan needs it: sort and
     // emit again below (the depth keys are intact)
     const bool pass0 = (ctx->host_counters->plan[0] & kPassActive) != 0;
@@ -573,6 +602,13 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     ctx->last_tiles = total_tiles;
   }
   const Counters* dn = deferred ? dcount : nullptr;
+  // deferred: grids for the expected count (the caller's hint, else the
+  // context's last count), not the capacity
+  const uint64_t expect = opts->instance_hint > 0.0f && std::isfinite(opts->instance_hint)
+                              ? (uint64_t)std::min(opts->instance_hint, 4.0e9f)
+                              : ctx->m_hint;
+  const int64_t m_plan =
+      deferred ? (int64_t)std::min<uint64_t>(M, expect + expect / 4 + 4096) : (int64_t)M;
   uint32_t* inst_tile = P<uint32_t>(ctx->inst_tile);
   uint32_t* inst_val = P<uint32_t>(ctx->inst_val);
   bool list_alt = false;
@@ -582,7 +618,7 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     const int tbits = bit_length((uint64_t)(total_tiles - 1));
     const int wt = radix_sort(inst_tile, inst_val, P<uint32_t>(ctx->inst_tile_alt),
                               P<uint32_t>(ctx->inst_val_alt), inst_tile, inst_val, (int64_t)M,
-                              tbits, P<uint32_t>(ctx->counts), s, dn);
+                              tbits, P<uint32_t>(ctx->counts), s, dn, m_plan);
     if (wt == 0) {
       inst_tile = P<uint32_t>(ctx->inst_tile_alt);
       inst_val = P<uint32_t>(ctx->inst_val_alt);
@@ -590,7 +626,7 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     }
     HIP_TRY(mark(5));
     // 4. tile ranges
-    launch_ranges(inst_tile, (int64_t)M, P<uint2>(ctx->ranges), s, dn);
+    launch_ranges(inst_tile, (int64_t)M, P<uint2>(ctx->ranges), s, dn, m_plan);
   } else {
     HIP_TRY(mark(5));
   }
@@ -625,6 +661,7 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
   HIP_TRY(hipGetLastError());
   HIP_TRY(mark(7));
   ctx->ev_valid = ctx->timing;
+  ctx->last_deferred = deferred;
 
   ctx->last_slots = S;
   ctx->last_n = g->n;
@@ -690,6 +727,8 @@ nxs_status nxs_create(nxs_context** out, int device, nxs_alloc_fn alloc, nxs_fre
   bool ok = hipSetDevice(device) == hipSuccess &&
             hipHostMalloc((void**)&ctx->host_counters, sizeof(Counters),
                           hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&ctx->host_status, sizeof(DeferredStatus),
+                          hipHostMallocDefault) == hipSuccess &&
             hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&ctx->counted, hipEventDisableTiming) == hipSuccess;
   for (int k = 0; k < nxs_context::kViewRing && ok; ++k)
@@ -712,6 +751,7 @@ nxs_status nxs_create(nxs_context** out, int device, nxs_alloc_fn alloc, nxs_fre
   if (!ok) {
     (void)hipGetLastError();
     if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+    if (ctx->host_status) (void)hipHostFree(ctx->host_status);
     if (ctx->done) (void)hipEventDestroy(ctx->done);
     if (ctx->counted) (void)hipEventDestroy(ctx->counted);
     for (int k = 0; k < nxs_context::kViewRing; ++k)
@@ -757,6 +797,7 @@ nxs_status nxs_destroy(nxs_context* ctx) {
     (void)hipMemPoolDestroy(ctx->al.pool);
   }
   if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+  if (ctx->host_status) (void)hipHostFree(ctx->host_status);
   for (int k = 0; k < nxs_context::kViewRing; ++k) {
     if (ctx->host_views[k]) (void)hipHostFree(ctx->host_views[k]);
     if (ctx->views_copied[k]) (void)hipEventDestroy(ctx->views_copied[k]);
@@ -830,11 +871,14 @@ nxs_status nxs_forward_status(nxs_context* ctx, int64_t* needed) {
   HIP_TRY(hipSetDevice(ctx->device));
   if (ctx->has_done) HIP_TRY(hipEventSynchronize(ctx->done));
   if (!ctx->status.p || !ctx->status_clear) return NXS_OK;
-  DeferredStatus ds{};
-  HIP_TRY(hipMemcpy(&ds, ctx->status.p, sizeof(ds), hipMemcpyDeviceToHost));
+  // (the last deferred render copied the status here before `done`)
+  const DeferredStatus ds = *ctx->host_status;
   if (ds.count == 0) return NXS_OK;
-  const DeferredStatus zero{};
+  DeferredStatus zero{};
+  zero.last = ds.last;
+  zero.last_fail = ds.last_fail;
   HIP_TRY(hipMemcpy(ctx->status.p, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  *ctx->host_status = zero;
   if (needed) *needed = (int64_t)ds.need;
   if (ds.fail & kFailPlan) ctx->depth_first = 0;
   if (ds.need >= 0xFFFFFFFFull)
@@ -850,6 +894,10 @@ nxs_status nxs_forward_status(nxs_context* ctx, int64_t* needed) {
                   why.c_str());
     }
   }
+  if (!(ds.fail & kFailCapacity))
+    return fail(ctx, NXS_ECAPACITY, "%u deferred render(s) needed a four-pass depth sort "
+                "where the context launched three; it now launches four: render them again",
+                ds.count);
   return fail(ctx, NXS_ECAPACITY, "%u deferred render(s) outgrew the workspace (%llu "
               "instances needed); the context has grown: render them again", ds.count,
               (unsigned long long)ds.need);
@@ -1054,15 +1102,15 @@ namespace {
 // The instance count of the last render; a deferred one's is read from the
 // device (its needed count if it failed).  Returns false if unknown.
 nxs_status resolve_last_m(nxs_context* ctx, bool* failed) {
-  *failed = false;
+  *failed = ctx->last_failed;
   if (ctx->last_m >= 0) return NXS_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   if (ctx->has_done) HIP_TRY(hipEventSynchronize(ctx->done));
-  Counters c{};
-  if (!ctx->counters.p) return fail(ctx, NXS_EINVAL, "no render on this context");
-  HIP_TRY(hipMemcpy(&c, ctx->counters.p, sizeof(c), hipMemcpyDeviceToHost));
-  ctx->last_m = (int64_t)c.total;
-  *failed = c.fail != 0;
+  // the deferred render copied its count and fail bits to the pinned status
+  // before `done`
+  ctx->last_m = (int64_t)ctx->host_status->last;
+  ctx->last_failed = ctx->host_status->last_fail != 0;
+  *failed = ctx->last_failed;
   return NXS_OK;
 }
 

@@ -68,15 +68,22 @@ constexpr uint32_t kFailPlan = 2u;       // the depth sort skipped a pass it nee
 // it (device memory, cleared by the host).
 struct DeferredStatus {
   unsigned long long need;   // largest instance count a failed render needed
+  unsigned long long last;   // instance count of the latest deferred render
   uint32_t fail;             // OR of their kFail* bits
   uint32_t count;            // failed renders
+  uint32_t last_fail;        // kFail* bits of the latest deferred render
+  uint32_t pad_;
 };
 
-// What the projection's final fold checks for a deferred render.
+// What the projection's final fold checks for a deferred render, and where
+// it also writes its results in pinned host memory (so that no copy command
+// follows it).
 struct DeferCheck {
   unsigned long long capacity;   // instance capacity (~0: not deferred)
   int first_pass;                // first depth-sort pass launched (0 or 1)
-  DeferredStatus* status;        // updated when the render fails; may be null
+  DeferredStatus* status;        // device status, updated by every deferred render
+  DeferredStatus* status_host;   // pinned copy of it after the update, or null
+  Counters* counters_host;       // pinned copy of the counters, or null
 };
 
 // The instance count a kernel after the emission works on: 0 for a failed
@@ -85,12 +92,24 @@ __device__ __forceinline__ int64_t live_count(const Counters* c) {
   return c->fail ? 0 : (int64_t)c->total;
 }
 
+// Up to this many views travel to the projection as a kernel argument (the
+// projection then writes the device view table the later kernels read), so
+// that a render needs no host-to-device copy.
+constexpr int kArgViews = 8;
+struct ViewArgs {
+  ViewDev v[kArgViews];
+};
+
 // ---- launchers (all enqueue on `s`) ------------------------------------------
 // `partials` needs project_partials_size(n) entries.  Also sets `counters`
 // (total instances, depth-bit range, depth-sort plan, fail bits from `check`)
-// and zeroes clear[0, n_clear).
+// and zeroes clear[0, n_clear).  host_views: null, or the n_views <=
+// kArgViews views (host memory, read during the call), which the projection
+// writes to `views`; otherwise `views` must already hold them.  Returns
+// false if host_views was given but cannot be used (no Gaussians): the
+// caller then copies the table itself.
 size_t project_partials_size(int n);
-void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
+bool launch_project(const GaussDev& g, ViewDev* views, const ViewDev* host_views, int n_views,
                     float kappa2, float alpha_min, int tile_w, int tile_h,
                     const ProjDev& out, uint4* partials, Counters* counters,
                     const DeferCheck& check, uint32_t* clear, int64_t n_clear,
@@ -106,11 +125,13 @@ constexpr uint32_t kPassActive = 1u << 16;
 // returns which pair holds the result (0 or 1).  vals_in == nullptr: values
 // are the input positions.  `counts` needs radix_counts_words(n) u32.
 // With `dn`, the number of pairs is read on the device (live_count(dn)) and
-// n is only its upper bound, which sizes the grids and the counts layout.
+// n is only its upper bound, which sizes the counts layout; the grids are
+// planned for n_plan pairs (0: n) and their work-groups loop over the chunks
+// of a larger count.
 size_t radix_counts_words(int64_t n);
 int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
-               hipStream_t s, const Counters* dn = nullptr);
+               hipStream_t s, const Counters* dn = nullptr, int64_t n_plan = 0);
 // The same sort with its digits read from device memory: plan[p] = shift |
 // width << 8 | kPassActive for kPlanPasses passes (an active pass of width 0
 // copies).  Passes 1..3 are always active, pass 0 only when three digits of
@@ -149,9 +170,10 @@ void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted, i
 // filled in, normally [0, 0)).
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s);
 // m: the number of instances, or with `dn` its upper bound (the count itself
-// is then read on the device).
+// is then read on the device; the grid is planned for m_plan instances and
+// loops beyond them).
 void launch_ranges(const uint32_t* inst_tile, int64_t m, uint2* ranges, hipStream_t s,
-                   const Counters* dn = nullptr);
+                   const Counters* dn = nullptr, int64_t m_plan = 0);
 
 struct CompositeParams {
   float log2_alpha_min;

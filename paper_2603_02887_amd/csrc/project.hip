@@ -18,6 +18,8 @@
 
 #include "nxs_internal.h"
 
+#include <cstring>
+
 namespace nxs {
 
 namespace {
@@ -232,12 +234,27 @@ __device__ void fold_partials(const uint4* partials, int nblocks, Counters* c,
     if (tot > chk.capacity) fail |= kFailCapacity;
     if (chk.first_pass > first) fail |= kFailPlan;
     c->fail = fail;
-    if (fail && chk.status) {
-      DeferredStatus* st = chk.status;
-      st->need = max(st->need, tot);
-      st->fail |= fail;
-      st->count += 1u;
+    if (chk.counters_host) {
+      Counters* h = chk.counters_host;
+      h->total = tot;
+      h->dmin = mn;
+      h->dmax = mx;
+      for (int p = 0; p < kPlanPasses; ++p) h->plan[p] = c->plan[p];
+      h->fail = fail;
     }
+    if (chk.status) {
+      DeferredStatus* st = chk.status;
+      st->last = tot;
+      st->last_fail = fail;
+      if (fail) {
+        st->need = max(st->need, tot);
+        st->fail |= fail;
+        st->count += 1u;
+      }
+      if (chk.status_host) *chk.status_host = *st;
+    }
+    // (the host reads the pinned copies once the kernel has completed)
+    if (chk.counters_host || chk.status_host) __threadfence_system();
   }
 }
 
@@ -245,12 +262,22 @@ __device__ void fold_partials(const uint4* partials, int nblocks, Counters* c,
 // block's SH coefficients (contiguous in HBM) are staged into LDS with
 // coalesced loads, padded to an odd stride so that per-thread reads are free
 // of bank conflicts; each Gaussian's inputs are read once for all views.
-template <int DEG>
+// ARGS: the views come as the kernel argument `va`, and work-group 0 writes
+// them to the device table `views` for the kernels that follow; otherwise
+// they are read from `views`.
+template <int DEG, bool ARGS>
 __global__ __launch_bounds__(kBlock) void project_kernel(
-    GaussDev g, const ViewDev* __restrict__ views, int n_views, float kappa2,
+    GaussDev g, ViewDev* __restrict__ views, ViewArgs va, int n_views, float kappa2,
     float alpha_min, int tile_w, int tile_h, ProjDev out, uint4* __restrict__ partials,
     uint32_t* __restrict__ clear, int64_t n_clear) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  if (ARGS && blockIdx.x == 0) {
+    constexpr int kWords = (int)(sizeof(ViewDev) / 4);
+    static_assert(sizeof(ViewDev) % 4 == 0, "the table is copied by words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(va.v);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(views);
+    for (int w = threadIdx.x; w < n_views * kWords; w += kBlock) dst[w] = src[w];
+  }
   // the tile ranges of this render start empty (the ranges pass fills in the
   // occupied tiles)
   for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n_clear;
@@ -336,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   uint32_t nt_sum = 0, dmin = 0xFFFFFFFFu, dmax = 0u;
   for (int vi = 0; vi < n_views; ++vi) {
     if (!valid) break;
-    const ViewDev& v = views[vi];
+    const ViewDev& v = ARGS ? va.v[vi] : views[vi];
     const int64_t slot = (int64_t)vi * g.n + i;
     KeyGeom kg = key_recipe(m, s, q, aleph, v, kappa2, alpha_min, tile_w, tile_h);
     uint2 rect = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
@@ -449,17 +476,26 @@ __global__ __launch_bounds__(kFoldThreads) void reduce_counters_kernel(
 
 }  // namespace
 
-void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
+bool launch_project(const GaussDev& g, ViewDev* views, const ViewDev* host_views, int n_views,
                     float kappa2, float alpha_min, int tile_w, int tile_h,
                     const ProjDev& out, uint4* partials, Counters* counters,
                     const DeferCheck& check, uint32_t* clear, int64_t n_clear,
                     hipStream_t s) {
   const bool any = g.n > 0 && n_views > 0;
   const int nblocks = any ? (g.n + kBlock - 1) / kBlock : 0;
-#define NXS_PROJECT(D)                                                                  \
-  hipLaunchKernelGGL(project_kernel<D>, dim3(nblocks), dim3(kBlock), 0, s, g, views,   \
-                     n_views, kappa2, alpha_min, tile_w, tile_h, out, partials, clear, \
-                     n_clear)
+  const bool args = host_views && any && n_views <= kArgViews;
+  ViewArgs va;
+  std::memset(&va, 0, sizeof(va));
+  if (args) std::memcpy(va.v, host_views, sizeof(ViewDev) * n_views);
+#define NXS_PROJECT(D)                                                                     \
+  if (args)                                                                                \
+    hipLaunchKernelGGL((project_kernel<D, true>), dim3(nblocks), dim3(kBlock), 0, s, g,    \
+                       views, va, n_views, kappa2, alpha_min, tile_w, tile_h, out,         \
+                       partials, clear, n_clear);                                          \
+  else                                                                                     \
+    hipLaunchKernelGGL((project_kernel<D, false>), dim3(nblocks), dim3(kBlock), 0, s, g,   \
+                       views, va, n_views, kappa2, alpha_min, tile_w, tile_h, out,         \
+                       partials, clear, n_clear)
   if (any) {
     switch (g.sh_degree) {
       case 0: NXS_PROJECT(0); break;
@@ -473,6 +509,7 @@ void launch_project(const GaussDev& g, const ViewDev* views, int n_views,
 #undef NXS_PROJECT
   hipLaunchKernelGGL(reduce_counters_kernel, dim3(1), dim3(kFoldThreads), 0, s, partials,
                      nblocks, counters, check);
+  return args || !host_views;
 }
 
 size_t project_partials_size(int n) { return (size_t)((n + kBlock - 1) / kBlock) + 1; }

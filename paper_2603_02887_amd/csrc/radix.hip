@@ -40,8 +40,23 @@ constexpr int kRBinsPerThread = kRBins / kRThreads;
 static_assert(kRBinsPerThread == 2, "the scans below take two digits per thread");
 constexpr uint32_t kRXcds = 8;
 
-__device__ __forceinline__ uint32_t chunk_of(uint32_t b, uint32_t per) {
-  return (b % kRXcds) * per + b / kRXcds;
+// The chunks of work-group b out of a grid of 8 * per_g when nlive chunks
+// hold keys: XCD x = b % 8 (work-groups are dealt to the XCDs round-robin)
+// owns the contiguous chunks [x * per_c, (x + 1) * per_c), per_c =
+// ceil(nlive / 8), and its work-groups take them in turn from x * per_c +
+// b / 8 in steps of per_g.  A grid planned for the chunk count gives every
+// work-group one chunk; a smaller grid loops.
+struct ChunkWalk {
+  uint32_t first, end, step;
+};
+__device__ __forceinline__ ChunkWalk chunk_walk(uint32_t b, uint32_t per_g, uint32_t nlive) {
+  const uint32_t per_c = (nlive + kRXcds - 1) / kRXcds;
+  const uint32_t x = b % kRXcds;
+  ChunkWalk w;
+  w.first = x * per_c + b / kRXcds;
+  w.end = min((x + 1) * per_c, nlive);
+  w.step = per_g;
+  return w;
 }
 
 // lanes of the wave whose digit equals this lane's (valid lanes only)
@@ -104,36 +119,38 @@ __global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* keys,
                                                       const Counters* __restrict__ dn) {
   __shared__ uint32_t h[kRBins];
   if (!pass_digit(plan, pass, shift, width)) return;   // the whole grid
-  const uint32_t c = chunk_of(blockIdx.x, per);
   n = key_count(n, dn);
-  if (c >= nchunks || c >= live_chunks<ITEMS>(n)) return;   // the whole work-group
+  const ChunkWalk walk = chunk_walk(blockIdx.x, per, min(nchunks, live_chunks<ITEMS>(n)));
   {
     const uint32_t* unused = nullptr;
     select_input(plan, pass, keys_first, nullptr, keys, unused);
   }
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  for (int d = t; d < kRBins; d += kRThreads) h[d] = 0;
-  __syncthreads();
   const uint32_t mask = (1u << width) - 1u;
-  const int64_t base = (int64_t)c * (kRThreads * ITEMS);
-  const int chunk_n = (int)min((int64_t)(kRThreads * ITEMS), n - base);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t k[ITEMS];
+  for (uint32_t c = walk.first; c < walk.end; c += walk.step) {   // (uniform per group)
+    for (int d = t; d < kRBins; d += kRThreads) h[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)c * (kRThreads * ITEMS);
+    const int chunk_n = (int)min((int64_t)(kRThreads * ITEMS), n - base);
+    uint32_t k[ITEMS];
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int li = wid * (64 * ITEMS) + r * 64 + lane;
-    k[r] = li < chunk_n ? keys[base + li] : 0u;
-  }
+    for (int r = 0; r < ITEMS; ++r) {
+      const int li = wid * (64 * ITEMS) + r * 64 + lane;
+      k[r] = li < chunk_n ? keys[base + li] : 0u;
+    }
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int li = wid * (64 * ITEMS) + r * 64 + lane;
-    const bool valid = li < chunk_n;
-    const uint32_t d = (k[r] >> shift) & mask;
-    const uint64_t peers = digit_peers(d, width, valid);
-    if (valid && (peers & lt_mask) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    for (int r = 0; r < ITEMS; ++r) {
+      const int li = wid * (64 * ITEMS) + r * 64 + lane;
+      const bool valid = li < chunk_n;
+      const uint32_t d = (k[r] >> shift) & mask;
+      const uint64_t peers = digit_peers(d, width, valid);
+      if (valid && (peers & lt_mask) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    for (int d = t; d <= (int)mask; d += kRThreads) counts[(int64_t)d * nchunks + c] = h[d];
+    __syncthreads();   // h is cleared for the next chunk
   }
-  __syncthreads();
-  for (int d = t; d <= (int)mask; d += kRThreads) counts[(int64_t)d * nchunks + c] = h[d];
 }
 
 __device__ __forceinline__ uint32_t rx_block_scan(uint32_t x, uint32_t* s_tmp, uint32_t* total) {
@@ -214,99 +231,101 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
   __shared__ uint32_t s_tmp[kRWaves];
 
   if (!pass_digit(plan, pass, shift, width)) return;   // the whole grid
-  const uint32_t c = chunk_of(blockIdx.x, per);
   n = key_count(n, dn);
-  if (c >= nchunks || c >= live_chunks<ITEMS>(n)) return;   // the whole work-group
+  const ChunkWalk walk = chunk_walk(blockIdx.x, per, min(nchunks, live_chunks<ITEMS>(n)));
   select_input(plan, pass, keys_first, vals_first, keys_in, vals_in);
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
-  for (int w = 0; w < kRWaves; ++w)
-    for (int d = t; d < kRBins; d += kRThreads) s_wave[w][d] = 0;
   const uint32_t mask = (1u << width) - 1u;
   const int nd = 1 << width;
-  const int64_t base = (int64_t)c * (kRThreads * ITEMS);
-  const int chunk_n = (int)min((int64_t)(kRThreads * ITEMS), n - base);
+  for (uint32_t c = walk.first; c < walk.end; c += walk.step) {   // (uniform per group)
+    for (int w = 0; w < kRWaves; ++w)
+      for (int d = t; d < kRBins; d += kRThreads) s_wave[w][d] = 0;
+    const int64_t base = (int64_t)c * (kRThreads * ITEMS);
+    const int chunk_n = (int)min((int64_t)(kRThreads * ITEMS), n - base);
 
-  uint32_t k_reg[ITEMS], v_reg[ITEMS];
+    uint32_t k_reg[ITEMS], v_reg[ITEMS];
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int li = wid * (64 * ITEMS) + r * 64 + lane;
-    k_reg[r] = 0u;
-    v_reg[r] = 0u;
-    if (li < chunk_n) {
-      k_reg[r] = keys_in[base + li];
-      v_reg[r] = vals_in ? vals_in[base + li] : (uint32_t)(base + li);
+    for (int r = 0; r < ITEMS; ++r) {
+      const int li = wid * (64 * ITEMS) + r * 64 + lane;
+      k_reg[r] = 0u;
+      v_reg[r] = 0u;
+      if (li < chunk_n) {
+        k_reg[r] = keys_in[base + li];
+        v_reg[r] = vals_in ? vals_in[base + li] : (uint32_t)(base + li);
+      }
     }
-  }
-  // global start of this chunk's run of each digit: keys of smaller digits
-  // plus keys of that digit in earlier chunks (thread t: digits 2t, 2t + 1)
-  {
-    const int d0 = 2 * t, d1 = 2 * t + 1;
-    const uint32_t tot0 = d0 < nd ? totals[d0] : 0u, tot1 = d1 < nd ? totals[d1] : 0u;
-    const uint32_t off0 = d0 < nd ? counts[(int64_t)d0 * nchunks + c] : 0u;
-    const uint32_t off1 = d1 < nd ? counts[(int64_t)d1 * nchunks + c] : 0u;
-    uint32_t all;
-    const uint32_t ex = rx_block_scan(tot0 + tot1, s_tmp, &all);
-    s_gbase[d0] = ex + off0;
-    s_gbase[d1] = ex + tot0 + off1;
-  }
-  __syncthreads();
-  // per-wave ranks: keys of the same digit earlier in this wave's part
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t rank[ITEMS], dig[ITEMS];
+    // global start of this chunk's run of each digit: keys of smaller digits
+    // plus keys of that digit in earlier chunks (thread t: digits 2t, 2t + 1)
+    {
+      const int d0 = 2 * t, d1 = 2 * t + 1;
+      const uint32_t tot0 = d0 < nd ? totals[d0] : 0u, tot1 = d1 < nd ? totals[d1] : 0u;
+      const uint32_t off0 = d0 < nd ? counts[(int64_t)d0 * nchunks + c] : 0u;
+      const uint32_t off1 = d1 < nd ? counts[(int64_t)d1 * nchunks + c] : 0u;
+      uint32_t all;
+      const uint32_t ex = rx_block_scan(tot0 + tot1, s_tmp, &all);
+      s_gbase[d0] = ex + off0;
+      s_gbase[d1] = ex + tot0 + off1;
+    }
+    __syncthreads();
+    // per-wave ranks: keys of the same digit earlier in this wave's part
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t rank[ITEMS], dig[ITEMS];
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int li = wid * (64 * ITEMS) + r * 64 + lane;
-    const bool valid = li < chunk_n;
-    const uint32_t d = valid ? (k_reg[r] >> shift) & mask : 0u;
-    const uint64_t peers = digit_peers(d, width, valid);
-    dig[r] = d;
-    rank[r] = 0;
-    if (valid) {
-      const uint32_t before = s_wave[wid][d];   // the same for every peer
-      const uint32_t pos = (uint32_t)__popcll(peers & lt_mask);
-      rank[r] = before + pos;
-      if (pos == 0) s_wave[wid][d] = before + (uint32_t)__popcll(peers);
+    for (int r = 0; r < ITEMS; ++r) {
+      const int li = wid * (64 * ITEMS) + r * 64 + lane;
+      const bool valid = li < chunk_n;
+      const uint32_t d = valid ? (k_reg[r] >> shift) & mask : 0u;
+      const uint64_t peers = digit_peers(d, width, valid);
+      dig[r] = d;
+      rank[r] = 0;
+      if (valid) {
+        const uint32_t before = s_wave[wid][d];   // the same for every peer
+        const uint32_t pos = (uint32_t)__popcll(peers & lt_mask);
+        rank[r] = before + pos;
+        if (pos == 0) s_wave[wid][d] = before + (uint32_t)__popcll(peers);
+      }
     }
-  }
-  __syncthreads();
-  // local start of each digit's run in the chunk
-  {
-    const int d0 = 2 * t, d1 = 2 * t + 1;
-    uint32_t cnt0 = 0, cnt1 = 0;
-    for (int w = 0; w < kRWaves; ++w) {
-      cnt0 += s_wave[w][d0];
-      cnt1 += s_wave[w][d1];
+    __syncthreads();
+    // local start of each digit's run in the chunk
+    {
+      const int d0 = 2 * t, d1 = 2 * t + 1;
+      uint32_t cnt0 = 0, cnt1 = 0;
+      for (int w = 0; w < kRWaves; ++w) {
+        cnt0 += s_wave[w][d0];
+        cnt1 += s_wave[w][d1];
+      }
+      uint32_t all;
+      const uint32_t ex = rx_block_scan(cnt0 + cnt1, s_tmp, &all);
+      s_lbase[d0] = ex;
+      s_lbase[d1] = ex + cnt0;
     }
-    uint32_t all;
-    const uint32_t ex = rx_block_scan(cnt0 + cnt1, s_tmp, &all);
-    s_lbase[d0] = ex;
-    s_lbase[d1] = ex + cnt0;
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int r = 0; r < ITEMS; ++r) {
-    const int li = wid * (64 * ITEMS) + r * 64 + lane;
-    if (li < chunk_n) {
-      const uint32_t d = dig[r];
-      uint32_t off = s_lbase[d] + rank[r];
-      for (int w = 0; w < wid; ++w) off += s_wave[w][d];
-      s_key[off] = k_reg[r];
-      s_val[off] = v_reg[r];
+    for (int r = 0; r < ITEMS; ++r) {
+      const int li = wid * (64 * ITEMS) + r * 64 + lane;
+      if (li < chunk_n) {
+        const uint32_t d = dig[r];
+        uint32_t off = s_lbase[d] + rank[r];
+        for (int w = 0; w < wid; ++w) off += s_wave[w][d];
+        s_key[off] = k_reg[r];
+        s_val[off] = v_reg[r];
+      }
     }
-  }
-  __syncthreads();
-  for (int i = t; i < chunk_n; i += kRThreads) {
-    const uint32_t k = s_key[i];
-    const uint32_t d = (k >> shift) & mask;
-    const uint32_t g = s_gbase[d] + (uint32_t)i - s_lbase[d];
-    keys_out[g] = k;
-    vals_out[g] = s_val[i];
-    if (tinfo) {   // the slot's tile record, now in sorted order
-      const uint4 ti = tinfo[s_val[i]];
-      nt_out[g] = ti.z;
-      rect_out[g] = make_uint2(ti.x, ti.y);
+    __syncthreads();
+    for (int i = t; i < chunk_n; i += kRThreads) {
+      const uint32_t k = s_key[i];
+      const uint32_t d = (k >> shift) & mask;
+      const uint32_t g = s_gbase[d] + (uint32_t)i - s_lbase[d];
+      keys_out[g] = k;
+      vals_out[g] = s_val[i];
+      if (tinfo) {   // the slot's tile record, now in sorted order
+        const uint4 ti = tinfo[s_val[i]];
+        nt_out[g] = ti.z;
+        rect_out[g] = make_uint2(ti.x, ti.y);
+      }
     }
+    __syncthreads();   // the LDS tables are rebuilt for the next chunk
   }
 }
 
@@ -326,11 +345,15 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
                uint32_t* k1, uint32_t* v1, int64_t n, int first, int passes,
                const int* shifts, const int* widths, const uint32_t* plan, uint32_t* counts,
                const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s,
-               const Counters* dn) {
-  const bool large = n >= kRLargeFrom;
+               const Counters* dn, int64_t n_plan) {
+  // n bounds the keys (the counts layout); the grid is planned for n_plan
+  // keys (with dn, the count expected on the device) and loops beyond it
+  const bool large = n_plan >= kRLargeFrom;
   const int chunk = kRThreads * (large ? kRItemsLarge : kRItemsSmall);
   const uint32_t nchunks = (uint32_t)((n + chunk - 1) / chunk);
-  const uint32_t per = (nchunks + kRXcds - 1) / kRXcds;
+  const uint32_t plan_chunks =
+      (uint32_t)std::max<int64_t>((std::min(n_plan, n) + chunk - 1) / chunk, 1);
+  const uint32_t per = (plan_chunks + kRXcds - 1) / kRXcds;
   const unsigned grid = per * kRXcds;
   uint32_t* totals = counts + (size_t)nchunks * kRBins;
   const uint32_t* kin = keys_in;
@@ -368,7 +391,7 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
 
 int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int nbits, uint32_t* counts,
-               hipStream_t s, const Counters* dn) {
+               hipStream_t s, const Counters* dn, int64_t n_plan) {
   if (n <= 0) return 0;
   nbits = std::max(nbits, 1);
   const int passes = (nbits + kMaxDigitBits - 1) / kMaxDigitBits;
@@ -379,7 +402,8 @@ int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
     shift += widths[p];
   }
   return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, 0, passes, shifts, widths, nullptr,
-                    counts, nullptr, nullptr, nullptr, s, dn);
+                    counts, nullptr, nullptr, nullptr, s, dn,
+                    dn && n_plan > 0 ? std::min(n_plan, n) : n);
 }
 
 int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
@@ -388,7 +412,7 @@ int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
                        const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
   if (n <= 0) return 1;
   return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, first_pass, kPlanPasses, nullptr,
-                    nullptr, plan, counts, tinfo, nt_out, rect_out, s, nullptr);
+                    nullptr, plan, counts, tinfo, nt_out, rect_out, s, nullptr, n);
 }
 
 }  // namespace nxs

@@ -18,11 +18,16 @@
 // one slot's projection runs while another's sort or composite does, and
 // requests that arrive meanwhile are admitted as slots free up.
 //
-// A batch whose estimate was too low fails with NXS_ECAPACITY before allocating
-// past the limit: the step reads the instance count the attempt needed,
-// re-estimates and starts the prefix that fits (after one release of a
-// fragmented workspace); a single request that cannot fit on its own, or one
-// with invalid options, is completed with its error without blocking the queue.
+// Batches are rendered deferred (NXS_FLAG_DEFERRED): starting one never waits
+// on the host.  A deferred batch that outgrew its slot's instance buffers is
+// found when it completes (nxs_forward_status): its requests go back to the
+// front of the queue and are rendered again, waiting this time, after the
+// slot has grown.  A waiting batch whose estimate was too low fails with
+// NXS_ECAPACITY before allocating past the limit: the step reads the instance
+// count the attempt needed, re-estimates and starts the prefix that fits
+// (after one release of a fragmented workspace); a single request that
+// cannot fit on its own, or one with invalid options, is completed with its
+// error without blocking the queue.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,6 +49,7 @@ struct Request {
   nxs_render_opts opts;
   nxs_image out;
   int64_t tag;
+  bool retry = false;   // a deferred render of it outgrew its slot: render waiting
 };
 
 struct Scene {
@@ -56,12 +62,16 @@ struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
+  bool deferred = false;         // the batch in flight was rendered deferred
   uint64_t seq = 0;              // start order, to report older batches first
   std::vector<int64_t> tags;     // requests in flight on this slot
+  std::vector<Request> reqs;     // the same requests, to queue again on a retry
 };
 
 bool same_batch(const Request& a, const Request& b) {
-  return a.scene == b.scene && std::memcmp(&a.opts, &b.opts, sizeof(nxs_render_opts)) == 0;
+  nxs_render_opts x = a.opts, y = b.opts;
+  x.instance_hint = y.instance_hint = 0.0f;   // a launch size, not a result
+  return a.scene == b.scene && std::memcmp(&x, &y, sizeof(nxs_render_opts)) == 0;
 }
 
 // Workspace bytes of one render (the library's per-slot, per-instance and
@@ -139,24 +149,35 @@ bool start_batch(nxs_server* s, Slot& sl, std::vector<int64_t>& tags,
 
   nxs_status st = NXS_OK;
   bool released = false;
+  bool deferred = false;
   for (;;) {
     const int32_t V = (int32_t)idx.size();
     std::vector<nxs_camera> cams(V);
     std::vector<nxs_image> outs(V);
     std::vector<const Request*> cur;
+    bool retry = false;
     for (int32_t v = 0; v < V; ++v) {
       cams[v] = s->pending[idx[v]].cam;
       outs[v] = s->pending[idx[v]].out;
       cur.push_back(&s->pending[idx[v]]);
+      retry = retry || s->pending[idx[v]].retry;
     }
     const double pixels = pixels_of(cur);
-    st = nxs_render_forward(sl.ctx, &sc.g, cams.data(), V, &s->pending[idx[0]].opts,
-                            outs.data(), nullptr, sl.stream);
+    nxs_render_opts opts = s->pending[idx[0]].opts;
+    deferred = !retry;
+    if (deferred) {
+      opts.flags |= NXS_FLAG_DEFERRED;
+      opts.instance_hint = (float)(sc.inst_per_px * pixels);
+    }
+    st = nxs_render_forward(sl.ctx, &sc.g, cams.data(), V, &opts, outs.data(), nullptr,
+                            sl.stream);
+    // (a waiting render's count is known now; a deferred one's when it completes)
     int64_t m = 0, t = 0;
-    nxs_inspect_counts(sl.ctx, &m, &t);
+    if (!deferred || st != NXS_OK) nxs_inspect_counts(sl.ctx, &m, &t);
     if (st == NXS_OK) {
       // follow the scene's instance density, decaying slowly towards lighter views
-      if (pixels > 0.0) sc.inst_per_px = std::max((double)m / pixels, 0.9 * sc.inst_per_px);
+      if (!deferred && pixels > 0.0)
+        sc.inst_per_px = std::max((double)m / pixels, 0.9 * sc.inst_per_px);
       if (hipEventRecord(sl.done, sl.stream) != hipSuccess) {
         (void)hipGetLastError();
         s->err = "event record failed";
@@ -192,9 +213,14 @@ bool start_batch(nxs_server* s, Slot& sl, std::vector<int64_t>& tags,
   }
   if (st == NXS_OK) {
     sl.busy = true;
+    sl.deferred = deferred;
     sl.seq = s->seq++;
     sl.tags.clear();
-    for (size_t k : idx) sl.tags.push_back(s->pending[k].tag);
+    sl.reqs.clear();
+    for (size_t k : idx) {
+      sl.tags.push_back(s->pending[k].tag);
+      sl.reqs.push_back(s->pending[k]);
+    }
   } else {
     tags.push_back(s->pending[idx[0]].tag);   // failed on its own: complete it now
     status.push_back(st);
@@ -314,9 +340,33 @@ nxs_status nxs_server_step(nxs_server* s, int32_t wait, int64_t* tags, int32_t* 
         return false;
       }
       block = false;
+      best->busy = false;
+      if (best->deferred) {
+        Scene& sc = s->scenes[best->reqs.front().scene];
+        double pixels = 0.0;
+        for (const Request& r : best->reqs) pixels += (double)r.cam.width * r.cam.height;
+        int64_t need = 0;
+        const nxs_status fs = nxs_forward_status(best->ctx, &need);
+        if (fs == NXS_ECAPACITY) {
+          // outgrew the slot: queue the requests again, in order, at the
+          // front; they are rendered waiting (the slot has grown if its
+          // limit allows, else the waiting render splits the batch)
+          if (need > 0 && pixels > 0.0)
+            sc.inst_per_px = std::max(sc.inst_per_px, 1.05 * (double)need / pixels);
+          for (size_t k = best->reqs.size(); k-- > 0;) {
+            Request r = best->reqs[k];
+            r.retry = true;
+            s->pending.push_front(r);
+          }
+          continue;
+        }
+        if (fs != NXS_OK) return false;
+        int64_t m = 0, t = 0;
+        if (nxs_inspect_counts(best->ctx, &m, &t) == NXS_OK && pixels > 0.0)
+          sc.inst_per_px = std::max((double)m / pixels, 0.9 * sc.inst_per_px);
+      }
       t_out.insert(t_out.end(), best->tags.begin(), best->tags.end());
       s_out.insert(s_out.end(), best->tags.size(), (int32_t)NXS_OK);
-      best->busy = false;
     }
   };
   // 1. batches that have finished

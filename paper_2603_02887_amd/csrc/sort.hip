@@ -13,6 +13,8 @@
 //
 #include "nxs_internal.h"
 
+#include <algorithm>
+
 namespace nxs {
 
 namespace {
@@ -234,12 +236,13 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t va
 __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict__ inst_tile,
                                                      int64_t m, uint2* __restrict__ ranges,
                                                      const Counters* __restrict__ dn) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (dn) m = min(m, live_count(dn));
-  if (j >= m) return;
-  const uint32_t tile = inst_tile[j];
-  if (j == 0 || inst_tile[j - 1] != tile) ranges[tile].x = (uint32_t)j;
-  if (j == m - 1 || inst_tile[j + 1] != tile) ranges[tile].y = (uint32_t)(j + 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    const uint32_t tile = inst_tile[j];
+    if (j == 0 || inst_tile[j - 1] != tile) ranges[tile].x = (uint32_t)j;
+    if (j == m - 1 || inst_tile[j + 1] != tile) ranges[tile].y = (uint32_t)(j + 1);
+  }
 }
 
 }  // namespace
@@ -278,9 +281,10 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t value, hipStream_t s) {
 }
 
 void launch_ranges(const uint32_t* inst_tile, int64_t m, uint2* ranges, hipStream_t s,
-                   const Counters* dn) {
+                   const Counters* dn, int64_t m_plan) {
   if (m <= 0) return;
-  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+  const int64_t g = dn && m_plan > 0 ? std::min(m_plan, m) : m;
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, s,
                      inst_tile, m, ranges, dn);
 }
 

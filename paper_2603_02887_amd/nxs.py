@@ -59,7 +59,7 @@ class RenderOpts(ctypes.Structure):
     _fields_ = [("model", c_int32), ("background", c_float * 3), ("alpha_min", c_float),
                 ("t_eps", c_float), ("tile_w", c_int32), ("tile_h", c_int32),
                 ("lds_batch", c_int32), ("param", c_float), ("flags", c_int32),
-                ("schedule", c_int32)]
+                ("schedule", c_int32), ("instance_hint", c_float)]
 
 
 FLAG_DEFERRED = 1
@@ -215,7 +215,7 @@ def _make_image(o):
 
 
 def _make_opts(model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0, t_eps=0.0, tile=(16, 16),
-               lds_batch=0, param=0.0, schedule=0, deferred=False):
+               lds_batch=0, param=0.0, schedule=0, deferred=False, instance_hint=0.0):
     if isinstance(model, str):
         model = MODEL_IDS[model]
     if isinstance(schedule, str):
@@ -230,6 +230,7 @@ def _make_opts(model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0, t_eps=0.0, ti
     opts.param = float(param)
     opts.flags = FLAG_DEFERRED if deferred else 0
     opts.schedule = int(schedule)
+    opts.instance_hint = float(instance_hint)
     return opts
 
 

@@ -97,6 +97,36 @@ def test_deferred_depth_plan_change_is_retried(nxs):
         ref_ctx.close()
 
 
+def test_deferred_render_larger_than_expected(nxs):
+    """The instance buffers hold a large render, but the context last saw a
+    small one: a deferred render of the large scene launches its tile sort and
+    ranges for the small count (with headroom) and their work-groups loop
+    over the remaining chunks; the result equals the waiting render."""
+    big = synth.random_scene(12, 20_000, sh_degree=0, log_scale=(-3.2, 0.4))
+    cam = synth.look_at_camera((0.1, 0.0, -3.0), width=256, height=256)
+    # the 20 nearest and 20 farthest: the same depth span (a four-pass depth
+    # sort, like the large scene) in few instances
+    by_depth = np.argsort(big.means[:, 2])
+    small = big.subset(np.concatenate([by_depth[:20], by_depth[-20:]]))
+    r, ref_ctx = nxs.Renderer(0), nxs.Renderer(0)
+    try:
+        gb, gs = nxs.scene_to_device(big), nxs.scene_to_device(small)
+        for model in (0, 2):
+            ref = ref_ctx.render(gb, [cam], model=model)[0]
+            r.render(gb, [cam], model=model)        # capacity for the large scene
+            m_big, _ = r.counts()
+            r.render(gs, [cam], model=model)        # ... but the last count is small
+            m_small, _ = r.counts()
+            assert m_big > 20 * (m_small + m_small // 4 + 4096)
+            out = r.render(gb, [cam], model=model, deferred=True)[0]
+            assert r.status() == 0
+            _same(out, ref)
+        parity.compare_keys(r, big, [cam])
+    finally:
+        r.close()
+        ref_ctx.close()
+
+
 def test_deferred_pipeline_equals_waiting(nxs):
     """Many deferred renders of alternating scenes and models enqueued with
     no wait in between equal the waiting renders; status() is clean."""

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -146,4 +147,51 @@ def test_batches_overlap_on_the_device(R):
     for q in reqs:
         q["model"] = 0
         assert torch.equal(done[q["tag"]]["rgb"], _alone(R, scenes[q["scene"]], q)["rgb"])
+    S.close()
+
+
+def test_served_results_match_the_oracle(R):
+    """Served requests of mixed scene, resolution and model (two slots,
+    continuous batching, deferred batches) against the FP64 oracle on
+    sampled pixels, at the tolerances of every other parity test."""
+    from paper_2603_02887_amd import nxs
+    scs = _scenes()
+    scenes = [nxs.scene_to_device(sc) for sc in scs]
+    S = nxs.Server(0, n_slots=2)
+    ids = [S.add_scene(g) for g in scenes]
+    reqs = _requests(16, len(scenes), seed=11)
+    for q in reqs:
+        S.submit(ids[q["scene"]], q["cam"], q["tag"], model=q["model"], overdraw=True)
+    done = {tag: (st, out) for tag, st, out in S.drain()}
+    S.close()
+    for q in reqs:
+        st, out = done[q["tag"]]
+        assert st == 0
+        px = parity.sample_pixels(q["cam"], 400, seed=q["tag"])
+        stats = parity.compare_view(out, scs[q["scene"]], q["cam"], q["model"], pixels=px)
+        print("served", q["tag"], q["model"], stats["max_rgb_err"], stats["ambiguous"])
+
+
+def test_deferred_overflow_in_a_batch_is_served_again(R):
+    """One slot sized by a tiny request, then a batch that needs far more
+    instances: its deferred render overflows, the batch is queued again and
+    rendered waiting after the slot has grown; every result equals the
+    request rendered alone."""
+    from paper_2603_02887_amd import nxs
+    scenes = [nxs.scene_to_device(sc) for sc in _scenes()]
+    S = nxs.Server(0, n_slots=1)
+    ids = [S.add_scene(g) for g in scenes]
+    tiny = synth.look_at_camera((0, 0, -5), width=16, height=16)
+    S.submit(ids[2], tiny, 1, model=1)
+    assert [t for t, st, _ in S.drain()] == [1]
+    small_ws = S.workspace_bytes()
+    reqs = [q for q in _requests(12, 2, seed=21)]
+    for q in reqs:
+        S.submit(ids[q["scene"]], q["cam"], q["tag"], model=q["model"])
+    done = {tag: (st, out) for tag, st, out in S.drain()}
+    assert S.workspace_bytes() > small_ws
+    for q in reqs:
+        st, out = done[q["tag"]]
+        assert st == 0
+        assert torch.equal(out["rgb"], _alone(R, scenes[q["scene"]], q)["rgb"])
     S.close()

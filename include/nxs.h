@@ -430,6 +430,16 @@ nxs_status nxs_inspect_projection(nxs_context* ctx, int32_t view,
                                   uint32_t* depth_bits_host, int32_t* rect_host,
                                   int64_t capacity);
 
+/* Per-slot sums of the last nxs_render_backward on this context, before the
+ * projection's chain rule (slot = view * n + Gaussian): for each slot, 9
+ * floats dLoss/d(aleph, u, v, A, B, C, r, g, b) -- the opacity aleph, the
+ * image-plane centre (u, v), the conic (A, B, C) of alpha = aleph exp(-q/2)
+ * with q = A dx^2 + 2 B dx dy + C dy^2, and the emission -- each summed over
+ * the pixels that composited the splat (appendix "Adjoints": dL/dalpha_i and
+ * dL/dE_i per pixel, chained through alpha_i).  slot_grads_host [capacity]
+ * with capacity >= 9 * n * n_views.  Waits for the backward. */
+nxs_status nxs_inspect_slot_grads(nxs_context* ctx, float* slot_grads_host, int64_t capacity);
+
 #ifdef __cplusplus
 }
 #endif

@@ -117,6 +117,7 @@ struct nxs_context {
   // instances of the context's last known render: a deferred render's tile
   // sort and ranges are launched for about this many (and loop beyond it)
   uint64_t m_hint = 0;
+  int64_t last_bwd_slots = -1;   // slots of the last backward (inspection)
 };
 
 namespace {
@@ -947,6 +948,7 @@ nxs_status nxs_render_backward(nxs_context* ctx, const nxs_fwd_state* state,
   launch_project_bwd(gd, P<ViewDev>(ctx->views), n_views, P<float>(ctx->gslot), gg, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(fs->used, s));
+  ctx->last_bwd_slots = S;
   return NXS_OK;
 }
 
@@ -1057,6 +1059,7 @@ nxs_status nxs_release_workspace(nxs_context* ctx) {
   HIP_TRY(hipSetDevice(ctx->device));
   if (ctx->has_done) HIP_TRY(hipEventSynchronize(ctx->done));
   free_workspace(ctx, nullptr);
+  ctx->last_bwd_slots = -1;
   if (!ctx->last_state) {
     ctx->last_inst_tile = ctx->last_inst_val = nullptr;
     ctx->last_m = ctx->last_tiles = ctx->last_slots = 0;
@@ -1160,6 +1163,19 @@ nxs_status nxs_inspect_ranges(nxs_context* ctx, int32_t* ranges_host, int64_t ca
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipEventSynchronize(ctx->done));
   HIP_TRY(hipMemcpy(ranges_host, src, 8 * ctx->last_tiles, hipMemcpyDeviceToHost));
+  return NXS_OK;
+}
+
+nxs_status nxs_inspect_slot_grads(nxs_context* ctx, float* slot_grads_host, int64_t capacity) {
+  if (!ctx || !slot_grads_host) return NXS_EINVAL;
+  if (ctx->last_bwd_slots < 0 || !ctx->gslot.p)
+    return fail(ctx, NXS_EINVAL, "no backward on this context");
+  if (capacity < 9 * ctx->last_bwd_slots) return fail(ctx, NXS_EINVAL, "capacity below 9 * slots");
+  if (ctx->last_bwd_slots == 0) return NXS_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipEventSynchronize(ctx->done));
+  HIP_TRY(hipMemcpy(slot_grads_host, ctx->gslot.p, 36 * ctx->last_bwd_slots,
+                    hipMemcpyDeviceToHost));
   return NXS_OK;
 }
 

@@ -31,7 +31,8 @@ SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_render_backwa
            "nxs_server_in_flight", "nxs_server_workspace_bytes", "nxs_server_last_error",
            "nxs_last_error",
            "nxs_set_timing", "nxs_inspect_stage_times", "nxs_inspect_counts",
-           "nxs_inspect_instances", "nxs_inspect_ranges", "nxs_inspect_projection"]
+           "nxs_inspect_instances", "nxs_inspect_ranges", "nxs_inspect_projection",
+           "nxs_inspect_slot_grads"]
 # entry points that do not return an nxs_status
 _NOT_STATUS = {"nxs_last_error": ctypes.c_char_p, "nxs_server_last_error": ctypes.c_char_p,
                "nxs_server_pending": c_int32, "nxs_server_in_flight": c_int32}
@@ -135,6 +136,7 @@ def lib():
         L.nxs_inspect_instances.argtypes = [c_void_p, c_void_p, c_void_p, c_int64]
         L.nxs_inspect_ranges.argtypes = [c_void_p, c_void_p, c_int64]
         L.nxs_inspect_projection.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_int64]
+        L.nxs_inspect_slot_grads.argtypes = [c_void_p, c_void_p, c_int64]
         for name in SYMBOLS:
             if name in _NOT_STATUS:
                 getattr(L, name).restype = _NOT_STATUS[name]
@@ -539,6 +541,13 @@ class Renderer:
         r = np.zeros(2 * max(t, 1), np.int32)
         self._check(self._L.nxs_inspect_ranges(self._ctx, r.ctypes.data, r.size))
         return r[:2 * t].reshape(t, 2)
+
+    def slot_grads(self, n, n_views):
+        """Per-slot sums of the last backward: [n_views, n, 9] float32 with
+        dLoss/d(aleph, u, v, A, B, C, r, g, b) (nxs_inspect_slot_grads)."""
+        out = np.zeros(9 * max(n * n_views, 1), np.float32)
+        self._check(self._L.nxs_inspect_slot_grads(self._ctx, out.ctypes.data, out.size))
+        return out[:9 * n * n_views].reshape(n_views, n, 9)
 
     def projection(self, view, n):
         d = np.zeros(max(n, 1), np.uint32)

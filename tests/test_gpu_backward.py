@@ -165,6 +165,49 @@ def test_backward_same_under_every_schedule(R, model):
             assert torch.allclose(v, ref[k], rtol=1e-4, atol=5e-4 * scale), (sched, k)
 
 
+@pytest.mark.parametrize("model,param", [(0, 0.0), (1, 0.0), (2, 0.0), (3, 0.0), (4, 0.8)])
+def test_slot_adjoints_match_the_appendix_recursions(R, model, param):
+    """The backward's per-slot sums dLoss/d(aleph, u, v, A, B, C, r, g, b)
+    (nxs_inspect_slot_grads) against the FP64 oracle's: per pixel the
+    appendix recursions for dLoss/dalpha_i and dLoss/dE_i (oracle.adjoint)
+    chained through alpha_i and summed per Gaussian (tests/adjoint_sums.py).
+    Random upstream gradients on colour and transmittance, zero at the
+    pixels the oracle flags; per element |got - want| <= 1e-3 |want| +
+    2e-4 max|want| of the field."""
+    from paper_2603_02887_amd import nxs
+    from tests import adjoint_sums
+    sc, cams = _scene()
+    op = O.MODELS[model] if model < 4 else O.Op("quadratic", param)
+    rng = np.random.default_rng(50 + model)
+    g = nxs.scene_to_device(sc)
+    R.render(g, cams, model=model, param=param, keep_state=True)
+    d_rgb, d_tr, want = [], [], []
+    for cam in cams:
+        amb = adjoint_sums.ambiguous(sc, cam, op)
+        w_rgb = rng.normal(size=(cam.height, cam.width, 3)).astype(np.float32)
+        w_T = rng.normal(size=(cam.height, cam.width)).astype(np.float32)
+        w_rgb[amb] = 0.0
+        w_T[amb] = 0.0
+        d_rgb.append(torch.from_numpy(w_rgb).cuda())
+        d_tr.append(torch.from_numpy(w_T).cuda())
+        want.append(adjoint_sums.slot_sums(sc, cam, op, w_rgb.astype(np.float64),
+                                           w_T.astype(np.float64)))
+    R.backward(g, d_rgb, d_tr)
+    got = R.slot_grads(sc.n, len(cams)).astype(np.float64)
+    want = np.stack(want)
+    worst = 0.0
+    for f in range(9):
+        scale = np.abs(want[..., f]).max()
+        assert scale > 0, f
+        tol = 1e-3 * np.abs(want[..., f]) + 2e-4 * scale
+        err = np.abs(got[..., f] - want[..., f])
+        worst = max(worst, float((err / tol).max()))
+        bad = np.argwhere(err > tol)
+        assert bad.size == 0, (f, bad[:4], got[..., f][tuple(bad[:4].T)],
+                               want[..., f][tuple(bad[:4].T)])
+    print("model", model, param, "worst/tol", worst)
+
+
 def test_autograd_survives_other_forwards(R):
     """Each differentiable render keeps its own forward state: forwards of
     other scenes and models on the same context between a render and its

@@ -54,3 +54,33 @@ def test_linear_adjoint_closed_form():
     da, dE = A.adjoint_sequence(al, O.LINEAR, E, [0.0], [1.0])
     assert np.allclose(da, [1 - 5, 2 - 5, 0, 0])
     assert np.allclose(dE[:, 0], [0.4, 0.4, 0.2, 0.0])
+
+
+@pytest.mark.parametrize("model", [0, 1, 3])
+def test_slot_sums_match_central_differences(model):
+    """tests/adjoint_sums.py (the per-slot sums the GPU backward is compared
+    with): its opacity and colour columns equal FP64 central differences of
+    the frozen-list oracle loss (tests/fd.py) in the opacity and in the DC
+    SH coefficient (which moves the emission by C0 = 1/(2 sqrt(pi)) per
+    unit where the emission is not clamped)."""
+    import synth
+    from tests import adjoint_sums, fd
+    sc = synth.random_scene(21, 60, log_scale=(-1.6, 0.3), logit=(1.5, 1.0), sh_degree=1)
+    cams = [synth.look_at_camera((0, 0, -3.2), width=40, height=32)]
+    F = fd.FrozenLoss(sc, cams, model, seed=4)
+    w_rgb, w_T = F.weights(0)
+    sums = adjoint_sums.slot_sums(sc, cams[0], model, w_rgb.astype(np.float64),
+                                  w_T.astype(np.float64))
+    params = fd.params_of(sc)
+    c0 = 0.28209479177387814
+    order = np.argsort(-np.abs(sums[:, 0]))[:6]        # the most-seen Gaussians
+    checked = 0
+    for i in order:
+        want = F.grad_element(params, "opacities", (int(i),), 1e-6)
+        assert abs(sums[i, 0] - want) <= 1e-6 * max(1.0, abs(want)), (i, sums[i, 0], want)
+        for ch in range(3):
+            want = F.grad_element(params, "sh", (int(i), 0, ch), 1e-6) / c0
+            if want != 0.0:             # (a clamped channel moves nothing)
+                assert abs(sums[i, 6 + ch] - want) <= 1e-6 * max(1.0, abs(want))
+                checked += 1
+    assert checked >= 6

@@ -199,7 +199,7 @@ def batched_views(R, torch, nxs, synth, steps, models=(0, 1, 2, 3)):
     for m in models:
         tune = R.autotune(g, cams, model=m, outputs=outs, reps=3)
         kw = {"tile": tune["tile"], "schedule": tune["schedule"],
-              "lds_batch": tune["lds_batch"]}
+              "lds_batch": tune["lds_batch"], "sort_order": tune["sort_order"]}
         t_tuned = timed(lambda: R.render(g, cams, model=m, outputs=outs, **kw))
         t_default = timed(lambda: R.render(g, cams, model=m, outputs=outs))
         t_per_view = timed(lambda: [R.render(g, [c], model=m, outputs=[o], **kw)
@@ -209,7 +209,8 @@ def batched_views(R, torch, nxs, synth, steps, models=(0, 1, 2, 3)):
                           "per_view_ms": t_per_view, "mpix_per_s": pix / t_tuned / 1e3,
                           "tuned": {"tile": "%dx%d" % tune["tile"],
                                     "schedule": tune["schedule"],
-                                    "lds_batch": tune["lds_batch"]},
+                                    "lds_batch": tune["lds_batch"],
+                                    "sort_order": tune["sort_order"]},
                           "speedup_vs_per_view": t_per_view / t_tuned}
     return {"workload": ("3,000,000 Gaussians (means from 256 clusters), SH degree 0, "
                          "16 views of uneven size on a radius-15 orbit"),
@@ -449,10 +450,12 @@ def main():
         cfg = {}
         for m in range(4):
             t = R.autotune(g, [cam], model=m, outputs=outs[m], reps=5)
-            cfg[m] = {"tile": t["tile"], "schedule": t["schedule"], "lds_batch": t["lds_batch"]}
+            cfg[m] = {"tile": t["tile"], "schedule": t["schedule"], "lds_batch": t["lds_batch"],
+                      "sort_order": t["sort_order"]}
     else:
         tw, th = (int(x) for x in args.tile.split("x"))
-        cfg = {m: {"tile": (tw, th), "schedule": "queue", "lds_batch": 64} for m in range(4)}
+        cfg = {m: {"tile": (tw, th), "schedule": "queue", "lds_batch": 64,
+                   "sort_order": "depth_first"} for m in range(4)}
     for m in range(4):
         R.render(g, [cam], model=m, outputs=outs[m], **cfg[m])
         R2.render(g, [cam], model=m, outputs=outs[m], **cfg[m])
@@ -543,7 +546,7 @@ def main():
             "stages_ms": st,
             "gpu_ms": sum(st.values()),
             "config": {"tile": "%dx%d" % cfg[m]["tile"], "schedule": cfg[m]["schedule"],
-                       "lds_batch": cfg[m]["lds_batch"]},
+                       "lds_batch": cfg[m]["lds_batch"], "sort_order": cfg[m]["sort_order"]},
         }
     # dominant kernel: the largest stage of any model
     all_stage = {(m, k): stage_mean[m][k] for m in range(4) for k in R.STAGES}

@@ -143,7 +143,24 @@ typedef struct {
   float instance_hint;    /* deferred renders: the tile instances the caller
                              expects (0 -> the context's last count); sizes the
                              tile sort's launches, never the result */
+  int32_t sort_order;     /* nxs_sort_order; 0 -> NXS_SORT_AUTO */
 } nxs_render_opts;
+
+/* How the per-tile front-to-back lists are built (bitwise the same lists,
+ * ordered by tile, float32 depth bits, Gaussian index):
+ *   DEPTH_FIRST  sort all projected Gaussians by depth, emit their tile
+ *                instances in that order, sort the instances stably by tile
+ *   TILE_FIRST   emit instances in Gaussian order, sort them stably by tile,
+ *                then sort each tile's list by depth in on-chip memory (a list
+ *                longer than 4,096 entries is sorted through device memory)
+ *   AUTO         TILE_FIRST when the expected instances per tile (the
+ *                caller's instance_hint, else the context's last count) are
+ *                at most 1,024 on average, else DEPTH_FIRST */
+typedef enum {
+  NXS_SORT_AUTO = 0,
+  NXS_SORT_DEPTH_FIRST = 1,
+  NXS_SORT_TILE_FIRST = 2
+} nxs_sort_order;
 
 /* opts.flags
  *   NXS_FLAG_DEFERRED  the forward does not wait on the host for the
@@ -305,13 +322,15 @@ typedef struct {
   int32_t tile_w, tile_h;
   int32_t schedule;       /* nxs_schedule */
   int32_t lds_batch;      /* list entries gathered per round (64, 128, 256) */
+  int32_t sort_order;     /* nxs_sort_order (DEPTH_FIRST or TILE_FIRST) */
   float ms;               /* median render time of the choice when measured */
 } nxs_tuning;
 
-/* Autotuner: the tile shape (8x8, 16x16, 32x8), composite schedule and LDS
- * batch (64, 128, 256 list entries per round) with the lowest median time
- * of a whole nxs_render_forward on this workload: every tile shape and
- * schedule at a batch of 64, then the other batches at the best of those.
+/* Autotuner: the tile shape (8x8, 16x16, 32x8), composite schedule, LDS
+ * batch (64, 128, 256 list entries per round) and sort order with the lowest
+ * median time of a whole nxs_render_forward on this workload: every tile
+ * shape and schedule at a batch of 64 and the automatic sort order, then
+ * the other batches, then both sort orders, at the best so far.
  * The result is cached per (GPU architecture, CU count, n, SH degree, model,
  * number and sizes of the views): first in the context, then, if cache_path
  * is not NULL, in that text file (one line per workload; read on a miss,
@@ -319,7 +338,7 @@ typedef struct {
  * every candidate is rendered once untimed and `reps` times (0 -> 5) timed
  * with events on `stream`, writing `out` (the outputs are those of the last
  * candidate) and synchronising the stream.  Other fields of `opts` are used
- * as given; its tile, schedule and lds_batch fields are ignored.  Errors as
+ * as given; its tile, schedule, lds_batch and sort_order fields are ignored.  Errors as
  * for nxs_render_forward; an unreadable or unwritable cache file is
  * ignored. */
 nxs_status nxs_autotune(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* cams,

@@ -25,6 +25,10 @@ static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace {
 
+// NXS_SORT_AUTO takes the tile-first order up to this many expected
+// instances per tile on average (0: never)
+constexpr double kAutoTileFirstPerTile = 0.0;
+
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mutex;
 char* g_scratch[kMaxDevices] = {};   // device address of `scratch`, per device
@@ -310,8 +314,8 @@ bool read_cache(const char* path, const std::string& key, nxs_tuning* t) {
   while (fgets(line, sizeof(line), f)) {
     char k[4000];
     nxs_tuning r{};
-    if (sscanf(line, "%3999s %d %d %d %d %f", k, &r.tile_w, &r.tile_h, &r.schedule,
-               &r.lds_batch, &r.ms) == 6 &&
+    if (sscanf(line, "%3999s %d %d %d %d %d %f", k, &r.tile_w, &r.tile_h, &r.schedule,
+               &r.lds_batch, &r.sort_order, &r.ms) == 7 &&
         key == k) {
       *t = r;   // the last line for a key wins
       found = true;
@@ -325,14 +329,14 @@ void append_cache(const char* path, const std::string& key, const nxs_tuning& t)
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d %d %d %.5f\n", key.c_str(), t.tile_w, t.tile_h, t.schedule, t.lds_batch,
-          (double)t.ms);
+  fprintf(f, "%s %d %d %d %d %d %.5f\n", key.c_str(), t.tile_w, t.tile_h, t.schedule,
+          t.lds_batch, t.sort_order, (double)t.ms);
   fclose(f);
 }
 
 // Everything a render needs, checked, before anything is launched.
 struct Checked {
-  int tw, th, sched, batch;
+  int tw, th, sched, batch, sort_order;
   float alpha_min, t_eps, param;
   int64_t total_tiles, S;
   bool deferred;
@@ -371,6 +375,9 @@ nxs_status check_args(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera
   c->batch = opts->lds_batch ? opts->lds_batch : 64;
   if (c->batch != 64 && c->batch != 128 && c->batch != 256)
     return fail(ctx, NXS_EINVAL, "lds_batch must be 0, 64, 128 or 256");
+  c->sort_order = opts->sort_order;
+  if (c->sort_order < NXS_SORT_AUTO || c->sort_order > NXS_SORT_TILE_FIRST)
+    return fail(ctx, NXS_EINVAL, "sort_order %d not supported (0..2)", opts->sort_order);
   c->alpha_min = opts->alpha_min > 0.0f ? opts->alpha_min : 1e-3f;
   if (!(c->alpha_min < 1.0f)) return fail(ctx, NXS_EINVAL, "alpha_min must be in (0, 1)");
   c->t_eps = opts->t_eps == 0.0f ? 1e-4f : opts->t_eps;
@@ -509,7 +516,15 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
   };
   ctx->ev_valid = false;
   HIP_TRY(mark(0));
-  const int depth_first = ctx->noalloc ? 0 : ctx->depth_first;
+  // the list order: the caller's, else by the expected instances per tile
+  // (the hint, else the context's last count; unknown: depth first)
+  bool tile_first = c.sort_order == NXS_SORT_TILE_FIRST;
+  if (c.sort_order == NXS_SORT_AUTO) {
+    const double expect = opts->instance_hint > 0.0f ? (double)opts->instance_hint
+                                                     : (double)ctx->m_hint;
+    tile_first = expect > 0.0 && expect <= kAutoTileFirstPerTile * (double)total_tiles;
+  }
+  const int depth_first = (ctx->noalloc || tile_first) ? 0 : ctx->depth_first;
   // (the fold writes the counters, or a deferred render's status, straight
   // into the context's pinned memory; the no-alloc call copies them)
   DeferCheck chk{~0ull, 0, nullptr, nullptr, ctx->noalloc ? nullptr : ctx->host_counters};
@@ -551,15 +566,21 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
                               P<uint32_t>(ctx->counts), proj.tinfo,
                               P<uint32_t>(ctx->nt_sorted), P<uint2>(ctx->rect_sorted), s);
   };
-  const int wd = depth_sort(depth_first);
-  uint32_t* sorted_slots = wd ? P<uint32_t>(ctx->slot_b) : P<uint32_t>(ctx->slot_a);
+  // (tile first: no depth sort; the slots are emitted in their own order)
+  uint32_t* sorted_slots = nullptr;
+  if (!tile_first) {
+    const int wd = depth_sort(depth_first);
+    sorted_slots = wd ? P<uint32_t>(ctx->slot_b) : P<uint32_t>(ctx->slot_a);
+  }
+  const uint32_t* nt_in = tile_first ? nullptr : P<uint32_t>(ctx->nt_sorted);
+  const uint2* rect_in = tile_first ? nullptr : P<uint2>(ctx->rect_sorted);
   HIP_TRY(mark(3));
-  // 2. emission in depth order, into the buffers as they are
-  launch_emit_scan(P<uint32_t>(ctx->nt_sorted), S, P<uint32_t>(ctx->scan_local),
+  // 2. emission (in depth order, or in slot order), into the buffers as they are
+  launch_emit_scan(nt_in, proj.tinfo, S, P<uint32_t>(ctx->scan_local),
                    P<uint32_t>(ctx->block_sums), s);
   const uint32_t cap32 = (uint32_t)instance_capacity(ctx);
   if (cap32 > 0)
-    launch_emit_write(sorted_slots, P<uint2>(ctx->rect_sorted), S, g->n, dviews,
+    launch_emit_write(sorted_slots, rect_in, proj.tinfo, S, g->n, dviews,
                       P<uint32_t>(ctx->scan_local), P<uint32_t>(ctx->block_sums), cap32,
                       P<uint32_t>(ctx->inst_tile), P<uint32_t>(ctx->inst_val), s);
   HIP_TRY(hipGetLastError());
@@ -577,7 +598,7 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     // the depth sort skipped pass 0 but this render's plan needs it: sort and
     // emit again below (the depth keys are intact)
     const bool pass0 = (ctx->host_counters->plan[0] & kPassActive) != 0;
-    const bool resort = S > 0 && depth_first == 1 && pass0;
+    const bool resort = !tile_first && S > 0 && depth_first == 1 && pass0;
     if (!ctx->noalloc) ctx->depth_first = pass0 ? 0 : 1;
     // what this render needs, visible through nxs_inspect_counts even if it fails
     ctx->last_m = (int64_t)M;
@@ -589,11 +610,11 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     if ((st = grow_instances(ctx, M, S, s))) return st;
     if (resort) {
       (void)depth_sort(0);
-      launch_emit_scan(P<uint32_t>(ctx->nt_sorted), S, P<uint32_t>(ctx->scan_local),
+      launch_emit_scan(nt_in, proj.tinfo, S, P<uint32_t>(ctx->scan_local),
                        P<uint32_t>(ctx->block_sums), s);
     }
     if (resort || M > cap32)   // emit (again) into the grown buffers
-      launch_emit_write(sorted_slots, P<uint2>(ctx->rect_sorted), S, g->n, dviews,
+      launch_emit_write(sorted_slots, rect_in, proj.tinfo, S, g->n, dviews,
                         P<uint32_t>(ctx->scan_local), P<uint32_t>(ctx->block_sums),
                         (uint32_t)M, P<uint32_t>(ctx->inst_tile), P<uint32_t>(ctx->inst_val),
                         s);
@@ -628,6 +649,13 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     HIP_TRY(mark(5));
     // 4. tile ranges
     launch_ranges(inst_tile, (int64_t)M, P<uint2>(ctx->ranges), s, dn, m_plan);
+    // 4a. tile first: each tile's list (in slot order) by depth, through the
+    //     buffer the tile sort left free
+    if (tile_first)
+      launch_tile_depth_sort(P<uint2>(ctx->ranges), total_tiles, P<uint32_t>(ctx->depth_key),
+                             dcount, inst_val,
+                             list_alt ? P<uint32_t>(ctx->inst_val) : P<uint32_t>(ctx->inst_val_alt),
+                             s);
   } else {
     HIP_TRY(mark(5));
   }
@@ -1013,31 +1041,48 @@ nxs_status nxs_autotune(nxs_context* ctx, const nxs_gaussians* g, const nxs_came
     return NXS_OK;
   };
   const int shapes[3][2] = {{8, 8}, {16, 16}, {32, 8}};
-  nxs_tuning best{0, 0, 0, 64, 0.0f};
+  nxs_tuning best{0, 0, 0, 64, NXS_SORT_AUTO, 0.0f};
   nxs_render_opts o = *opts;
   o.flags = 0;
-  // every tile shape and schedule at a batch of 64 list entries
-  for (int sh = 0; sh < 3 && st == NXS_OK; ++sh) {
-    for (int sc = NXS_SCHED_TILES; sc <= NXS_SCHED_PERSISTENT && st == NXS_OK; ++sc) {
-      o.tile_w = shapes[sh][0];
-      o.tile_h = shapes[sh][1];
-      o.schedule = sc;
-      o.lds_batch = 64;
-      float med = 0.0f;
-      st = measure(o, &med);
-      if (st == NXS_OK && (best.schedule == 0 || med < best.ms))
-        best = {o.tile_w, o.tile_h, sc, 64, med};
-    }
-  }
-  // then the larger batches at the best of those
-  for (int b = 128; b <= 256 && st == NXS_OK; b *= 2) {
-    o.tile_w = best.tile_w;
-    o.tile_h = best.tile_h;
-    o.schedule = best.schedule;
-    o.lds_batch = b;
+  auto apply = [&](const nxs_tuning& t) {
+    o.tile_w = t.tile_w;
+    o.tile_h = t.tile_h;
+    o.schedule = t.schedule;
+    o.lds_batch = t.lds_batch;
+    o.sort_order = t.sort_order;
+  };
+  auto consider = [&](const nxs_tuning& t) {
+    apply(t);
     float med = 0.0f;
     st = measure(o, &med);
-    if (st == NXS_OK && med < best.ms) best.lds_batch = b, best.ms = med;
+    if (st == NXS_OK && (best.schedule == 0 || med < best.ms)) {
+      best = t;
+      best.ms = med;
+    }
+  };
+  // every tile shape and schedule at a batch of 64 list entries
+  for (int sh = 0; sh < 3 && st == NXS_OK; ++sh)
+    for (int sc = NXS_SCHED_TILES; sc <= NXS_SCHED_PERSISTENT && st == NXS_OK; ++sc)
+      consider({shapes[sh][0], shapes[sh][1], sc, 64, NXS_SORT_AUTO, 0.0f});
+  // then the larger batches, then both sort orders, at the best so far
+  for (int b = 128; b <= 256 && st == NXS_OK; b *= 2) {
+    nxs_tuning t = best;
+    t.lds_batch = b;
+    consider(t);
+  }
+  // both sort orders explicitly (the automatic one is one of them); the
+  // result names the faster
+  float m_order[2] = {0.0f, 0.0f};
+  for (int k = 0; k < 2 && st == NXS_OK; ++k) {
+    nxs_tuning t = best;
+    t.sort_order = NXS_SORT_DEPTH_FIRST + k;
+    apply(t);
+    st = measure(o, &m_order[k]);
+  }
+  if (st == NXS_OK) {
+    const int k = m_order[0] <= m_order[1] ? 0 : 1;
+    best.sort_order = NXS_SORT_DEPTH_FIRST + k;
+    best.ms = std::min(best.ms, m_order[k]);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -150,17 +150,30 @@ int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
 
 // Exclusive scan of ntiles in sorted-slot order and emission of instances.
 size_t scan_blocks_size(int64_t n);
-// Exclusive scan of the depth-sorted tile counts, per block of 1,024 slots
-// (block totals in block_sums; scanned across blocks here only when there
-// are more blocks than the emission sums itself).
-void launch_emit_scan(const uint32_t* nt_sorted, int64_t n_slots, uint32_t* scan_local,
-                      uint32_t* block_sums, hipStream_t s);
-// Writes the instances of the depth-sorted slots (rectangles in rect_sorted);
-// instances at positions >= capacity are not written.
-void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted, int64_t n_slots,
-                       int32_t n_gauss, const ViewDev* views, const uint32_t* scan_local,
+// Exclusive scan of the depth-sorted tile counts (nt_sorted), or with
+// nt_sorted null of the counts in the tile records in slot order, per block
+// of 1,024 slots (block totals in block_sums; scanned across blocks here
+// only when there are more blocks than the emission sums itself).
+void launch_emit_scan(const uint32_t* nt_sorted, const uint4* tinfo, int64_t n_slots,
+                      uint32_t* scan_local, uint32_t* block_sums, hipStream_t s);
+// Writes the instances of the depth-sorted slots (rectangles in
+// rect_sorted), or with sorted_slots null of the slots in their own order
+// (rectangles in tinfo); instances at positions >= capacity are not written.
+void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted,
+                       const uint4* tinfo, int64_t n_slots, int32_t n_gauss,
+                       const ViewDev* views, const uint32_t* scan_local,
                        const uint32_t* block_sums, uint32_t capacity, uint32_t* inst_tile,
                        uint32_t* inst_val, hipStream_t s);
+
+// The tile-first order: after a stable sort by tile of instances emitted in
+// slot order, each tile's list (ranges) is sorted stably by its slots'
+// float32 depth bits (depth_key), in LDS up to kSegMax entries and through
+// `temp` (the same positions) beyond; the bits that vary come from the
+// projection's counters.  Nothing is done for a failed deferred render.
+constexpr int kSegMax = 4096;
+void launch_tile_depth_sort(const uint2* ranges, int64_t n_tiles, const uint32_t* depth_key,
+                            const Counters* counters, uint32_t* list, uint32_t* temp,
+                            hipStream_t s);
 
 
 

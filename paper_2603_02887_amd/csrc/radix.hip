@@ -329,6 +329,233 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
   }
 }
 
+// ------------------------------------------------- per-tile depth sort
+
+// One work-group sorts one tile's list (slots in slot order after the stable
+// tile sort) stably by the slots' depth bits: LSD passes of balanced digits
+// of up to kMaxDigitBits over the bits that vary among visible depths, each
+// pass ranked like a scatter chunk (wave ballots, per-wave digit counters,
+// a scan over the digits, two per thread).  Up to kSegMax entries live in
+// LDS for all passes; a longer list is sorted through global memory in
+// chunks of kSegMax, ping-ponging with `temp`.
+
+// Per-wave digit counters -> each wave's first position per digit: s_wave[w][d]
+// becomes base + (entries of digit d in waves < w) + (entries of digits < d),
+// base[d] = run[d] (0 for a single chunk); run[d] then advances by the
+// digit's count.  Threads t own digits 2t and 2t + 1.
+__device__ __forceinline__ void seg_digit_offsets(uint32_t (*s_wave)[kRBins], uint32_t* s_run,
+                                                  uint32_t* s_tmp, int nd, bool chained) {
+  const int t = threadIdx.x;
+  const int d0 = 2 * t, d1 = 2 * t + 1;
+  uint32_t c0 = 0, c1 = 0;
+  for (int w = 0; w < kRWaves; ++w) {
+    c0 += d0 < nd ? s_wave[w][d0] : 0u;
+    c1 += d1 < nd ? s_wave[w][d1] : 0u;
+  }
+  uint32_t all;
+  const uint32_t ex = rx_block_scan(c0 + c1, s_tmp, &all);   // (synchronises)
+  uint32_t r0 = chained ? s_run[d0] : ex, r1 = chained ? s_run[d1] : ex + c0;
+  for (int w = 0; w < kRWaves; ++w) {
+    if (d0 < nd) {
+      const uint32_t x = s_wave[w][d0];
+      s_wave[w][d0] = r0;
+      r0 += x;
+    }
+    if (d1 < nd) {
+      const uint32_t x = s_wave[w][d1];
+      s_wave[w][d1] = r1;
+      r1 += x;
+    }
+  }
+  if (chained) {
+    s_run[d0] = r0;
+    s_run[d1] = r1;
+  }
+}
+
+// Stable ranks of one chunk's digits within their wave; items of wave w,
+// round r, lane l are chunk entries w * 64 * ITEMS + r * 64 + l.
+template <int ITEMS>
+__device__ __forceinline__ void seg_rank(const uint32_t (&k)[ITEMS], int m, int shift, int width,
+                                         uint32_t (*s_wave)[kRBins], uint32_t (&dig)[ITEMS],
+                                         uint32_t (&rank)[ITEMS]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const uint32_t mask = (1u << width) - 1u;
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = wid * (64 * ITEMS) + r * 64 + lane;
+    const bool valid = li < m;
+    const uint32_t d = valid ? (k[r] >> shift) & mask : 0u;
+    const uint64_t peers = digit_peers(d, width, valid);
+    dig[r] = d;
+    rank[r] = 0;
+    if (valid) {
+      const uint32_t before = s_wave[wid][d];   // the same for every peer
+      const uint32_t pos = (uint32_t)__popcll(peers & lt);
+      rank[r] = before + pos;
+      if (pos == 0) s_wave[wid][d] = before + (uint32_t)__popcll(peers);
+    }
+  }
+}
+
+struct SegLds {
+  uint32_t key[kSegMax];
+  uint32_t val[kSegMax];
+  uint32_t wave[kRWaves][kRBins];
+  uint32_t run[kRBins];
+  uint32_t tmp[kRWaves];
+};
+
+// All passes in LDS (m <= 256 * ITEMS <= kSegMax).
+template <int ITEMS>
+__device__ void seg_sort_lds(uint32_t* list, int m, const uint32_t* __restrict__ depth_key,
+                             const int* shifts, const int* widths, int passes, SegLds& L) {
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  uint32_t k[ITEMS], v[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = wid * (64 * ITEMS) + r * 64 + lane;
+    v[r] = li < m ? list[li] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = wid * (64 * ITEMS) + r * 64 + lane;
+    k[r] = li < m ? depth_key[v[r]] : 0u;
+  }
+  for (int p = 0; p < passes; ++p) {
+    for (int i = t; i < kRWaves * kRBins; i += kRThreads) (&L.wave[0][0])[i] = 0u;
+    __syncthreads();
+    uint32_t dig[ITEMS], rank[ITEMS];
+    seg_rank<ITEMS>(k, m, shifts[p], widths[p], L.wave, dig, rank);
+    __syncthreads();
+    seg_digit_offsets(L.wave, L.run, L.tmp, 1 << widths[p], false);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const int li = wid * (64 * ITEMS) + r * 64 + lane;
+      if (li < m) {
+        const uint32_t dst = L.wave[wid][dig[r]] + rank[r];
+        L.key[dst] = k[r];
+        L.val[dst] = v[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const int li = wid * (64 * ITEMS) + r * 64 + lane;
+      if (li < m) {
+        k[r] = L.key[li];
+        v[r] = L.val[li];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = wid * (64 * ITEMS) + r * 64 + lane;
+    if (li < m) list[li] = v[r];
+  }
+}
+
+// A list longer than kSegMax: every pass counts the whole list, then ranks
+// and writes it chunk by chunk in order, between `list` and `temp`.
+__device__ void seg_sort_global(uint32_t* list, uint32_t* temp, int m,
+                                const uint32_t* __restrict__ depth_key, const int* shifts,
+                                const int* widths, int passes, SegLds& L) {
+  constexpr int ITEMS = kSegMax / kRThreads;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  uint32_t* src = list;
+  uint32_t* dst = temp;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = shifts[p], width = widths[p], nd = 1 << width;
+    const uint32_t mask = (1u << width) - 1u;
+    for (int i = t; i < kRBins; i += kRThreads) L.run[i] = 0u;
+    __syncthreads();
+    for (int i = t; i < m; i += kRThreads)
+      atomicAdd(&L.run[(depth_key[src[i]] >> shift) & mask], 1u);
+    __syncthreads();
+    {
+      // exclusive scan of the digit totals: the first position of each digit
+      const int d0 = 2 * t, d1 = 2 * t + 1;
+      const uint32_t c0 = d0 < nd ? L.run[d0] : 0u, c1 = d1 < nd ? L.run[d1] : 0u;
+      uint32_t all;
+      const uint32_t ex = rx_block_scan(c0 + c1, L.tmp, &all);
+      if (d0 < nd) L.run[d0] = ex;
+      if (d1 < nd) L.run[d1] = ex + c0;
+    }
+    __syncthreads();
+    for (int c = 0; c < m; c += kSegMax) {
+      const int cm = min(kSegMax, m - c);
+      uint32_t k[ITEMS], v[ITEMS];
+#pragma unroll
+      for (int r = 0; r < ITEMS; ++r) {
+        const int li = wid * (64 * ITEMS) + r * 64 + lane;
+        v[r] = li < cm ? src[c + li] : 0u;
+      }
+#pragma unroll
+      for (int r = 0; r < ITEMS; ++r) {
+        const int li = wid * (64 * ITEMS) + r * 64 + lane;
+        k[r] = li < cm ? depth_key[v[r]] : 0u;
+      }
+      for (int i = t; i < kRWaves * kRBins; i += kRThreads) (&L.wave[0][0])[i] = 0u;
+      __syncthreads();
+      uint32_t dig[ITEMS], rank[ITEMS];
+      seg_rank<ITEMS>(k, cm, shift, width, L.wave, dig, rank);
+      __syncthreads();
+      seg_digit_offsets(L.wave, L.run, L.tmp, nd, true);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < ITEMS; ++r) {
+        const int li = wid * (64 * ITEMS) + r * 64 + lane;
+        if (li < cm) dst[L.wave[wid][dig[r]] + rank[r]] = v[r];
+      }
+      __syncthreads();   // the counters are cleared for the next chunk
+    }
+    uint32_t* x = src;
+    src = dst;
+    dst = x;
+    __threadfence_block();   // this pass's writes before the next pass reads them
+    __syncthreads();
+  }
+  if (src != list) {
+    for (int i = t; i < m; i += kRThreads) list[i] = src[i];
+  }
+}
+
+__global__ __launch_bounds__(kRThreads) void tile_depth_sort_kernel(
+    const uint2* __restrict__ ranges, uint32_t n_tiles, const uint32_t* __restrict__ depth_key,
+    const Counters* __restrict__ cnt, uint32_t* __restrict__ list, uint32_t* __restrict__ temp) {
+  __shared__ SegLds L;
+  const uint32_t tile = blockIdx.x;
+  if (tile >= n_tiles || cnt->fail) return;
+  const uint2 rg = ranges[tile];
+  const int m = (int)(rg.y - rg.x);
+  if (m <= 1) return;
+  const uint32_t diff = cnt->dmin <= cnt->dmax ? (cnt->dmin ^ cnt->dmax) : 0u;
+  const int nbits = diff ? 32 - __clz((int)diff) : 0;
+  if (nbits == 0) return;   // equal depths: slot order is the order
+  const int passes = (nbits + kMaxDigitBits - 1) / kMaxDigitBits;
+  int shifts[4], widths[4], sh = 0;
+  for (int p = 0; p < passes; ++p) {
+    widths[p] = (nbits - sh + (passes - p) - 1) / (passes - p);
+    shifts[p] = sh;
+    sh += widths[p];
+  }
+  uint32_t* seg = list + rg.x;
+  if (m <= 256)
+    seg_sort_lds<1>(seg, m, depth_key, shifts, widths, passes, L);
+  else if (m <= 512)
+    seg_sort_lds<2>(seg, m, depth_key, shifts, widths, passes, L);
+  else if (m <= 1024)
+    seg_sort_lds<4>(seg, m, depth_key, shifts, widths, passes, L);
+  else if (m <= 2048)
+    seg_sort_lds<8>(seg, m, depth_key, shifts, widths, passes, L);
+  else if (m <= kSegMax)
+    seg_sort_lds<16>(seg, m, depth_key, shifts, widths, passes, L);
+  else
+    seg_sort_global(seg, temp + rg.x, m, depth_key, shifts, widths, passes, L);
+}
+
 }  // namespace
 
 size_t radix_counts_words(int64_t n) {
@@ -413,6 +640,14 @@ int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
   if (n <= 0) return 1;
   return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, first_pass, kPlanPasses, nullptr,
                     nullptr, plan, counts, tinfo, nt_out, rect_out, s, nullptr, n);
+}
+
+void launch_tile_depth_sort(const uint2* ranges, int64_t n_tiles, const uint32_t* depth_key,
+                            const Counters* counters, uint32_t* list, uint32_t* temp,
+                            hipStream_t s) {
+  if (n_tiles <= 0) return;
+  hipLaunchKernelGGL(tile_depth_sort_kernel, dim3((unsigned)n_tiles), dim3(kRThreads), 0, s,
+                     ranges, (uint32_t)n_tiles, depth_key, counters, list, temp);
 }
 
 }  // namespace nxs

@@ -60,7 +60,7 @@ class RenderOpts(ctypes.Structure):
     _fields_ = [("model", c_int32), ("background", c_float * 3), ("alpha_min", c_float),
                 ("t_eps", c_float), ("tile_w", c_int32), ("tile_h", c_int32),
                 ("lds_batch", c_int32), ("param", c_float), ("flags", c_int32),
-                ("schedule", c_int32), ("instance_hint", c_float)]
+                ("schedule", c_int32), ("instance_hint", c_float), ("sort_order", c_int32)]
 
 
 FLAG_DEFERRED = 1
@@ -68,7 +68,10 @@ FLAG_DEFERRED = 1
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("schedule", c_int32),
-                ("lds_batch", c_int32), ("ms", c_float)]
+                ("lds_batch", c_int32), ("sort_order", c_int32), ("ms", c_float)]
+
+
+SORT_ORDERS = {"auto": 0, "depth_first": 1, "tile_first": 2}
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p, c_void_p)
@@ -217,11 +220,14 @@ def _make_image(o):
 
 
 def _make_opts(model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0, t_eps=0.0, tile=(16, 16),
-               lds_batch=0, param=0.0, schedule=0, deferred=False, instance_hint=0.0):
+               lds_batch=0, param=0.0, schedule=0, deferred=False, instance_hint=0.0,
+               sort_order=0):
     if isinstance(model, str):
         model = MODEL_IDS[model]
     if isinstance(schedule, str):
         schedule = SCHEDULES[schedule]
+    if isinstance(sort_order, str):
+        sort_order = SORT_ORDERS[sort_order]
     opts = RenderOpts()
     opts.model = int(model)
     for k in range(3):
@@ -233,6 +239,7 @@ def _make_opts(model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0, t_eps=0.0, ti
     opts.flags = FLAG_DEFERRED if deferred else 0
     opts.schedule = int(schedule)
     opts.instance_hint = float(instance_hint)
+    opts.sort_order = int(sort_order)
     return opts
 
 
@@ -382,28 +389,31 @@ class Renderer:
             raise NxsError(st, msg.decode() if msg else "")
 
     def _marshal(self, g, cams, model, background, alpha_min, t_eps, tile, lds_batch,
-                 outputs, overdraw, param, schedule, deferred):
+                 outputs, overdraw, param, schedule, deferred, sort_order=0,
+                 instance_hint=0.0):
         gs = _make_gaussians(g)
         V = len(cams)
         carr = (Camera * V)(*[make_camera(c) for c in cams])
         outputs = _make_outputs(self.device, cams, outputs, overdraw)
         imgs = (Image * V)(*[_make_image(o) for o in outputs])
         opts = _make_opts(model, background, alpha_min, t_eps, tile, lds_batch, param,
-                          schedule, deferred)
+                          schedule, deferred, instance_hint, sort_order)
         return gs, carr, V, imgs, opts, outputs
 
     def render(self, g, cams, model=0, background=(0.0, 0.0, 0.0), alpha_min=0.0,
                t_eps=0.0, tile=(16, 16), lds_batch=0, outputs=None, overdraw=True,
-               stream=None, param=0.0, keep_state=False, schedule=0, deferred=False):
+               stream=None, param=0.0, keep_state=False, schedule=0, deferred=False,
+               sort_order=0, instance_hint=0.0):
         """Render the Gaussians `g` (dict of GPU tensors, see scene_to_device) in
         every camera of `cams`.  Returns a list of dicts {rgb [H,W,3], trans [H,W],
         overdraw [H,W] int32} (or fills `outputs`, a list of such dicts).
         keep_state: keep a FwdState for backward() in self.last_state.
         deferred: do not wait for the instance count (NXS_FLAG_DEFERRED); check
-        the outcome with status()."""
+        the outcome with status().  sort_order: "auto", "depth_first" or
+        "tile_first" (nxs_sort_order)."""
         gs, carr, V, imgs, opts, outputs = self._marshal(
             g, cams, model, background, alpha_min, t_eps, tile, lds_batch, outputs, overdraw,
-            param, schedule, deferred)
+            param, schedule, deferred, sort_order, instance_hint)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         h = c_void_p()
@@ -460,8 +470,9 @@ class Renderer:
                                   int(reps), byref(res), c_void_p(stream.cuda_stream))
         self._check(st)
         name = {v: k for k, v in SCHEDULES.items()}[res.schedule]
+        order = {v: k for k, v in SORT_ORDERS.items()}[res.sort_order]
         return {"tile": (res.tile_w, res.tile_h), "schedule": name,
-                "lds_batch": int(res.lds_batch), "ms": float(res.ms)}
+                "lds_batch": int(res.lds_batch), "sort_order": order, "ms": float(res.ms)}
 
     def backward(self, g, dL_drgb, dL_dtrans=None, stream=None, state=None):
         """Gradients of the Gaussians (dict of tensors shaped like `g`) from the
@@ -637,22 +648,6 @@ class Server:
             done += self.step(wait=True)
         return done
 
-    def render_noalloc(self, g, cams, outputs, model=0, background=(0.0, 0.0, 0.0),
-                       alpha_min=0.0, t_eps=0.0, tile=(16, 16), lds_batch=0, param=0.0,
-                       schedule=0, stream=None):
-        """The same render through nxs_render_forward_noalloc: the library
-        allocates nothing (its workspace is a fixed 64 MiB scratch per
-        device); `outputs` must be given (a list of dicts as render returns)."""
-        gs, carr, V, imgs, opts, outputs = self._marshal(
-            g, cams, model, background, alpha_min, t_eps, tile, lds_batch, outputs, True,
-            param, schedule, False)
-        if stream is None:
-            stream = torch.cuda.current_stream(self.device)
-        self._check(self._L.nxs_render_forward_noalloc(self._ctx, byref(gs), carr, V,
-                                                       byref(opts), imgs,
-                                                       c_void_p(stream.cuda_stream)))
-        return outputs
-
     def workspace_bytes(self):
         b = ctypes.c_size_t()
         self._check(self._L.nxs_server_workspace_bytes(self._s, byref(b)))
@@ -661,8 +656,9 @@ class Server:
 
 class RenderFunction(torch.autograd.Function):
     """Differentiable render: (means, scales, quats, opacities, sh) -> per view
-    (rgb [H,W,3], trans [H,W]).  The backward is the library's path replay; it
-    must run before the next forward on the same Renderer."""
+    (rgb [H,W,3], trans [H,W]).  The backward is the library's path replay
+    over the forward state this render kept (other renders may run between
+    the two); the state is released after the backward."""
 
     @staticmethod
     def forward(ctx, renderer, cams, opts, means, scales, quats, opacities, sh):

@@ -115,6 +115,50 @@ def test_depth_sort_plan_changes_between_renders():
         r.close()
 
 
+@pytest.mark.parametrize("order", ["depth_first", "tile_first"])
+@pytest.mark.parametrize("near,far", [(2.1, 15.0), (0.4, 60.0)])
+def test_sort_orders(R, order, near, far):
+    """Both ways of building the lists (a global depth sort before binning,
+    or binning in Gaussian order and a per-tile depth sort after the tile
+    sort) give the same keys, bit-exact, under three-digit (25 bits) and
+    four-digit (31 bits) depth plans, and the same images, bitwise."""
+    sc = _depth_range_scene(near, far)
+    cam = synth.look_at_camera((0, 0, -3), width=320, height=240)
+    other = "tile_first" if order == "depth_first" else "depth_first"
+    for model in (0, 3):
+        out = _render(R, sc, [cam], model, sort_order=order)
+        parity.compare_keys(R, sc, [cam])
+        ref = _render(R, sc, [cam], model, sort_order=other)
+        for k in ("rgb", "trans", "overdraw"):
+            assert torch.equal(out[0][k], ref[0][k]), k
+        parity.compare_view(out[0], sc, cam, model, pixels=parity.sample_pixels(cam, 1500))
+
+
+def test_tile_first_long_lists(R):
+    """Tiles whose lists exceed the 4,096 entries sorted on chip are sorted
+    through device memory in chunks: 12,000 Gaussians, every one covering the
+    whole 48x40 view, at depths from 0.4 to 60 (a four-pass depth sort):
+    nine lists of 12,000 entries, bit-exact against the oracle and bitwise
+    the depth-first render."""
+    rng = np.random.default_rng(17)
+    sc = synth.random_scene(17, 12_000, sh_degree=0, log_scale=(0.5, 0.2), logit=(-2.0, 1.0))
+    z = rng.uniform(0.4, 60.0, sc.n)
+    sc.means[:, 0] = rng.uniform(-0.05, 0.05, sc.n) * z
+    sc.means[:, 1] = rng.uniform(-0.05, 0.05, sc.n) * z
+    sc.means[:, 2] = z - 3.0
+    cam = synth.look_at_camera((0, 0, -3), width=48, height=40)
+    for model in (0, 1):
+        out = _render(R, sc, [cam], model, sort_order="tile_first")
+        n = parity.compare_keys(R, sc, [cam])
+        assert n > 8 * 4096
+        ranges = R.ranges()
+        assert int((ranges[:, 1] - ranges[:, 0]).max()) > 4096
+        ref = _render(R, sc, [cam], model, sort_order="depth_first")
+        for k in ("rgb", "trans", "overdraw"):
+            assert torch.equal(out[0][k], ref[0][k]), k
+        parity.compare_view(out[0], sc, cam, model, pixels=parity.sample_pixels(cam, 300))
+
+
 @pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
 def test_emission_of_large_footprints(R, tile):
     """Splats from a few pixels up to the whole 256x192 view: 1,024

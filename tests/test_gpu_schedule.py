@@ -46,21 +46,24 @@ def _same(a, b):
 @pytest.mark.parametrize("tile", [(8, 8), (16, 16), (32, 8)])
 @pytest.mark.parametrize("model", [0, 2, 6])
 def test_schedules_bitwise_equal(R, tile, model):
-    """Every schedule and LDS batch renders bitwise what one work-group per
-    tile with batches of 64 list entries renders."""
+    """Every schedule, LDS batch and sort order renders bitwise what one
+    work-group per tile with batches of 64 list entries renders after a depth
+    sort."""
     from paper_2603_02887_amd import nxs
     sc, cams = _uneven_views()
     g = nxs.scene_to_device(sc)
     kw = {"tile": tile, "model": model, "param": 0.5 if model == 6 else 0.0}
-    ref = R.render(g, cams, schedule="tiles", **kw)
+    ref = R.render(g, cams, schedule="tiles", sort_order="depth_first", **kw)
     for sched in ("tiles", "blocks", "queue", "persistent"):
         for batch in (64, 128, 256):        # list entries gathered per round
-            if sched == "tiles" and batch == 64:
-                continue
-            out = R.render(g, cams, schedule=sched, lds_batch=batch, **kw)
-            torch.cuda.synchronize()
-            for a, b in zip(ref, out):
-                _same(a, b)
+            for order in ("depth_first", "tile_first"):
+                if sched == "tiles" and batch == 64 and order == "depth_first":
+                    continue
+                out = R.render(g, cams, schedule=sched, lds_batch=batch, sort_order=order,
+                               **kw)
+                torch.cuda.synchronize()
+                for a, b in zip(ref, out):
+                    _same(a, b)
 
 
 @pytest.mark.parametrize("sched", ["tiles", "blocks", "queue", "persistent"])
@@ -124,9 +127,11 @@ def test_autotune_and_cache(R, tmp_path):
     assert t["schedule"] in ("tiles", "blocks", "queue", "persistent") and t["ms"] > 0
     lines = path.read_text().splitlines()
     assert t["lds_batch"] in (64, 128, 256)
-    assert len(lines) == 1 and lines[0].split()[1:5] == [str(t["tile"][0]), str(t["tile"][1]),
+    assert t["sort_order"] in ("depth_first", "tile_first")
+    assert len(lines) == 1 and lines[0].split()[1:6] == [str(t["tile"][0]), str(t["tile"][1]),
                                                          str(nxs.SCHEDULES[t["schedule"]]),
-                                                         str(t["lds_batch"])]
+                                                         str(t["lds_batch"]),
+                                                         str(nxs.SORT_ORDERS[t["sort_order"]])]
     # a fresh context finds it in the file and renders nothing
     R2 = nxs.Renderer(0)
     outs = [{"rgb": torch.full((c.height, c.width, 3), -7.0, device="cuda"),
@@ -135,7 +140,7 @@ def test_autotune_and_cache(R, tmp_path):
     t2 = R2.autotune(g, cams, model=0, cache_path=path, outputs=outs)
     torch.cuda.synchronize()
     assert t2["tile"] == t["tile"] and t2["schedule"] == t["schedule"]
-    assert t2["lds_batch"] == t["lds_batch"]
+    assert t2["lds_batch"] == t["lds_batch"] and t2["sort_order"] == t["sort_order"]
     assert all(torch.all(o["rgb"] == -7.0) for o in outs)
     # another model is another key
     R2.autotune(g, cams, model=1, cache_path=path, reps=1)
@@ -144,7 +149,7 @@ def test_autotune_and_cache(R, tmp_path):
     # the tuned choice renders what the tile schedule renders at that tile shape
     ref = R.render(g, cams, model=0, tile=t["tile"], schedule="tiles")
     out = R.render(g, cams, model=0, tile=t["tile"], schedule=t["schedule"],
-                   lds_batch=t["lds_batch"])
+                   lds_batch=t["lds_batch"], sort_order=t["sort_order"])
     torch.cuda.synchronize()
     for a, b in zip(ref, out):
         _same(a, b)

@@ -522,6 +522,150 @@ __device__ void seg_sort_global(uint32_t* list, uint32_t* temp, int m,
   }
 }
 
+// Lists of up to kSegWaveMax entries are sorted by one wave with no
+// work-group barrier: its items stay in registers (ITEMS per lane, entry
+// r * 64 + lane), each pass ranks them with ballots against per-digit
+// counters in LDS, a wave-wide scan turns the counters into each digit's
+// first position, and the items go to their positions through LDS.  The
+// wave's LDS accesses complete in order, so a fence that keeps the compiler
+// from moving them is all the ordering a pass needs.
+constexpr int kSegWaveMax = 1024;
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct SegWaveLds {
+  uint32_t key[kSegWaveMax];
+  uint32_t val[kSegWaveMax];
+  uint32_t cnt[kRBins];
+};
+
+template <int ITEMS>
+__device__ void seg_sort_wave(uint32_t* list, int m, const uint32_t* __restrict__ depth_key,
+                              const int* shifts, const int* widths, int passes,
+                              SegWaveLds& L) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint32_t k[ITEMS], v[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) v[r] = r * 64 + lane < m ? list[r * 64 + lane] : 0u;
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) k[r] = r * 64 + lane < m ? depth_key[v[r]] : 0u;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = shifts[p], width = widths[p], nd = 1 << width;
+    const uint32_t mask = (1u << width) - 1u;
+    for (int d = lane; d < nd; d += 64) L.cnt[d] = 0u;
+    wave_lds_fence();
+    uint32_t dig[ITEMS], rank[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const bool valid = r * 64 + lane < m;
+      const uint32_t d = valid ? (k[r] >> shift) & mask : 0u;
+      const uint64_t peers = digit_peers(d, width, valid);
+      dig[r] = d;
+      rank[r] = 0;
+      uint32_t before = 0;
+      if (valid) before = L.cnt[d];   // the same for every peer
+      wave_lds_fence();
+      const uint32_t pos = (uint32_t)__popcll(peers & lt);
+      if (valid) {
+        rank[r] = before + pos;
+        if (pos == 0) L.cnt[d] = before + (uint32_t)__popcll(peers);
+      }
+      wave_lds_fence();
+    }
+    // each digit's first position: lane l scans digits [l * per, (l + 1) * per)
+    {
+      const int per = nd / 64 > 0 ? nd / 64 : 1;
+      const int d0 = lane * per;
+      uint32_t local = 0;
+      for (int i = 0; i < per; ++i)
+        if (d0 + i < nd) local += L.cnt[d0 + i];
+      uint32_t incl = local;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      uint32_t run = incl - local;
+      wave_lds_fence();
+      for (int i = 0; i < per; ++i)
+        if (d0 + i < nd) {
+          const uint32_t c = L.cnt[d0 + i];
+          L.cnt[d0 + i] = run;
+          run += c;
+        }
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+      if (r * 64 + lane < m) {
+        const uint32_t dst = L.cnt[dig[r]] + rank[r];
+        L.key[dst] = k[r];
+        L.val[dst] = v[r];
+      }
+    wave_lds_fence();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+      if (r * 64 + lane < m) {
+        k[r] = L.key[r * 64 + lane];
+        v[r] = L.val[r * 64 + lane];
+      }
+    wave_lds_fence();
+  }
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r)
+    if (r * 64 + lane < m) list[r * 64 + lane] = v[r];
+}
+
+// The digits of the per-tile sort: balanced digits of up to kMaxDigitBits
+// over the bits that vary among the render's visible depths.  Returns the
+// number of passes (0: equal depths).
+__device__ __forceinline__ int seg_plan(const Counters* __restrict__ cnt, int* shifts,
+                                        int* widths) {
+  const uint32_t diff = cnt->dmin <= cnt->dmax ? (cnt->dmin ^ cnt->dmax) : 0u;
+  const int nbits = diff ? 32 - __clz((int)diff) : 0;
+  if (nbits == 0) return 0;
+  const int passes = (nbits + kMaxDigitBits - 1) / kMaxDigitBits;
+  int sh = 0;
+  for (int p = 0; p < passes; ++p) {
+    widths[p] = (nbits - sh + (passes - p) - 1) / (passes - p);
+    shifts[p] = sh;
+    sh += widths[p];
+  }
+  return passes;
+}
+
+// One wave per tile of at most kSegWaveMax entries (longer lists: skipped,
+// for tile_depth_sort_kernel).
+__global__ __launch_bounds__(64) void tile_depth_sort_wave_kernel(
+    const uint2* __restrict__ ranges, uint32_t n_tiles, const uint32_t* __restrict__ depth_key,
+    const Counters* __restrict__ cnt, uint32_t* __restrict__ list) {
+  __shared__ SegWaveLds L;
+  const uint32_t tile = blockIdx.x;
+  if (tile >= n_tiles || cnt->fail) return;
+  const uint2 rg = ranges[tile];
+  const int m = (int)(rg.y - rg.x);
+  if (m <= 1 || m > kSegWaveMax) return;
+  int shifts[4], widths[4];
+  const int passes = seg_plan(cnt, shifts, widths);
+  if (passes == 0) return;   // equal depths: slot order is the order
+  uint32_t* seg = list + rg.x;
+  if (m <= 64)
+    seg_sort_wave<1>(seg, m, depth_key, shifts, widths, passes, L);
+  else if (m <= 128)
+    seg_sort_wave<2>(seg, m, depth_key, shifts, widths, passes, L);
+  else if (m <= 256)
+    seg_sort_wave<4>(seg, m, depth_key, shifts, widths, passes, L);
+  else if (m <= 512)
+    seg_sort_wave<8>(seg, m, depth_key, shifts, widths, passes, L);
+  else
+    seg_sort_wave<16>(seg, m, depth_key, shifts, widths, passes, L);
+}
+
 __global__ __launch_bounds__(kRThreads) void tile_depth_sort_kernel(
     const uint2* __restrict__ ranges, uint32_t n_tiles, const uint32_t* __restrict__ depth_key,
     const Counters* __restrict__ cnt, uint32_t* __restrict__ list, uint32_t* __restrict__ temp) {
@@ -530,25 +674,12 @@ __global__ __launch_bounds__(kRThreads) void tile_depth_sort_kernel(
   if (tile >= n_tiles || cnt->fail) return;
   const uint2 rg = ranges[tile];
   const int m = (int)(rg.y - rg.x);
-  if (m <= 1) return;
-  const uint32_t diff = cnt->dmin <= cnt->dmax ? (cnt->dmin ^ cnt->dmax) : 0u;
-  const int nbits = diff ? 32 - __clz((int)diff) : 0;
-  if (nbits == 0) return;   // equal depths: slot order is the order
-  const int passes = (nbits + kMaxDigitBits - 1) / kMaxDigitBits;
-  int shifts[4], widths[4], sh = 0;
-  for (int p = 0; p < passes; ++p) {
-    widths[p] = (nbits - sh + (passes - p) - 1) / (passes - p);
-    shifts[p] = sh;
-    sh += widths[p];
-  }
+  if (m <= kSegWaveMax) return;   // (tile_depth_sort_wave_kernel's)
+  int shifts[4], widths[4];
+  const int passes = seg_plan(cnt, shifts, widths);
+  if (passes == 0) return;   // equal depths: slot order is the order
   uint32_t* seg = list + rg.x;
-  if (m <= 256)
-    seg_sort_lds<1>(seg, m, depth_key, shifts, widths, passes, L);
-  else if (m <= 512)
-    seg_sort_lds<2>(seg, m, depth_key, shifts, widths, passes, L);
-  else if (m <= 1024)
-    seg_sort_lds<4>(seg, m, depth_key, shifts, widths, passes, L);
-  else if (m <= 2048)
+  if (m <= 2048)
     seg_sort_lds<8>(seg, m, depth_key, shifts, widths, passes, L);
   else if (m <= kSegMax)
     seg_sort_lds<16>(seg, m, depth_key, shifts, widths, passes, L);
@@ -646,6 +777,8 @@ void launch_tile_depth_sort(const uint2* ranges, int64_t n_tiles, const uint32_t
                             const Counters* counters, uint32_t* list, uint32_t* temp,
                             hipStream_t s) {
   if (n_tiles <= 0) return;
+  hipLaunchKernelGGL(tile_depth_sort_wave_kernel, dim3((unsigned)n_tiles), dim3(64), 0, s,
+                     ranges, (uint32_t)n_tiles, depth_key, counters, list);
   hipLaunchKernelGGL(tile_depth_sort_kernel, dim3((unsigned)n_tiles), dim3(kRThreads), 0, s,
                      ranges, (uint32_t)n_tiles, depth_key, counters, list, temp);
 }

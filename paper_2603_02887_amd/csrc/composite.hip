@@ -99,7 +99,8 @@ __device__ __forceinline__ void composite_block(
   // columns that still hold a running pixel (act: the wave's running lanes).
   // Slot indices are read two rounds ahead and records one round ahead.
   constexpr uint32_t kRound = 64u * NB;
-  uint64_t act = __builtin_amdgcn_ballot_w64(!op.stopped(t_eps));
+  bool running = !op.stopped(t_eps);
+  uint64_t act = __builtin_amdgcn_ballot_w64(running);
   // (an empty tile fetches nothing: its range is [0, 0) or [x, x))
   StageSlot slots[NB];
   StageFetch fetched[NB];
@@ -116,6 +117,34 @@ __device__ __forceinline__ void composite_block(
       slots[k] = stage_slot(inst_val, (uint64_t)rg.x + kRound + 64u * k, rg.y, lane);
     }
   }
+  auto composite_one = [&](const float4* r) {
+    const float4 q0 = r[0], q1 = r[1];
+    const float c[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, r[2].x};
+    const float dx = fx - c[0], dy = fy - c[1];
+    const float e = fmaf(dx, fmaf(c[2], dx, c[3] * dy), fmaf(c[4] * dy, dy, c[5]));
+    const bool valid = (e >= amin) && running;
+    const float a = valid ? __builtin_amdgcn_exp2f(e) : 0.0f;
+    const float s_before = op.S;
+    const float p = op.step(a, param, t_eps);
+    if (kSat) {
+      // the saturating splat's emission, and the sums over the splats before it
+      const bool sat_now = op.S >= 1.0f && s_before < 1.0f;
+      ek0 = sat_now ? c[6] : ek0;
+      ek1 = sat_now ? c[7] : ek1;
+      ek2 = sat_now ? c[8] : ek2;
+      const float a_pre = op.S >= 1.0f ? 0.0f : a;
+      u0 = fmaf(c[6], a_pre, u0);
+      u1 = fmaf(c[7], a_pre, u1);
+      u2 = fmaf(c[8], a_pre, u2);
+      tau_s += a_pre;
+    }
+    L0 = fmaf(c[6], p, L0);
+    L1 = fmaf(c[7], p, L1);
+    L2 = fmaf(c[8], p, L2);
+    od += valid ? 1 : 0;
+    running = !op.stopped(t_eps);
+    act = __builtin_amdgcn_ballot_w64(running);
+  };
   for (uint32_t base = rg.x; base < rg.y && act != 0; base += kRound) {
     const StageBlock sbr = stage_shrink(sb, act);
     uint32_t n = 0;
@@ -125,33 +154,20 @@ __device__ __forceinline__ void composite_block(
       fetched[k] = stage_records(slots[k], rec);                                 // next round
       slots[k] = stage_slot(inst_val, (uint64_t)base + 2 * kRound + 64u * k, rg.y, lane);
     }
-    for (const float4 *r = wlds, *r_end = wlds + 3 * n; r != r_end; r += 3) {
-      const float4 q0 = r[0], q1 = r[1];
-      const float c[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, r[2].x};
-      const float dx = fx - c[0], dy = fy - c[1];
-      const float e = fmaf(dx, fmaf(c[2], dx, c[3] * dy), fmaf(c[4] * dy, dy, c[5]));
-      const bool valid = (e >= amin) && !op.stopped(t_eps);
-      const float a = valid ? __builtin_amdgcn_exp2f(e) : 0.0f;
-      const float s_before = op.S;
-      const float p = op.step(a, param, t_eps);
-      if (kSat) {
-        // the saturating splat's emission, and the sums over the splats before it
-        const bool sat_now = op.S >= 1.0f && s_before < 1.0f;
-        ek0 = sat_now ? c[6] : ek0;
-        ek1 = sat_now ? c[7] : ek1;
-        ek2 = sat_now ? c[8] : ek2;
-        const float a_pre = op.S >= 1.0f ? 0.0f : a;
-        u0 = fmaf(c[6], a_pre, u0);
-        u1 = fmaf(c[7], a_pre, u1);
-        u2 = fmaf(c[8], a_pre, u2);
-        tau_s += a_pre;
-      }
-      L0 = fmaf(c[6], p, L0);
-      L1 = fmaf(c[7], p, L1);
-      L2 = fmaf(c[8], p, L2);
-      od += valid ? 1 : 0;
-      act = __builtin_amdgcn_ballot_w64(!op.stopped(t_eps));
-      if (act == 0) break;
+    // two staged splats per trip: an odd count (below 64 NB, so the stage has
+    // room) is padded with a splat whose exponent is -inf at every pixel
+    // (alpha 0, no emission); a pair's second splat after every pixel stopped
+    // composites a = 0 as well
+    n = __builtin_amdgcn_readfirstlane(n);
+    if (n & 1u) {
+      if (lane < 3)
+        wlds[3 * n + lane] = lane == 1 ? make_float4(0.0f, -__builtin_inff(), 0.0f, 0.0f)
+                                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      wave_lds_order();
+    }
+    for (uint32_t i = 0; i < n && act != 0; i += 2) {
+      composite_one(wlds + 3 * i);
+      composite_one(wlds + 3 * i + 3);
     }
   }
   if (inside) {

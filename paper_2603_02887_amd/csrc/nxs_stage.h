@@ -98,66 +98,93 @@ __device__ __forceinline__ StageFetch stage_records(const StageSlot& s,
   return f;
 }
 
-// Forms the tile-relative centre ((hi - corner) is exact, then + lo) and
-// keeps the splat if its alpha >= alpha_min box reaches the block and,
-// exactly, if the largest exponent over the rectangle spanned by the block's
-// pixel centres reaches log2(alpha_min) (2e-3 of margin in log2 units, so
-// float32 rounding can keep a block that no pixel needs but never drop one
-// that some pixel needs: a kept splat that reaches no pixel composites
-// nothing).  The kept records are written, in list order, to `wlds`;
-// returns how many.
+// A fetched splat's footprint in the frame of its tile: the tile-relative
+// centre ((hi - corner) is exact, then + lo), the half-extents of its
+// alpha >= alpha_min box (two fp16, rounded up) and the exponent terms of
+// Q = -(e - lo) >= 0, with the bound qlim: e >= log2(alpha_min) <=> Q <= qlim
+// (plus 2e-3 of margin in log2 units, so that float32 rounding can keep a
+// splat that no pixel needs but never drop one that some pixel needs).
+struct SplatGeom {
+  float du, dv, rx, ry;
+  float qa, qb, qc, qlim;
+};
+
+__device__ __forceinline__ SplatGeom splat_geom(const StageFetch& f, float cu, float cv,
+                                                float amin) {
+  SplatGeom g;
+  g.du = (f.r0.x - cu) + f.r0.y;
+  g.dv = (f.r0.z - cv) + f.r0.w;
+  const uint32_t hx = __float_as_uint(f.r2.w);
+  g.rx = __half2float(__ushort_as_half((unsigned short)(hx & 0xFFFFu)));
+  g.ry = __half2float(__ushort_as_half((unsigned short)(hx >> 16)));
+  g.qa = -f.r1.x;
+  g.qb = -f.r1.y;
+  g.qc = -f.r1.z;
+  g.qlim = f.r1.w - amin + 2e-3f;
+  return g;
+}
+
+// Whether the splat can reach alpha_min somewhere on the rectangle
+// [x0, x1] x [y0, y1] of pixel centres (tile relative; x0 > x1 or y0 > y1:
+// an empty rectangle, never reached): its box must overlap the rectangle and
+// the smallest Q over the rectangle must be within qlim.
+__device__ __forceinline__ bool reach_rect(const SplatGeom& g, float x0, float x1, float y0,
+                                           float y1) {
+  if (g.dv - g.ry > y1 || g.dv + g.ry < y0 || g.du - g.rx > x1 || g.du + g.rx < x0) return false;
+  const float xlo = x0 - g.du, xhi = x1 - g.du;   // dx range over the rectangle
+  const float ylo = y0 - g.dv, yhi = y1 - g.dv;   // dy range over the rectangle
+  float qmin = 0.0f;
+  const bool face_x = !(xlo <= 0.0f && xhi >= 0.0f);   // the centre is left or right
+  const bool face_y = !(ylo <= 0.0f && yhi >= 0.0f);   // the centre is above or below
+  if (face_x || face_y) {
+    // the centre is outside: Q is convex, so its minimum over the rectangle
+    // lies on an edge that faces the centre (at most one in x and one in y),
+    // at the edge's own minimiser clamped to the edge (hardware reciprocals:
+    // a relative error of ~1e-7 in the minimiser moves Q far less than the
+    // margin)
+    const float qa = g.qa, qb = g.qb, qc = g.qc;
+    const float ia = 0.5f * __builtin_amdgcn_rcpf(qa), ic = 0.5f * __builtin_amdgcn_rcpf(qc);
+    const float X = xlo > 0.0f ? xlo : xhi;
+    const float y = fminf(fmaxf(-qb * X * ic, ylo), yhi);
+    const float qx = X * (qa * X + qb * y) + qc * y * y;
+    const float Y = ylo > 0.0f ? ylo : yhi;
+    const float x = fminf(fmaxf(-qb * Y * ia, xlo), xhi);
+    const float qy = Y * (qc * Y + qb * x) + qa * x * x;
+    qmin = fminf(face_x ? qx : __builtin_inff(), face_y ? qy : __builtin_inff());
+  }
+  return qmin <= g.qlim;
+}
+
+// LDS operations of one wave complete in order: the reads that follow see the
+// wave's earlier writes without a barrier; this keeps the compiler from
+// moving them
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Keeps the splats whose footprint reaches the wave's block (reach_rect over
+// the block's running rows and columns) and writes their records, in list
+// order, to `wlds`; returns how many.
 __device__ __forceinline__ uint32_t stage_batch(const StageFetch& f, const StageBlock& b,
                                                 float4* wlds) {
   bool keep = false;
-  float du = 0.f, dv = 0.f;
-  const float4 r0 = f.r0, r1 = f.r1, r2 = f.r2;
+  SplatGeom g{};
   if (f.valid) {
-    du = (r0.x - b.cu) + r0.y;
-    dv = (r0.z - b.cv) + r0.w;
-    // half-extents of the alpha >= alpha_min box, two fp16 rounded up
-    const uint32_t hx = __float_as_uint(r2.w);
-    const float rx = __half2float(__ushort_as_half((unsigned short)(hx & 0xFFFFu)));
-    const float ry = __half2float(__ushort_as_half((unsigned short)(hx >> 16)));
-    if (!(dv - ry > b.y1 || dv + ry < b.y0 || du - rx > b.x1 || du + rx < b.x0)) {
-      const float qa = -r1.x, qb = -r1.y, qc = -r1.z;   // Q = -(e - lo) >= 0
-      const float qlim = r1.w - b.amin + 2e-3f;         // e >= amin <=> Q <= qlim
-      const float xlo = b.x0 - du, xhi = b.x1 - du;     // dx range over the block
-      const float ylo = b.y0 - dv, yhi = b.y1 - dv;     // dy range over the block
-      float qmin = 0.0f;
-      const bool face_x = !(xlo <= 0.0f && xhi >= 0.0f);   // the centre is left or right
-      const bool face_y = !(ylo <= 0.0f && yhi >= 0.0f);   // the centre is above or below
-      if (face_x || face_y) {
-        // the centre is outside: Q is convex, so its minimum over the
-        // rectangle lies on an edge that faces the centre (at most one in x
-        // and one in y), at the edge's own minimiser clamped to the edge
-        // (hardware reciprocals: a relative error of ~1e-7 in the minimiser
-        // moves Q far less than the margin)
-        const float ia = 0.5f * __builtin_amdgcn_rcpf(qa), ic = 0.5f * __builtin_amdgcn_rcpf(qc);
-        const float X = xlo > 0.0f ? xlo : xhi;
-        const float y = fminf(fmaxf(-qb * X * ic, ylo), yhi);
-        const float qx = X * (qa * X + qb * y) + qc * y * y;
-        const float Y = ylo > 0.0f ? ylo : yhi;
-        const float x = fminf(fmaxf(-qb * Y * ia, xlo), xhi);
-        const float qy = Y * (qc * Y + qb * x) + qa * x * x;
-        qmin = fminf(face_x ? qx : __builtin_inff(), face_y ? qy : __builtin_inff());
-      }
-      keep = qmin <= qlim;
-    }
+    g = splat_geom(f, b.cu, b.cv, b.amin);
+    keep = reach_rect(g, b.x0, b.x1, b.y0, b.y1);
   }
   const uint64_t sel = __builtin_amdgcn_ballot_w64(keep);
   if (keep) {
     // position among the kept lanes below this one
     const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
         (uint32_t)(sel >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)sel, 0u));
-    wlds[3 * pos + 0] = make_float4(du, dv, r1.x, r1.y);
-    wlds[3 * pos + 1] = make_float4(r1.z, r1.w, r2.x, r2.y);
-    wlds[3 * pos + 2] = make_float4(r2.z, __uint_as_float(f.slot), 0.0f, 0.0f);
+    wlds[3 * pos + 0] = make_float4(g.du, g.dv, f.r1.x, f.r1.y);
+    wlds[3 * pos + 1] = make_float4(f.r1.z, f.r1.w, f.r2.x, f.r2.y);
+    wlds[3 * pos + 2] = make_float4(f.r2.z, __uint_as_float(f.slot), 0.0f, 0.0f);
   }
-  // LDS operations of one wave complete in order: the reads that follow see
-  // these writes without a barrier; this keeps the compiler from moving them
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_lds_order();
   return (uint32_t)__builtin_popcountll(sel);
 }
 

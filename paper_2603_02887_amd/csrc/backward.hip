@@ -16,11 +16,13 @@
 //   every model   dL/dE_i = p_i.
 // The final transmittance rides along as a fourth channel with emission 0 and
 // background 1, so dLoss/dtrans needs no separate code.  Each splat's
-// per-pixel contributions to d(opacity, centre, conic, colour) are summed
-// over the wave and added once per wave into its slot's gradient.
+// per-pixel moments alpha dL/dalpha (1, dx, dy, dx^2, dx dy, dy^2) and
+// p (dL/dL_rgb) are summed over the wave and added once per wave into its
+// slot (dx, dy: the pixel centre relative to the splat's).
 //
-// project_bwd: one thread per Gaussian chains the slot gradients of every
-// view through the conic inverse, the EWA covariance, the perspective
+// project_bwd: one thread per Gaussian turns each view's slot moments into
+// dL/d(opacity, centre, conic, colour) (written back to the slot) and chains
+// them through the conic inverse, the EWA covariance, the perspective
 // Jacobian, the rotation and scales, and the SH emission.
 #include "nxs_internal.h"
 #include "nxs_ops.h"
@@ -47,14 +49,6 @@ __device__ __forceinline__ float row_total(float x) {
   x = dpp_add<0x141>(x);   // row_half_mirror
   x = dpp_add<0x140>(x);   // row_mirror
   return x;
-}
-
-// LDS operations of one wave complete in order; this keeps the compiler from
-// moving the wave's LDS accesses across it.
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int MODEL, int TW, int TH>
@@ -181,24 +175,20 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
         }
       }
       done = done || stops;
-      // alpha = aleph exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2
-      const float A = (-2.0f * kLn2) * r[2], B = -kLn2 * r[3], C = (-2.0f * kLn2) * r[4];
-      const float dq = -0.5f * a * dalpha;
-      const float d_op = dalpha * __builtin_amdgcn_exp2f(e - r[5]);
-      const float d_u = -2.0f * dq * (A * dx + B * dy);
-      const float d_v = -2.0f * dq * (B * dx + C * dy);
-      const float d_A = dq * dx * dx;
-      const float d_B = 2.0f * dq * dx * dy;
-      const float d_C = dq * dy * dy;
-      const float d_r = p * g0;
-      const float d_g = p * g1;
-      const float d_b = p * g2;
+      // alpha = aleph exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2: with
+      // da = alpha dL/dalpha a pixel adds dL/daleph = da / aleph,
+      // dL/du = da (A dx + B dy), dL/dv = da (B dx + C dy) and
+      // dL/d(A, B, C) = -da (dx^2 / 2, dx dy, dy^2 / 2), all linear in the
+      // moments da (1, dx, dy, dx^2, dx dy, dy^2): the wave sums those, and
+      // project_bwd applies the slot's aleph and conic once per slot
+      const float da = dalpha * a;
+      const float dax = da * dx, day = da * dy;
       if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
         // the wave's sums: row totals, written to LDS by each row's first
         // lane, then lane f adds field f of the 4 rows and issues the atomic
-        const float t[9] = {row_total(d_op), row_total(d_u), row_total(d_v),
-                            row_total(d_A),  row_total(d_B), row_total(d_C),
-                            row_total(d_r),  row_total(d_g), row_total(d_b)};
+        const float t[9] = {row_total(da),       row_total(dax),      row_total(day),
+                            row_total(dax * dx), row_total(dax * dy), row_total(day * dy),
+                            row_total(p * g0),   row_total(p * g1),   row_total(p * g2)};
         if ((lane & 15) == 0) {
           float4* rr = reinterpret_cast<float4*>(wred + 12 * (lane >> 4));
           rr[0] = make_float4(t[0], t[1], t[2], t[3]);
@@ -268,7 +258,7 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, float* 
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     GaussDev g, const ViewDev* __restrict__ views, int n_views,
-    const float* __restrict__ gslot, GaussGradDev out) {
+    float* __restrict__ gslot, GaussGradDev out) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= g.n) return;
@@ -298,11 +288,12 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
       for (int b = 0; b < 3; ++b) M[a][b] = Rq[a][b] * s[b];
     float gRq[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     for (int vi = 0; vi < n_views; ++vi) {
-      const float* gsl = gslot + 9 * ((size_t)vi * g.n + i);
-      const float g_op = gsl[0], g_u = gsl[1], g_v = gsl[2], gA = gsl[3], gB = gsl[4],
-                  gC = gsl[5];
+      float* gsl = gslot + 9 * ((size_t)vi * g.n + i);
+      // the slot's moments: alpha dL/dalpha (1, dx, dy, dx^2, dx dy, dy^2), colour
+      const float m0 = gsl[0], m1 = gsl[1], m2 = gsl[2], m3 = gsl[3], m4 = gsl[4],
+                  m5 = gsl[5];
       const float g_rgb[3] = {gsl[6], gsl[7], gsl[8]};
-      if (g_op == 0.f && g_u == 0.f && g_v == 0.f && gA == 0.f && gB == 0.f && gC == 0.f &&
+      if (m0 == 0.f && m1 == 0.f && m2 == 0.f && m3 == 0.f && m4 == 0.f && m5 == 0.f &&
           g_rgb[0] == 0.f && g_rgb[1] == 0.f && g_rgb[2] == 0.f)
         continue;   // no pixel of this view saw the Gaussian
       const ViewDev& v = views[vi];
@@ -331,6 +322,16 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
       const float idet = 1.0f / (a * cc - b * b);
       // conic K = Sigma2D^-1; dL/dSigma = -K G_K K with G_K = [[gA, gB/2], [gB/2, gC]]
       const float K00 = cc * idet, K01 = -b * idet, K11 = a * idet;
+      // dL/d(opacity, u, v) and dL/d(A, B, C) of the conic q = A dx^2 + 2 B dx dy + C dy^2
+      const float g_op = m0 / g.opac[i];
+      const float g_u = K00 * m1 + K01 * m2, g_v = K01 * m1 + K11 * m2;
+      const float gA = -0.5f * m3, gB = -m4, gC = -0.5f * m5;
+      gsl[0] = g_op;
+      gsl[1] = g_u;
+      gsl[2] = g_v;
+      gsl[3] = gA;
+      gsl[4] = gB;
+      gsl[5] = gC;
       const float G00 = gA, G01 = 0.5f * gB, G11 = gC;
       // (K G K) entries
       const float KG00 = K00 * G00 + K01 * G01, KG01 = K00 * G01 + K01 * G11;
@@ -483,7 +484,7 @@ void launch_composite_bwd(int model, int tile_w, int tile_h, int64_t n_tiles,
 }
 
 void launch_project_bwd(const GaussDev& g, const ViewDev* views, int n_views,
-                        const float* gslot, const GaussGradDev& out, hipStream_t s) {
+                        float* gslot, const GaussGradDev& out, hipStream_t s) {
   if (g.n <= 0) return;
   dim3 grid((g.n + kBlock - 1) / kBlock);
   switch (g.sh_degree) {

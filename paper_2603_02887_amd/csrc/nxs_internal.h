@@ -227,9 +227,11 @@ void launch_composite_order(const CompositeLaunch& L, hipStream_t s);
 void launch_composite(int model, const CompositeLaunch& L, const CompositeParams& p,
                       float4* pstate, hipStream_t s);
 
-// Path-replay backward of the composite (models 0..4): per-slot gradients
-// gslot[9 * slot + f] for f = dLoss/d(opacity, u, v, conic A, B, C, r, g, b),
-// accumulated with atomics (the caller zeroes gslot).  `order`: the forward's
+// Path-replay backward of the composite (models 0..4): per-slot moments
+// gslot[9 * slot + f], f = sums over the slot's pixels of alpha dLoss/dalpha
+// times (1, dx, dy, dx^2, dx dy, dy^2) and of p dLoss/dL (r, g, b),
+// accumulated with atomics (the caller zeroes gslot; launch_project_bwd turns
+// them into gradients).  `order`: the forward's
 // tile order (longest lists first) to walk the tiles in, or null.
 void launch_composite_bwd(int model, int tile_w, int tile_h, int64_t n_tiles,
                           const ViewDev* views, int n_views, const uint2* ranges,
@@ -246,7 +248,9 @@ struct GaussGradDev {
   float* opac;
   float* sh;
 };
+// gslot holds each slot's moments from the composite's backward on entry and
+// its dL/d(opacity, u, v, A, B, C, r, g, b) on return.
 void launch_project_bwd(const GaussDev& g, const ViewDev* views, int n_views,
-                        const float* gslot, const GaussGradDev& out, hipStream_t s);
+                        float* gslot, const GaussGradDev& out, hipStream_t s);
 
 }  // namespace nxs

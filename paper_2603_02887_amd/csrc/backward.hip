@@ -43,13 +43,19 @@ __device__ __forceinline__ float dpp_add(float x) {
   const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true);
   return x + __int_as_float(y);
 }
-__device__ __forceinline__ float row_total(float x) {
+__device__ __forceinline__ float quad_total(float x) {
   x = dpp_add<0xB1>(x);    // quad_perm [1,0,3,2]
   x = dpp_add<0x4E>(x);    // quad_perm [2,3,0,1]
-  x = dpp_add<0x141>(x);   // row_half_mirror
-  x = dpp_add<0x140>(x);   // row_mirror
   return x;
 }
+
+// Per-wave sums of the 9 per-pixel fields of up to kRedSplats splats at a
+// time: each splat's fields are summed over lane quads (two DPP adds each)
+// and the quads' first lanes write the 16 quad sums of field f to row
+// 9 j + f of the wave's table (j: the splat's place among the pending ones);
+// a flush has lane r add row r's 16 sums and issue its atomic.
+constexpr int kRedSplats = 4;                    // 36 rows: one per lane
+constexpr int kRedF4 = 9 * kRedSplats * 16 / 4;  // float4 per wave
 
 template <int MODEL, int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
@@ -58,7 +64,8 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
     const float4* __restrict__ pstate, float* __restrict__ gslot, uint32_t n_tiles,
     uint32_t per_xcd, const uint32_t* __restrict__ order) {
   __shared__ float4 stage[(TW / 8) * (TH / 8) * kStageF4];
-  __shared__ float4 rsum[(TW / 8) * (TH / 8) * 12];   // per wave: 4 rows x 9 sums
+  __shared__ float4 rsum[(TW / 8) * (TH / 8) * kRedF4];   // per wave: pending quad sums
+  __shared__ uint32_t rslot[(TW / 8) * (TH / 8) * kRedSplats];   // and their slots
   // the forward's order (longest tile lists first) when it made one, else
   // each XCD a contiguous band of tiles
   const uint32_t w = order ? blockIdx.x : xcd_banded(blockIdx.x, per_xcd);
@@ -85,7 +92,8 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
   const float fx = (float)lx + 0.5f, fy = (float)ly + 0.5f;
   const StageBlock sb = stage_block<TW>(tx, ty, TH, wid, prm.log2_alpha_min);
   float4* wlds = stage + wid * kStageF4;
-  float* wred = reinterpret_cast<float*>(rsum + wid * 12);
+  float* wred = reinterpret_cast<float*>(rsum + wid * kRedF4);
+  uint32_t* wslot = rslot + wid * kRedSplats;
   const uint2 rg = ranges[tile];
   const float amin = prm.log2_alpha_min;
   const float t_eps = prm.t_eps;
@@ -129,6 +137,21 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
     fetched = stage_records(slots, rec);
     slots = stage_slot(inst_val, (uint64_t)rg.x + 64, rg.y, lane);
   }
+  // the pending splats' sums: lane r < 9 pend adds row r and issues its atomic
+  uint32_t pend = 0;
+  auto flush = [&]() {
+    wave_lds_order();
+    if (lane < 9 * (int)pend) {
+      const float4* q = reinterpret_cast<const float4*>(wred + 16 * lane);
+      const float4 a0 = q[0], a1 = q[1], a2 = q[2], a3 = q[3];
+      const float sum = ((a0.x + a0.y) + (a0.z + a0.w)) + ((a1.x + a1.y) + (a1.z + a1.w)) +
+                        (((a2.x + a2.y) + (a2.z + a2.w)) + ((a3.x + a3.y) + (a3.z + a3.w)));
+      const int j = (lane * 57) >> 9;   // lane / 9 for lane < 64
+      atomicAdd(gslot + 9 * (size_t)wslot[j] + (lane - 9 * j), sum);
+    }
+    wave_lds_order();
+    pend = 0;
+  };
   for (uint32_t base = rg.x; base < rg.y && act != 0; base += 64) {
     const uint32_t n = stage_batch(fetched, stage_shrink(sb, act), wlds);
     fetched = stage_records(slots, rec);                              // batch base + 64
@@ -184,27 +207,21 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
       const float da = dalpha * a;
       const float dax = da * dx, day = da * dy;
       if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
-        // the wave's sums: row totals, written to LDS by each row's first
-        // lane, then lane f adds field f of the 4 rows and issues the atomic
-        const float t[9] = {row_total(da),       row_total(dax),      row_total(day),
-                            row_total(dax * dx), row_total(dax * dy), row_total(day * dy),
-                            row_total(p * g0),   row_total(p * g1),   row_total(p * g2)};
-        if ((lane & 15) == 0) {
-          float4* rr = reinterpret_cast<float4*>(wred + 12 * (lane >> 4));
-          rr[0] = make_float4(t[0], t[1], t[2], t[3]);
-          rr[1] = make_float4(t[4], t[5], t[6], t[7]);
-          rr[2].x = t[8];
+        const float t[9] = {quad_total(da),       quad_total(dax),      quad_total(day),
+                            quad_total(dax * dx), quad_total(dax * dy), quad_total(day * dy),
+                            quad_total(p * g0),   quad_total(p * g1),   quad_total(p * g2)};
+        if ((lane & 3) == 0) {
+          float* row = wred + 9 * 16 * pend + (lane >> 2);
+#pragma unroll
+          for (int f = 0; f < 9; ++f) row[16 * f] = t[f];
         }
-        wave_lds_order();
-        if (lane < 9) {
-          const float sum = (wred[lane] + wred[12 + lane]) + (wred[24 + lane] + wred[36 + lane]);
-          atomicAdd(gslot + 9 * (size_t)__float_as_uint(r[9]) + lane, sum);
-        }
-        wave_lds_order();
+        if (lane == 0) wslot[pend] = __float_as_uint(r[9]);
+        if (++pend == kRedSplats) flush();
       }
       act = __builtin_amdgcn_ballot_w64(!done);
     }
   }
+  if (pend) flush();
 }
 
 // ------------------------------------------------------------ projection

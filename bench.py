@@ -12,12 +12,15 @@ tile shape, composite schedule and LDS batch the library's autotuner picks
 for each model.  The scene is uploaded to HBM before the timed region.
 
 The timed steps enqueue their renders back to back without waiting
-(deferred renders, whose instance count is checked on the device),
-alternating between two library contexts, each on a stream of its own: one
-render's short, latency-bound sort kernels then overlap the other's
-projection or composite.  `value` is the frame's pixels over that time.
-The same steps on one context and one stream, deferred and waiting, are
-reported beside it, as is per-model throughput.  Latency is measured
+(deferred renders, whose instance count is checked on the device), taking
+two or three library contexts in turn, each on a stream of its own: one
+render's short, latency-bound sort kernels then overlap another's projection
+or composite.  Each is timed with the tuner's configuration and with the
+tile schedule in its place where the tuner chose the longest-first queue
+(another render in flight fills the composite's tail, so the queue's two
+order kernels may not pay for themselves); the fastest is `value`.  `value` is the frame's pixels
+over that time.  The same steps on one context and one stream, deferred and
+waiting, are reported beside it, as is per-model throughput.  Latency is measured
 separately, one render at a time, waiting for each: p50/p99 per model, with
 per-stage GPU times from hipEvents the library records on the render stream
 (the composite's time there, alone on the GPU, is the one the roofline uses).
@@ -442,8 +445,10 @@ def main():
     dev = torch.device("cuda", 0)
     g = nxs.scene_to_device(scene, dev)
     R = nxs.Renderer(0)
-    R2 = nxs.Renderer(0)
+    ctxs = [R, nxs.Renderer(0), nxs.Renderer(0)]   # up to three renders in flight
     outs = {m: R.render(g, [cam], model=m) for m in range(4)}
+    # (each further context writes outputs of its own)
+    ctx_outs = [outs] + [{m: c.render(g, [cam], model=m) for m in range(4)} for c in ctxs[1:]]
     torch.cuda.synchronize()
     # the render configuration per model
     if args.tile == "auto":
@@ -457,23 +462,44 @@ def main():
         cfg = {m: {"tile": (tw, th), "schedule": "queue", "lds_batch": 64,
                    "sort_order": "depth_first"} for m in range(4)}
     for m in range(4):
-        R.render(g, [cam], model=m, outputs=outs[m], **cfg[m])
-        R2.render(g, [cam], model=m, outputs=outs[m], **cfg[m])
+        for c, o in zip(ctxs, ctx_outs):
+            c.render(g, [cam], model=m, outputs=o[m], **cfg[m])
     torch.cuda.synchronize()
     od_sum = {m: int(outs[m][0]["overdraw"].sum().item()) for m in range(4)}
     n_inst, _ = R.counts()
 
-    def render(m, ctx=R, deferred=True):
-        ctx.render(g, [cam], model=m, outputs=outs[m], deferred=deferred, **cfg[m])
+    def render(m, ci=0, deferred=True, conf=None):
+        ctxs[ci].render(g, [cam], model=m, outputs=ctx_outs[ci][m], deferred=deferred,
+                        **(conf or cfg)[m])
+
+    # The tuner measures one render at a time; with several renders in flight
+    # another render fills the composite's tail, so the longest-first queue
+    # (two latency-bound order kernels per render) can lose to the tile
+    # schedule: both sets are timed and the faster is reported
+    cfg_sets = {"tuned": cfg}
+    no_order = {m: dict(c, schedule="tiles") if c["schedule"] in ("queue", "persistent") else c
+                for m, c in cfg.items()}
+    if no_order != cfg:
+        cfg_sets["tuned_tile_schedule"] = no_order
+    for conf in cfg_sets.values():
+        for m in range(4):
+            for c, o in zip(ctxs, ctx_outs):
+                c.render(g, [cam], model=m, outputs=o[m], **conf[m])
+    torch.cuda.synchronize()
 
     # Throughput (the timed steps): each step enqueues one render per model back
     # to back, as a pipelined caller would (each model writes its own outputs)
-    streams = [torch.cuda.Stream(dev), torch.cuda.Stream(dev)]
+    streams = [torch.cuda.Stream(dev) for _ in ctxs]
+    turn = [0]
 
-    def step_two():          # alternating between two contexts on two streams
-        for m in range(4):
-            with torch.cuda.stream(streams[m % 2]):
-                render(m, (R, R2)[m % 2])
+    def step_multi(k, conf):   # k contexts on k streams, taken in turn
+        def step():
+            for m in range(4):
+                ci = turn[0] % k
+                turn[0] += 1
+                with torch.cuda.stream(streams[ci]):
+                    render(m, ci, conf=conf)
+        return step
 
     def step_one():          # one context, one stream, deferred
         for m in range(4):
@@ -494,19 +520,26 @@ def main():
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             try:                       # every deferred render fitted its context
-                R.status()
-                R2.status()
+                for c in ctxs:
+                    c.status()
                 return dt
             except nxs.NxsError:       # (the contexts have grown: time it again)
                 continue
         raise RuntimeError("deferred renders kept outgrowing their contexts")
 
-    modes = {"two_contexts_deferred": timed(step_two),
-             "one_context_deferred": timed(step_one),
-             "one_context_waiting": timed(step_wait)}
+    modes, mode_cfg = {}, {}
+    for name, conf in cfg_sets.items():
+        for k, kname in ((3, "three"), (2, "two")):
+            key = f"{kname}_contexts_deferred" + ("" if name == "tuned" else "_" + name)
+            modes[key] = timed(step_multi(k, conf))
+            mode_cfg[key] = conf
+    modes["one_context_deferred"] = timed(step_one)
+    modes["one_context_waiting"] = timed(step_wait)
     best_mode = min(modes, key=modes.get)
     total = modes[best_mode]
-    R2.close()
+    best_cfg = mode_cfg.get(best_mode, cfg)
+    for c in ctxs[1:]:
+        c.close()
     # per model, the same back-to-back throughput (one context, deferred)
     thr = {}
     for m in range(4):
@@ -604,7 +637,10 @@ def main():
                                 "anisotropic clusters, SH degree 3, one 1920x1080 camera; "
                                 "one step = one render per transmittance model"),
                    "gaussians": scene.n, "width": W, "height": H,
-                   "render_config": {MODELS[m]: per_model[MODELS[m]]["config"]
+                   "render_config": {MODELS[m]: {"tile": "%dx%d" % best_cfg[m]["tile"],
+                                                 "schedule": best_cfg[m]["schedule"],
+                                                 "lds_batch": best_cfg[m]["lds_batch"],
+                                                 "sort_order": best_cfg[m]["sort_order"]}
                                      for m in range(4)},
                    "in_flight": best_mode, "instances": n_inst, "models": list(MODELS)},
         "throughput_modes_mpix_per_s": {k: W * H * renders / v / 1e6 for k, v in modes.items()},

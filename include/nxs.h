@@ -323,20 +323,23 @@ typedef struct {
   int32_t schedule;       /* nxs_schedule */
   int32_t lds_batch;      /* list entries gathered per round (64, 128, 256) */
   int32_t sort_order;     /* nxs_sort_order (DEPTH_FIRST or TILE_FIRST) */
-  float ms;               /* median render time of the choice when measured */
+  float ms;               /* GPU time per render of the choice when measured */
 } nxs_tuning;
 
 /* Autotuner: the tile shape (8x8, 16x16, 32x8), composite schedule, LDS
  * batch (64, 128, 256 list entries per round) and sort order with the lowest
- * median time of a whole nxs_render_forward on this workload: every tile
+ * GPU time of a whole nxs_render_forward on this workload: every tile
  * shape and schedule at a batch of 64 and the automatic sort order, then
- * the other batches, then both sort orders, at the best so far.
+ * the other batches, then both sort orders, at the best so far.  A
+ * candidate's time is that of `reps` deferred renders enqueued back to back
+ * (no host wait inside the timed span) over their number.
  * The result is cached per (GPU architecture, CU count, n, SH degree, model,
  * number and sizes of the views): first in the context, then, if cache_path
  * is not NULL, in that text file (one line per workload; read on a miss,
  * appended after a sweep).  On a cache hit nothing is rendered.  On a miss
- * every candidate is rendered once untimed and `reps` times (0 -> 5) timed
- * with events on `stream`, writing `out` (the outputs are those of the last
+ * every candidate is rendered once untimed (waiting) and `reps` times
+ * (0 -> 5) timed with events on `stream` (deferred; timed again if they
+ * outgrew the context), writing `out` (the outputs are those of the last
  * candidate) and synchronising the stream.  Other fields of `opts` are used
  * as given; its tile, schedule, lds_batch and sort_order fields are ignored.  Errors as
  * for nxs_render_forward; an unreadable or unwritable cache file is

@@ -1023,22 +1023,35 @@ nxs_status nxs_autotune(nxs_context* ctx, const nxs_gaussians* g, const nxs_came
     return fail(ctx, NXS_EHIP, "hipEventCreate failed");
   }
   nxs_status st = NXS_OK;
-  // median time of `reps` renders after one untimed
-  auto measure = [&](const nxs_render_opts& o, float* med) -> nxs_status {
-    std::vector<float> ms;
-    for (int r = 0; r <= reps; ++r) {
+  // GPU time per render: one waiting render (it sizes the buffers), then
+  // `reps` deferred renders back to back on the stream between two events, so
+  // that no host wait sits inside the timed span; renders that outgrew the
+  // context (the device's flag, read by nxs_forward_status, which also grows
+  // it) are timed again
+  auto measure = [&](const nxs_render_opts& o, float* per_render) -> nxs_status {
+    nxs_status rs = nxs_render_forward(ctx, g, cams, n_views, &o, out, nullptr, stream);
+    if (rs != NXS_OK) return rs;
+    nxs_render_opts od = o;
+    od.flags |= NXS_FLAG_DEFERRED;
+    for (int attempt = 0; attempt < 3; ++attempt) {
       if (hipEventRecord(e0, s) != hipSuccess) return fail(ctx, NXS_EHIP, "event record");
-      nxs_status rs = nxs_render_forward(ctx, g, cams, n_views, &o, out, nullptr, stream);
-      if (rs != NXS_OK) return rs;
+      for (int r = 0; r < reps; ++r) {
+        rs = nxs_render_forward(ctx, g, cams, n_views, &od, out, nullptr, stream);
+        if (rs != NXS_OK) return rs;
+      }
       float t_ms = 0.0f;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&t_ms, e0, e1) != hipSuccess)
         return fail(ctx, NXS_EHIP, "autotune timing failed");
-      if (r > 0) ms.push_back(t_ms);   // the first render is a warm-up
+      rs = nxs_forward_status(ctx, nullptr);
+      if (rs == NXS_OK) {
+        *per_render = t_ms / (float)reps;
+        return NXS_OK;
+      }
+      if (rs != NXS_ECAPACITY) return rs;
+      ctx->err.clear();
     }
-    std::sort(ms.begin(), ms.end());
-    *med = ms[ms.size() / 2];
-    return NXS_OK;
+    return fail(ctx, NXS_ECAPACITY, "autotune: deferred renders kept outgrowing the context");
   };
   const int shapes[3][2] = {{8, 8}, {16, 16}, {32, 8}};
   nxs_tuning best{0, 0, 0, 64, NXS_SORT_AUTO, 0.0f};

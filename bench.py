@@ -64,17 +64,20 @@ SLOTS_PER_PAIR = 24
 VALU_SLOT_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of each composite kernel on this workload (16x16 tiles),
+# HBM bytes per launch of each composite kernel on this workload (16x16 tiles,
+# per schedule: the queue and the tile schedule),
 # from FETCH_SIZE and WRITE_SIZE counter runs scaled by a copy kernel of known
 # size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
 # kernel sources with this digest and are reported as null once those change.
 TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_stage.h", "nxs_internal.h")
-TRAFFIC = {"digest": "3d81eabe39606fedd5915aba967e17bc8af29c075d654f215516f90cfa1ed186",
+TRAFFIC = {"digest": "b3ccc597a7ca39d85ca27910251425582d2f25d0d54bfb3f3f9af59fa8da3c7a",
            "tile": "16x16",
-           "bytes": {0: 494453052, 1: 247928712, 2: 277706664, 3: 236480548}}
+           "bytes": {
+               "queue": {0: 495125615, 1: 254632166, 2: 287463222, 3: 241358466},
+               "tiles": {0: 225043082, 1: 131651756, 2: 145924923, 3: 127210112}}}
 
 
-def measured_traffic(model, tile):
+def measured_traffic(model, tile, schedule):
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -82,7 +85,7 @@ def measured_traffic(model, tile):
             h.update(fh.read())
     if h.hexdigest() != TRAFFIC["digest"] or tile != TRAFFIC["tile"]:
         return None
-    return TRAFFIC["bytes"].get(model)
+    return TRAFFIC["bytes"].get(schedule, {}).get(model)
 
 
 def percentile(xs, q):
@@ -592,7 +595,7 @@ def main():
         roofline = {"bound": "alu", "kernel": f"composite<{MODELS[dm]}>",
                     "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-                    "traffic": (measured_traffic(dm, tile)
+                    "traffic": (measured_traffic(dm, tile, cfg[dm]["schedule"])
                                 if cfg[dm]["lds_batch"] == 64 else None),
                     "work_per_launch": {"composited_pairs": od_sum[dm],
                                         "flops_per_pair": FLOPS_PER_PAIR[dm]},

@@ -209,8 +209,10 @@ typedef struct nxs_fwd_state nxs_fwd_state;
 
 /* Device allocator of the caller (e.g. a framework's caching allocator).
  *   alloc(bytes, stream, user): device memory of at least `bytes` bytes on
- *       the context's device, usable by work enqueued on `stream` after the
- *       call; NULL on failure (the render then fails with NXS_ENOMEM).
+ *       the context's device, aligned to 256 bytes, usable by work enqueued
+ *       on `stream` after the call; NULL on failure (the render then fails
+ *       with NXS_ENOMEM; a block that is not aligned is given back and the
+ *       render fails with NXS_EINVAL).
  *   free(ptr, stream, user): gives back a block from alloc.  Work enqueued
  *       on `stream` before the call may still use it, and all other work
  *       that used it is ordered before that point of `stream`: the

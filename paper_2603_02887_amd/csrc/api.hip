@@ -160,6 +160,12 @@ nxs_status dev_alloc(nxs_context* ctx, size_t bytes, hipStream_t s, void** p) {
   if (a.alloc) {
     *p = a.alloc(bytes, (void*)s, a.user);
     if (!*p) return fail(ctx, NXS_ENOMEM, "the caller's allocator failed for %zu bytes", bytes);
+    if (reinterpret_cast<uintptr_t>(*p) & 255u) {
+      a.free(*p, (void*)s, a.user);
+      *p = nullptr;
+      return fail(ctx, NXS_EINVAL, "the caller's allocator returned a block not aligned to "
+                  "256 bytes");
+    }
     return NXS_OK;
   }
   if (hipMallocFromPoolAsync(p, bytes, a.pool, s) != hipSuccess) {

@@ -243,16 +243,40 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t va
 }
 
 // Entry j starts its tile's range if the entry before it has another tile,
-// and ends it if the entry after it has another tile.
+// and ends it if the entry after it has another tile.  A thread takes
+// kRangeItems consecutive entries (one 16-byte load) and their two neighbours.
+constexpr int kRangeItems = 4;
+
 __global__ __launch_bounds__(256) void ranges_kernel(const uint32_t* __restrict__ inst_tile,
                                                      int64_t m, uint2* __restrict__ ranges,
                                                      const Counters* __restrict__ dn) {
   if (dn) m = min(m, live_count(dn));
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
-    const uint32_t tile = inst_tile[j];
-    if (j == 0 || inst_tile[j - 1] != tile) ranges[tile].x = (uint32_t)j;
-    if (j == m - 1 || inst_tile[j + 1] != tile) ranges[tile].y = (uint32_t)(j + 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * kRangeItems;
+  for (int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems; j0 < m;
+       j0 += stride) {
+    uint32_t t[kRangeItems];
+    if (j0 + kRangeItems <= m) {
+      const uint4 q = *reinterpret_cast<const uint4*>(inst_tile + j0);   // (j0 % 4 == 0)
+      t[0] = q.x;
+      t[1] = q.y;
+      t[2] = q.z;
+      t[3] = q.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < kRangeItems; ++k) t[k] = j0 + k < m ? inst_tile[j0 + k] : 0u;
+    }
+    // (no tile is ~0: the neighbour outside the list never matches)
+    const uint32_t prev = j0 > 0 ? inst_tile[j0 - 1] : ~0u;
+    const uint32_t next = j0 + kRangeItems < m ? inst_tile[j0 + kRangeItems] : ~0u;
+#pragma unroll
+    for (int k = 0; k < kRangeItems; ++k) {
+      const int64_t j = j0 + k;
+      if (j >= m) break;
+      const uint32_t before = k == 0 ? prev : t[k - 1];
+      const uint32_t after = j == m - 1 ? ~0u : (k == kRangeItems - 1 ? next : t[k + 1]);
+      if (before != t[k]) ranges[t[k]].x = (uint32_t)j;
+      if (after != t[k]) ranges[t[k]].y = (uint32_t)(j + 1);
+    }
   }
 }
 
@@ -296,8 +320,9 @@ void launch_ranges(const uint32_t* inst_tile, int64_t m, uint2* ranges, hipStrea
                    const Counters* dn, int64_t m_plan) {
   if (m <= 0) return;
   const int64_t g = dn && m_plan > 0 ? std::min(m_plan, m) : m;
-  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((g + 255) / 256)), dim3(256), 0, s,
-                     inst_tile, m, ranges, dn);
+  const int64_t per_group = 256 * kRangeItems;
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((g + per_group - 1) / per_group)), dim3(256),
+                     0, s, inst_tile, m, ranges, dn);
 }
 
 }  // namespace nxs

@@ -570,7 +570,8 @@ def main():
     per_model = {}
     stage_mean = {}
     for m in range(4):
-        st = {k: float(np.mean([x[k] for x in stages[m]])) for k in R.STAGES}
+        # (medians: a render that a host hiccup delays shifts the mean)
+        st = {k: float(np.median([x[k] for x in stages[m]])) for k in R.STAGES}
         stage_mean[m] = st
         per_model[MODELS[m]] = {
             "mpix_per_s": W * H / thr[m] / 1e6,

@@ -38,8 +38,11 @@ constexpr float kLn2 = 0.6931471805599453f;   // 1 / log2(e)
 // Sum over each row of 16 lanes with DPP adds (VALU only): pairs and quads
 // by quad_perm, then half-rows and rows by mirror patterns; every lane of a
 // row ends with the row's total.
+// (no contraction: an add of the moved value folds into one DPP add, which a
+// product of the caller fused into an FMA with it would prevent)
 template <int CTRL>
 __device__ __forceinline__ float dpp_add(float x) {
+#pragma clang fp contract(off)
   const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true);
   return x + __int_as_float(y);
 }

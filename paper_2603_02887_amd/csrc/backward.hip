@@ -210,9 +210,14 @@ __global__ __launch_bounds__(TW* TH) void composite_bwd_kernel(
       const float da = dalpha * a;
       const float dax = da * dx, day = da * dy;
       if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
-        const float t[9] = {quad_total(da),       quad_total(dax),      quad_total(day),
-                            quad_total(dax * dx), quad_total(dax * dy), quad_total(day * dy),
-                            quad_total(p * g0),   quad_total(p * g1),   quad_total(p * g2)};
+        float t[9] = {quad_total(da),       quad_total(dax),      quad_total(day),
+                      quad_total(dax * dx), quad_total(dax * dy), quad_total(day * dy),
+                      quad_total(p * g0),   quad_total(p * g1),   quad_total(p * g2)};
+        // (an empty statement that keeps each sum's last add here, with every
+        // lane active, where it folds into one DPP add, instead of letting it
+        // sink into the quad leaders' store below)
+#pragma unroll
+        for (int f = 0; f < 9; ++f) __asm__ volatile("" : "+v"(t[f]));
         if ((lane & 3) == 0) {
           float* row = wred + 9 * 16 * pend + (lane >> 2);
 #pragma unroll

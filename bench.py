@@ -470,6 +470,9 @@ def main():
     torch.cuda.synchronize()
     od_sum = {m: int(outs[m][0]["overdraw"].sum().item()) for m in range(4)}
     n_inst, _ = R.counts()
+    # this GPU's measured FP32 FMA rate (non-packed) and copy bandwidth, beside
+    # the datasheet peaks
+    peaks = R.measure_peaks()
 
     def render(m, ci=0, deferred=True, conf=None):
         ctxs[ci].render(g, [cam], model=m, outputs=ctx_outs[ci][m], deferred=deferred,
@@ -604,7 +607,9 @@ def main():
                                          "peak_T_per_s": VALU_SLOT_PEAK_T,
                                          "frac": slots / VALU_SLOT_PEAK_T},
                     "config": per_model[MODELS[dm]]["config"],
-                    "avg_launch_ms": dms}
+                    "avg_launch_ms": dms,
+                    "measured_peak": peaks["fp32_fma_tflops"],
+                    "frac_of_measured_peak": achieved / peaks["fp32_fma_tflops"]}
     else:
         roofline = {"bound": "hbm", "kernel": dk, "avg_launch_ms": dms, "achieved": None,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}
@@ -650,6 +655,10 @@ def main():
         "throughput_modes_mpix_per_s": {k: W * H * renders / v / 1e6 for k, v in modes.items()},
         "per_model": per_model,
         "roofline": roofline,
+        "measured_peaks": {"fp32_fma_tflops": peaks["fp32_fma_tflops"],
+                           "copy_gbs": peaks["copy_gbs"],
+                           "datasheet": {"fp32_tflops": FP32_VALU_PEAK_TFLOPS,
+                                         "hbm_gbs": HBM_PEAK_GBS}},
         "cpu_baseline": cpu,
         "batched": batched,
         "differentiation": diff,

@@ -419,6 +419,18 @@ const char* nxs_last_error(const nxs_context* ctx);
  * buffers the caller provides.
  * ------------------------------------------------------------------------- */
 
+/* Measured peaks of the context's GPU, to report kernels against what this
+ * build reaches as well as against the datasheet: *fp32_fma_tflops from
+ * independent FP32 FMA chains (8 waves per SIMD; an FMA counts 2 flops;
+ * packed FP32 is disabled in every kernel of the library, so this is the
+ * non-packed rate), *copy_gbs from the best of three device-to-device copies
+ * of 512 MiB (bytes read + written over time).  Takes 1 GiB of workspace
+ * for the call (from the context's allocator, freed stream-ordered before
+ * returning) and a few tens of milliseconds; enqueues on `stream` and
+ * synchronises it.  Errors: NXS_EINVAL (null argument), NXS_ENOMEM, NXS_EHIP. */
+nxs_status nxs_measure_peaks(nxs_context* ctx, double* fp32_fma_tflops, double* copy_gbs,
+                             void* stream);
+
 /* Per-stage GPU timing.  With timing enabled, each render records hipEvents
  * on its stream between its stages; nxs_inspect_stage_times then returns the
  * milliseconds of the last render's stages, in this order:

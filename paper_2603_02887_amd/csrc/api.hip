@@ -1139,6 +1139,72 @@ nxs_status nxs_workspace_bytes(const nxs_context* ctx, size_t* bytes) {
   return NXS_OK;
 }
 
+nxs_status nxs_measure_peaks(nxs_context* ctx, double* fp32_fma_tflops, double* copy_gbs,
+                             void* stream) {
+  if (!ctx) return NXS_EINVAL;
+  ctx->err.clear();
+  if (!fp32_fma_tflops || !copy_gbs) return fail(ctx, NXS_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int groups = 8 * ctx->n_cu;              // 8 waves per SIMD
+  const int iters = 20000;
+  const size_t copy_bytes = size_t(512) << 20;   // read, and again written
+  void* out = nullptr;
+  void* src = nullptr;
+  void* dst = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  nxs_status st = NXS_OK;
+  float fma_ms = 0.0f, copy_ms = 0.0f;
+  auto hip = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && st == NXS_OK)
+      st = fail(ctx, NXS_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+    return st == NXS_OK;
+  };
+  auto timed = [&](auto&& launch, float* ms) {
+    if (!hip(hipEventRecord(e0, s), "hipEventRecord")) return false;
+    launch();
+    if (!hip(hipGetLastError(), "peak kernel launch") || !hip(hipEventRecord(e1, s), "hipEventRecord") ||
+        !hip(hipEventSynchronize(e1), "hipEventSynchronize") ||
+        !hip(hipEventElapsedTime(ms, e0, e1), "hipEventElapsedTime"))
+      return false;
+    return true;
+  };
+  if ((st = dev_alloc(ctx, 4 * peak_fma_out_floats(groups), s, &out)) == NXS_OK &&
+      (st = dev_alloc(ctx, copy_bytes, s, &src)) == NXS_OK &&
+      (st = dev_alloc(ctx, copy_bytes, s, &dst)) == NXS_OK &&
+      hip(hipEventCreate(&e0), "hipEventCreate") && hip(hipEventCreate(&e1), "hipEventCreate")) {
+    // FP32 FMA chains: one warm-up launch, then the timed one
+    auto fma = [&]() { launch_peak_fma(static_cast<float*>(out), groups, iters, s); };
+    fma();
+    if (timed(fma, &fma_ms)) {
+      // copy: the source set first, one warm-up, then the best of three
+      const int64_t n4 = (int64_t)(copy_bytes / 16);
+      auto copy = [&]() {
+        launch_peak_copy(static_cast<const float4*>(src), static_cast<float4*>(dst), n4, s);
+      };
+      if (hip(hipMemsetAsync(src, 0, copy_bytes, s), "hipMemsetAsync")) {
+        copy();
+        copy_ms = 1e30f;
+        for (int r = 0; r < 3 && st == NXS_OK; ++r) {
+          float ms = 0.0f;
+          if (timed(copy, &ms)) copy_ms = std::min(copy_ms, ms);
+        }
+      }
+    }
+  }
+  if (out) dev_free(ctx, out, s);
+  if (src) dev_free(ctx, src, s);
+  if (dst) dev_free(ctx, dst, s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != NXS_OK) return st;
+  if (!(fma_ms > 0.0f) || !(copy_ms > 0.0f))
+    return fail(ctx, NXS_EHIP, "peak timing gave no duration");
+  *fp32_fma_tflops = (double)peak_fma_flops(groups, iters) / (fma_ms * 1e-3) / 1e12;
+  *copy_gbs = 2.0 * (double)copy_bytes / (copy_ms * 1e-3) / 1e9;
+  return NXS_OK;
+}
+
 nxs_status nxs_set_timing(nxs_context* ctx, int32_t enable) {
   if (!ctx) return NXS_EINVAL;
   HIP_TRY(hipSetDevice(ctx->device));

@@ -253,4 +253,12 @@ struct GaussGradDev {
 void launch_project_bwd(const GaussDev& g, const ViewDev* views, int n_views,
                         float* gslot, const GaussGradDev& out, hipStream_t s);
 
+// Measured peaks (peaks.hip): `groups` work-groups of independent FP32 FMA
+// chains, `iters` steps each (peak_fma_flops of them, out: peak_fma_out_floats
+// floats); a float4 copy of n4 elements (n4 < 2^39), one per thread.
+int64_t peak_fma_flops(int groups, int iters);
+size_t peak_fma_out_floats(int groups);
+void launch_peak_fma(float* out, int groups, int iters, hipStream_t s);
+void launch_peak_copy(const float4* src, float4* dst, int64_t n4, hipStream_t s);
+
 }  // namespace nxs

@@ -30,6 +30,7 @@ SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_render_backwa
            "nxs_server_submit", "nxs_server_step", "nxs_server_pending",
            "nxs_server_in_flight", "nxs_server_workspace_bytes", "nxs_server_last_error",
            "nxs_last_error",
+           "nxs_measure_peaks",
            "nxs_set_timing", "nxs_inspect_stage_times", "nxs_inspect_counts",
            "nxs_inspect_instances", "nxs_inspect_ranges", "nxs_inspect_projection",
            "nxs_inspect_slot_grads"]
@@ -524,6 +525,16 @@ class Renderer:
 
     # -------------------------------------------------------- inspection
     STAGES = ("project", "depth_sort", "emit", "tile_sort", "ranges", "composite")
+
+    def measure_peaks(self, stream=None):
+        """Measured FP32 FMA rate (TFLOP/s, non-packed) and copy bandwidth
+        (GB/s) of this GPU (nxs_measure_peaks)."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        fma, copy = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        self._check(self._L.nxs_measure_peaks(self._ctx, byref(fma), byref(copy),
+                                              c_void_p(stream.cuda_stream)))
+        return {"fp32_fma_tflops": fma.value, "copy_gbs": copy.value}
 
     def set_timing(self, enable=True):
         self._check(self._L.nxs_set_timing(self._ctx, int(bool(enable))))

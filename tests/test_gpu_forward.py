@@ -338,3 +338,16 @@ def test_operator_parameter_checks(R):
     for model, param in ((4, -0.6), (5, 1.5), (6, -0.1), (7, 0.0)):
         with pytest.raises(nxs.NxsError):
             R.render(g, cams, model=model, param=param)
+
+
+def test_measured_peaks(R):
+    """nxs_measure_peaks: the FP32 FMA rate of independent chains and the copy
+    bandwidth are positive and below MI355X's datasheet figures (157.3
+    TFLOP/s counts packed FP32, which no kernel here uses; HBM 8 TB/s), and
+    the call leaves the context usable."""
+    p = R.measure_peaks()
+    assert 10.0 < p["fp32_fma_tflops"] < 157.3, p
+    assert 500.0 < p["copy_gbs"] < 8000.0, p
+    sc, cams = synth.tiny_scene(seed=2, n=512)
+    out = _render(R, sc, cams, 1)
+    parity.compare_view(out[0], sc, cams[0], 1, pixels=parity.sample_pixels(cams[0], 200))

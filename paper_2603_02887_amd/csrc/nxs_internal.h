@@ -152,7 +152,7 @@ int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_
 size_t scan_blocks_size(int64_t n);
 // Exclusive scan of the depth-sorted tile counts (nt_sorted), or with
 // nt_sorted null of the counts in the tile records in slot order, per block
-// of 1,024 slots (block totals in block_sums; scanned across blocks here
+// of 512 slots (block totals in block_sums; scanned across blocks here
 // only when there are more blocks than the emission sums itself).
 void launch_emit_scan(const uint32_t* nt_sorted, const uint4* tinfo, int64_t n_slots,
                       uint32_t* scan_local, uint32_t* block_sums, hipStream_t s);

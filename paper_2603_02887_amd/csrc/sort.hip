@@ -47,7 +47,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
 // ---------------------------------------------------------------- scan + emit
 
 constexpr int kScanBlock = 256;
-constexpr int kScanItems = 4;
+constexpr int kScanItems = 2;
 constexpr int kScanChunk = kScanBlock * kScanItems;
 
 // Block-local exclusive scan of the slots' tile counts: nt_sorted in
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(uint32_t* __res
   }
 }
 
-// One work-group per 1024 sorted slots writes all of their instances as one
+// One work-group per 512 sorted slots writes all of their instances as one
 // contiguous run, consecutive threads at consecutive addresses however
 // unevenly the Gaussians' tile counts are spread: the run is taken in windows
 // of kEmitWindow positions, each slot first marks the positions of its

@@ -6,8 +6,7 @@
 // 4,096 keys above (longer digit runs per chunk, which is what bounds them at
 // tens of millions).  Each pass is three kernels:
 //   count    per chunk and digit                counts[d * nchunks + c]
-//            (one LDS add per distinct digit per wave round: lanes with equal
-//            digits are matched by ballots first)
+//            (one LDS atomic add per key)
 //   scan     per digit over chunks (one work-group per digit) -> exclusive
 //            offsets in place, digit totals
 //   scatter  per chunk: stable local ranks via wave ballots, a reorder by
@@ -127,7 +126,6 @@ __global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* keys,
   }
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const uint32_t mask = (1u << width) - 1u;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (uint32_t c = walk.first; c < walk.end; c += walk.step) {   // (uniform per group)
     for (int d = t; d < kRBins; d += kRThreads) h[d] = 0;
     __syncthreads();
@@ -144,8 +142,7 @@ __global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* keys,
       const int li = wid * (64 * ITEMS) + r * 64 + lane;
       const bool valid = li < chunk_n;
       const uint32_t d = (k[r] >> shift) & mask;
-      const uint64_t peers = digit_peers(d, width, valid);
-      if (valid && (peers & lt_mask) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+      if (valid) atomicAdd(&h[d], 1u);
     }
     __syncthreads();
     for (int d = t; d <= (int)mask; d += kRThreads) counts[(int64_t)d * nchunks + c] = h[d];

@@ -1,10 +1,10 @@
 // Stable LSD radix sort of (u32 key, u32 value) pairs, reduce-then-scan.
 //
 // Digits of up to 9 bits (as few passes as that allows, widths balanced) over
-// chunks of 1,024 keys below 16M keys (many work-groups, short per-group
+// chunks of 1,024 keys below 3M keys (many work-groups, short per-group
 // latency, which is what bounds these passes at 1-3 million keys) and of
-// 4,096 keys above (longer digit runs per chunk, which is what bounds them at
-// tens of millions).  Each pass is three kernels:
+// 4,096 keys above (longer digit runs per chunk, and a grid that four
+// work-groups per CU cover in fewer rounds).  Each pass is three kernels:
 //   count    per chunk and digit                counts[d * nchunks + c]
 //            (one LDS atomic add per key)
 //   scan     per digit over chunks (one work-group per digit) -> exclusive
@@ -27,12 +27,13 @@ namespace {
 constexpr int kRThreads = 256;
 constexpr int kRWaves = kRThreads / 64;
 // Keys per thread: 4 (chunks of 1,024) keeps the per-group latency short,
-// which is what bounds a pass at a few million keys; 16 (chunks of 4,096)
-// gives each digit runs four times longer in a chunk's output, which is what
-// bounds a pass at tens of millions of keys (partial cache lines at run ends).
+// which is what bounds a pass at up to about 3 million keys; 16 (chunks of
+// 4,096) gives each digit runs four times longer in a chunk's output (fewer
+// partial cache lines at run ends) and needs a quarter of the work-groups
+// (4M keys: 2.5 rounds of the small chunks' grid, one of the large).
 constexpr int kRItemsSmall = 4;
 constexpr int kRItemsLarge = 16;
-constexpr int64_t kRLargeFrom = int64_t(1) << 24;   // keys
+constexpr int64_t kRLargeFrom = int64_t(3) << 20;   // keys
 constexpr int kRChunkMin = kRThreads * kRItemsSmall;
 constexpr int kRBins = 1 << kMaxDigitBits;     // digits of up to 9 bits
 constexpr int kRBinsPerThread = kRBins / kRThreads;
@@ -220,11 +221,15 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
     const uint4* __restrict__ tinfo, uint32_t* __restrict__ nt_out,
     uint2* __restrict__ rect_out, const Counters* __restrict__ dn) {
+  // Per-wave digit counts (at most 64 * ITEMS) and each digit's local start
+  // in the chunk (at most 256 * ITEMS) are kept in 16 bits: at 4,096 keys
+  // the tables then leave room for four work-groups per CU instead of three.
+  static_assert(kRThreads * ITEMS <= 0xFFFF, "local positions must fit 16 bits");
   __shared__ uint32_t s_key[(kRThreads * ITEMS)];
   __shared__ uint32_t s_val[(kRThreads * ITEMS)];
-  __shared__ uint32_t s_wave[kRWaves][kRBins];
-  __shared__ uint32_t s_gbase[kRBins];
-  __shared__ uint32_t s_lbase[kRBins];
+  __shared__ uint16_t s_wave[kRWaves][kRBins];
+  __shared__ uint16_t s_lbase[kRBins];
+  __shared__ uint32_t s_delta[kRBins];   // global minus local start of each digit's run
   __shared__ uint32_t s_tmp[kRWaves];
 
   if (!pass_digit(plan, pass, shift, width)) return;   // the whole grid
@@ -253,18 +258,19 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
       }
     }
     // global start of this chunk's run of each digit: keys of smaller digits
-    // plus keys of that digit in earlier chunks (thread t: digits 2t, 2t + 1)
+    // plus keys of that digit in earlier chunks (thread t: digits 2t, 2t + 1;
+    // the scan's barriers also order the cleared counters before the ranks)
+    const int d0 = 2 * t, d1 = 2 * t + 1;
+    uint32_t gbase0, gbase1;
     {
-      const int d0 = 2 * t, d1 = 2 * t + 1;
       const uint32_t tot0 = d0 < nd ? totals[d0] : 0u, tot1 = d1 < nd ? totals[d1] : 0u;
       const uint32_t off0 = d0 < nd ? counts[(int64_t)d0 * nchunks + c] : 0u;
       const uint32_t off1 = d1 < nd ? counts[(int64_t)d1 * nchunks + c] : 0u;
       uint32_t all;
       const uint32_t ex = rx_block_scan(tot0 + tot1, s_tmp, &all);
-      s_gbase[d0] = ex + off0;
-      s_gbase[d1] = ex + tot0 + off1;
+      gbase0 = ex + off0;
+      gbase1 = ex + tot0 + off1;
     }
-    __syncthreads();
     // per-wave ranks: keys of the same digit earlier in this wave's part
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t rank[ITEMS], dig[ITEMS];
@@ -280,13 +286,12 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
         const uint32_t before = s_wave[wid][d];   // the same for every peer
         const uint32_t pos = (uint32_t)__popcll(peers & lt_mask);
         rank[r] = before + pos;
-        if (pos == 0) s_wave[wid][d] = before + (uint32_t)__popcll(peers);
+        if (pos == 0) s_wave[wid][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
       }
     }
     __syncthreads();
     // local start of each digit's run in the chunk
     {
-      const int d0 = 2 * t, d1 = 2 * t + 1;
       uint32_t cnt0 = 0, cnt1 = 0;
       for (int w = 0; w < kRWaves; ++w) {
         cnt0 += s_wave[w][d0];
@@ -294,8 +299,10 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
       }
       uint32_t all;
       const uint32_t ex = rx_block_scan(cnt0 + cnt1, s_tmp, &all);
-      s_lbase[d0] = ex;
-      s_lbase[d1] = ex + cnt0;
+      s_lbase[d0] = (uint16_t)ex;
+      s_lbase[d1] = (uint16_t)(ex + cnt0);
+      s_delta[d0] = gbase0 - ex;
+      s_delta[d1] = gbase1 - (ex + cnt0);
     }
     __syncthreads();
 #pragma unroll
@@ -313,7 +320,7 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     for (int i = t; i < chunk_n; i += kRThreads) {
       const uint32_t k = s_key[i];
       const uint32_t d = (k >> shift) & mask;
-      const uint32_t g = s_gbase[d] + (uint32_t)i - s_lbase[d];
+      const uint32_t g = s_delta[d] + (uint32_t)i;
       keys_out[g] = k;
       vals_out[g] = s_val[i];
       if (tinfo) {   // the slot's tile record, now in sorted order

@@ -21,6 +21,7 @@ namespace {
 
 
 // Block-wide exclusive scan of one value per thread (256 threads).
+template <int NW = 4>   // waves in the work-group
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s_tmp,
                                                          uint32_t* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -34,7 +35,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
   __syncthreads();
   uint32_t wave_off = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
+  for (int w = 0; w < NW; ++w) {
     uint32_t v = s_tmp[w];
     if (w < wid) wave_off += v;
     tot += v;
@@ -79,24 +80,29 @@ __global__ __launch_bounds__(kScanBlock) void scan_local_kernel(
   }
 }
 
-// Single work-group exclusive scan of the block sums (in place).
-__global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(uint32_t* __restrict__ sums,
-                                                                 int nblocks) {
-  __shared__ uint32_t s_tmp[kScanBlock / 64];
+// Single work-group exclusive scan of the block sums (in place): 1,024
+// threads of 16 consecutive sums each, so that 16,384 sums take one round of
+// loads, one scan and one round of stores (93,750 block sums of a 48M-slot
+// batch: 6 rounds; with 256 threads of 4 sums, 92 rounds took 91 us).
+constexpr int kSumThreads = 1024;
+constexpr int kSumItems = 16;
+__global__ __launch_bounds__(kSumThreads) void scan_blocks_kernel(uint32_t* __restrict__ sums,
+                                                                  int nblocks) {
+  __shared__ uint32_t s_tmp[kSumThreads / 64];
   uint32_t running = 0;
-  for (int b = 0; b < nblocks; b += kScanBlock * 4) {
-    uint32_t v[4], sum = 0;
+  for (int b = 0; b < nblocks; b += kSumThreads * kSumItems) {
+    uint32_t v[kSumItems], sum = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      int idx = b + threadIdx.x * 4 + k;
+    for (int k = 0; k < kSumItems; ++k) {
+      const int idx = b + threadIdx.x * kSumItems + k;
       v[k] = idx < nblocks ? sums[idx] : 0u;
       sum += v[k];
     }
     uint32_t tot;
-    uint32_t ex = block_exclusive_scan(sum, s_tmp, &tot) + running;
+    uint32_t ex = block_exclusive_scan<kSumThreads / 64>(sum, s_tmp, &tot) + running;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      int idx = b + threadIdx.x * 4 + k;
+    for (int k = 0; k < kSumItems; ++k) {
+      const int idx = b + threadIdx.x * kSumItems + k;
       if (idx < nblocks) sums[idx] = ex;
       ex += v[k];
     }
@@ -293,7 +299,7 @@ void launch_emit_scan(const uint32_t* nt_sorted, const uint4* tinfo, int64_t n_s
   hipLaunchKernelGGL(scan_local_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, nt_sorted, tinfo,
                      n_slots, scan_local, block_sums);
   if (nblocks > kInlineBlocks)
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kScanBlock), 0, s, block_sums,
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kSumThreads), 0, s, block_sums,
                        nblocks);
 }
 

@@ -138,20 +138,29 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
   __shared__ uint16_t s_owner[kEmitWindow];   // block-local slot of each position
   const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
   const int cnt = (int)min((int64_t)kScanChunk, n - b0);
-  uint32_t out0;
-  if (nblocks <= kInlineBlocks) {
-    // the sum of the totals of the blocks before this one
-    uint32_t part = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBlock) part += block_sums[b];
-    uint32_t all;
-    (void)block_exclusive_scan(part, s_tmp, &all);
-    out0 = all;
-  } else {
-    out0 = block_sums[blockIdx.x];   // scanned in place
-  }
-  const uint32_t out1 = out0 + (nblocks <= kInlineBlocks ? block_sums[blockIdx.x]
-                                                         : block_sums[nblocks + blockIdx.x]);
-  // loads first (all independent), then the LDS tables
+  // This block's output offset: with the inline sum (many loads and a block
+  // scan) before the slots' loads, else after them (measured both ways: the
+  // 1080p frame's 1,954 blocks 20.9 against 21.8 us with the sum first; the
+  // eight 720p views' 7,813 pre-scanned blocks 149 against 154 us with the
+  // loads first).
+  const bool inline_sum = nblocks <= kInlineBlocks;
+  uint32_t out0 = 0, out1 = 0;
+  auto block_offset = [&]() {
+    if (inline_sum) {
+      // the sum of the totals of the blocks before this one
+      uint32_t part = 0;
+      for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBlock) part += block_sums[b];
+      uint32_t all;
+      (void)block_exclusive_scan(part, s_tmp, &all);
+      out0 = all;
+      out1 = out0 + block_sums[blockIdx.x];
+    } else {
+      out0 = block_sums[blockIdx.x];   // scanned in place
+      out1 = out0 + block_sums[nblocks + blockIdx.x];
+    }
+  };
+  if (inline_sum) block_offset();
+  // the slots' loads (all independent), then the LDS tables
   constexpr int kPerT = kScanChunk / kScanBlock;
   uint32_t slot_r[kPerT], off_r[kPerT];
   uint2 rect_r[kPerT];
@@ -173,6 +182,7 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
       rect_r[q] = make_uint2(ti.x, ti.y);
     }
   }
+  if (!inline_sum) block_offset();
 #pragma unroll
   for (int q = 0; q < kPerT; ++q) {
     const int k = q * kScanBlock + threadIdx.x;

@@ -1,7 +1,7 @@
 // Stable LSD radix sort of (u32 key, u32 value) pairs, reduce-then-scan.
 //
 // Digits of up to 9 bits (as few passes as that allows, widths balanced) over
-// chunks of 1,024 keys below 3M keys (many work-groups, short per-group
+// chunks of 1,024 keys below 3.5M keys (many work-groups, short per-group
 // latency, which is what bounds these passes at 1-3 million keys) and of
 // 4,096 keys above (longer digit runs per chunk, and a grid that four
 // work-groups per CU cover in fewer rounds).  Each pass is three kernels:
@@ -27,13 +27,16 @@ namespace {
 constexpr int kRThreads = 256;
 constexpr int kRWaves = kRThreads / 64;
 // Keys per thread: 4 (chunks of 1,024) keeps the per-group latency short,
-// which is what bounds a pass at up to about 3 million keys; 16 (chunks of
+// which is what bounds a pass at up to about 3.5 million keys; 16 (chunks of
 // 4,096) gives each digit runs four times longer in a chunk's output (fewer
 // partial cache lines at run ends) and needs a quarter of the work-groups
 // (4M keys: 2.5 rounds of the small chunks' grid, one of the large).
 constexpr int kRItemsSmall = 4;
 constexpr int kRItemsLarge = 16;
-constexpr int64_t kRLargeFrom = int64_t(3) << 20;   // keys
+// Planned keys from which the large chunks are used; a deferred render plans
+// its tile sort for the expected count plus a quarter (the 1080p frame's
+// 2.69M instances: 3.37M planned, faster in small chunks).
+constexpr int64_t kRLargeFrom = int64_t(7) << 19;   // 3.5M keys
 constexpr int kRChunkMin = kRThreads * kRItemsSmall;
 constexpr int kRBins = 1 << kMaxDigitBits;     // digits of up to 9 bits
 constexpr int kRBinsPerThread = kRBins / kRThreads;

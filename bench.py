@@ -70,11 +70,11 @@ HBM_PEAK_GBS = 8000.0
 # size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
 # kernel sources with this digest and are reported as null once those change.
 TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_stage.h", "nxs_internal.h")
-TRAFFIC = {"digest": "b3ccc597a7ca39d85ca27910251425582d2f25d0d54bfb3f3f9af59fa8da3c7a",
+TRAFFIC = {"digest": "366497bff0df9da7a2f6bbb7176565a5406797d0df448e4379b12777e3f7fd1f",
            "tile": "16x16",
            "bytes": {
-               "queue": {0: 495125615, 1: 254632166, 2: 287463222, 3: 241358466},
-               "tiles": {0: 225043082, 1: 131651756, 2: 145924923, 3: 127210112}}}
+               "queue": {0: 502216918, 1: 254830257, 2: 288599259, 3: 242061326},
+               "tiles": {0: 225049701, 1: 131736034, 2: 145836523, 3: 127258251}}}
 
 
 def measured_traffic(model, tile, schedule):

@@ -1,9 +1,11 @@
-"""Sorts past the chunk-size switch (16M keys), bit-exact against the oracle.
+"""Sorts past the chunk-size switch, bit-exact against the oracle.
 
-2.2M Gaussians seen by 8 small views give 17.6M projected slots (the depth
-sort takes 4,096-key chunks) and about 29M tile instances (so does the tile
-sort); the instance list, tile ranges and per-slot keys must equal the float32
-key recipe's exactly, and sampled pixels must match the oracle render.
+The radix passes take 4,096-key chunks from 3.5M planned keys on.  2.2M
+Gaussians seen by 8 small views give 17.6M projected slots and about 29M
+tile instances (both sorts past 16M keys); 460,000 Gaussians in 8 views give
+3.68M slots, just past the switch.  The instance list, tile ranges and
+per-slot keys must equal the float32 key recipe's exactly, and sampled pixels
+must match the oracle render.
 """
 import numpy as np
 import pytest
@@ -34,6 +36,34 @@ def test_depth_and_tile_sorts_past_16m_keys():
         for v in (0, 5):
             px = parity.sample_pixels(cams[v], 400, seed=v)
             parity.compare_view(out[v], sc, cams[v], 1, pixels=px)
+        print("instances", m)
+    finally:
+        R.close()
+
+
+@pytest.mark.timeout(300)
+def test_depth_sort_just_past_the_chunk_switch():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2603_02887_amd import nxs
+    R = nxs.Renderer(0)
+    try:
+        sc = synth.random_scene(23, 460_000, sh_degree=0, log_scale=(-4.0, 0.3))
+        cams = synth.orbit_cameras(8, 4.0, [96] * 8, [64] * 8, rng=np.random.default_rng(2))
+        assert (7 << 19) <= sc.n * len(cams) < (1 << 22)
+        g = nxs.scene_to_device(sc)
+        print("case: 3.68M slots, waiting then deferred", flush=True)
+        out = R.render(g, cams, model=2)
+        torch.cuda.synchronize()
+        m = parity.compare_keys(R, sc, cams)
+        # a deferred render plans from the previous count (plus a quarter)
+        out = R.render(g, cams, model=2, outputs=out, deferred=True)
+        R.status()
+        torch.cuda.synchronize()
+        assert parity.compare_keys(R, sc, cams) == m
+        for v in (1, 6):
+            px = parity.sample_pixels(cams[v], 300, seed=v)
+            parity.compare_view(out[v], sc, cams[v], 2, pixels=px)
         print("instances", m)
     finally:
         R.close()

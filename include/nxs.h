@@ -256,7 +256,7 @@ nxs_status nxs_render_forward(nxs_context* ctx, const nxs_gaussians* g,
  * holds until the process ends; nothing is allocated, on the device or in
  * pinned host memory, and no state is kept.
  *   Arguments as for nxs_render_forward; opts.flags must be 0.
- *   Size limit: the render's workspace must fit the 64 MiB -- about 100
+ *   Size limit: the render's workspace must fit the 64 MiB -- about 90
  *   bytes per Gaussian per view, 16 per tile instance, 16 per tile, plus the
  *   sort's digit counts (e.g. 150,000 Gaussians at 1920x1080 with about a
  *   million instances).  A render beyond it fails with NXS_ECAPACITY and a

@@ -75,7 +75,7 @@ struct nxs_context {
   bool noalloc = false;   // the no-alloc entry point: no events, no pinned memory
   // workspace
   DevBuf views, counters, partials, status;
-  DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, tinfo, nt_sorted, rect_sorted, prec;
+  DevBuf depth_key, dsort_a, dsort_b, slot_a, slot_b, trect, nt_sorted, rect_sorted, prec;
   DevBuf scan_local, block_sums, counts;
   DevBuf inst_tile, inst_tile_alt, inst_val, inst_val_alt;
   DevBuf ranges, pstate, gslot, order;
@@ -224,7 +224,7 @@ nxs_status ensure(nxs_context* ctx, DevBuf& b, size_t bytes, hipStream_t s) {
 void free_workspace(nxs_context* ctx, hipStream_t s) {
   DevBuf* list[] = {&ctx->views,      &ctx->counters,  &ctx->partials,      &ctx->status,
                     &ctx->depth_key,  &ctx->dsort_a,   &ctx->dsort_b,       &ctx->slot_a,
-                    &ctx->slot_b,     &ctx->tinfo,     &ctx->nt_sorted,     &ctx->rect_sorted,
+                    &ctx->slot_b,     &ctx->trect,     &ctx->nt_sorted,     &ctx->rect_sorted,
                     &ctx->prec,       &ctx->scan_local, &ctx->block_sums,   &ctx->counts,
                     &ctx->inst_tile,  &ctx->inst_tile_alt, &ctx->inst_val,  &ctx->inst_val_alt,
                     &ctx->ranges,     &ctx->pstate,    &ctx->gslot,         &ctx->order};
@@ -493,7 +493,7 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
   if ((st = ensure(ctx, ctx->depth_key, 4 * S, s)) || (st = ensure(ctx, ctx->dsort_a, 4 * S, s)) ||
       (st = ensure(ctx, ctx->dsort_b, 4 * S, s)) ||
       (st = ensure(ctx, ctx->slot_a, 4 * S, s)) || (st = ensure(ctx, ctx->slot_b, 4 * S, s)) ||
-      (st = ensure(ctx, ctx->tinfo, 16 * S, s)) || (st = ensure(ctx, ctx->nt_sorted, 4 * S, s)) ||
+      (st = ensure(ctx, ctx->trect, 8 * S, s)) || (st = ensure(ctx, ctx->nt_sorted, 4 * S, s)) ||
       (st = ensure(ctx, ctx->rect_sorted, 8 * S, s)) ||
       (st = ensure(ctx, ctx->prec, 48 * S, s)) || (st = ensure(ctx, ctx->scan_local, 4 * S, s)) ||
       (st = ensure(ctx, ctx->block_sums, 4 * scan_blocks_size(S), s)) ||
@@ -513,7 +513,7 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     if ((st = ensure(ctx, ctx->counts, 4 * radix_counts_words(std::max<int64_t>(S, icap)), s)))
       return st;
   }
-  ProjDev proj{P<uint32_t>(ctx->depth_key), P<uint4>(ctx->tinfo), P<float4>(ctx->prec)};
+  ProjDev proj{P<uint32_t>(ctx->depth_key), P<uint2>(ctx->trect), P<float4>(ctx->prec)};
   GaussDev gd{g->means, g->scales, g->quats, g->opacities, g->sh, g->n, g->sh_degree};
   Counters* dcount = P<Counters>(ctx->counters);
   const float kappa2 = (float)(2.0 * std::log(1.0 / (double)c.alpha_min));
@@ -569,7 +569,7 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     return radix_sort_planned(P<uint32_t>(ctx->depth_key), nullptr, P<uint32_t>(ctx->dsort_a),
                               P<uint32_t>(ctx->slot_a), P<uint32_t>(ctx->dsort_b),
                               P<uint32_t>(ctx->slot_b), S, dcount->plan, first,
-                              P<uint32_t>(ctx->counts), proj.tinfo,
+                              P<uint32_t>(ctx->counts), proj.trect,
                               P<uint32_t>(ctx->nt_sorted), P<uint2>(ctx->rect_sorted), s);
   };
   // (tile first: no depth sort; the slots are emitted in their own order)
@@ -582,11 +582,11 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
   const uint2* rect_in = tile_first ? nullptr : P<uint2>(ctx->rect_sorted);
   HIP_TRY(mark(3));
   // 2. emission (in depth order, or in slot order), into the buffers as they are
-  launch_emit_scan(nt_in, proj.tinfo, S, P<uint32_t>(ctx->scan_local),
+  launch_emit_scan(nt_in, proj.trect, S, P<uint32_t>(ctx->scan_local),
                    P<uint32_t>(ctx->block_sums), s);
   const uint32_t cap32 = (uint32_t)instance_capacity(ctx);
   if (cap32 > 0)
-    launch_emit_write(sorted_slots, rect_in, proj.tinfo, S, g->n, dviews,
+    launch_emit_write(sorted_slots, rect_in, proj.trect, S, g->n, dviews,
                       P<uint32_t>(ctx->scan_local), P<uint32_t>(ctx->block_sums), cap32,
                       P<uint32_t>(ctx->inst_tile), P<uint32_t>(ctx->inst_val), s);
   HIP_TRY(hipGetLastError());
@@ -616,11 +616,11 @@ nxs_status forward(nxs_context* ctx, const nxs_gaussians* g, const nxs_camera* c
     if ((st = grow_instances(ctx, M, S, s))) return st;
     if (resort) {
       (void)depth_sort(0);
-      launch_emit_scan(nt_in, proj.tinfo, S, P<uint32_t>(ctx->scan_local),
+      launch_emit_scan(nt_in, proj.trect, S, P<uint32_t>(ctx->scan_local),
                        P<uint32_t>(ctx->block_sums), s);
     }
     if (resort || M > cap32)   // emit (again) into the grown buffers
-      launch_emit_write(sorted_slots, rect_in, proj.tinfo, S, g->n, dviews,
+      launch_emit_write(sorted_slots, rect_in, proj.trect, S, g->n, dviews,
                         P<uint32_t>(ctx->scan_local), P<uint32_t>(ctx->block_sums),
                         (uint32_t)M, P<uint32_t>(ctx->inst_tile), P<uint32_t>(ctx->inst_val),
                         s);
@@ -1318,10 +1318,10 @@ nxs_status nxs_inspect_projection(nxs_context* ctx, int32_t view, uint32_t* dept
   if (n == 0) return NXS_OK;
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipEventSynchronize(ctx->done));
-  std::vector<uint4> rect(n);
+  std::vector<uint2> rect(n);
   HIP_TRY(hipMemcpy(depth_bits_host, (uint32_t*)ctx->depth_key.p + view * n, 4 * n,
                     hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(rect.data(), (uint4*)ctx->tinfo.p + view * n, 16 * n,
+  HIP_TRY(hipMemcpy(rect.data(), (uint2*)ctx->trect.p + view * n, 8 * n,
                     hipMemcpyDeviceToHost));
   for (int64_t i = 0; i < n; ++i) {
     if (rect[i].x == 0xFFFFFFFFu) {

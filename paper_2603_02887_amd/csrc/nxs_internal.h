@@ -39,9 +39,9 @@ struct GaussDev {
 // Per projected slot (slot = view * n + gaussian) arrays written by the projection.
 struct ProjDev {
   uint32_t* depth_key;      // float32 depth bits; 0xFFFFFFFF when culled
-  // tile record (tx0 | tx1 << 16, ty0 | ty1 << 16, covered tiles, 0); the
-  // rectangle is all ones and the count 0 when culled
-  uint4* tinfo;
+  // tile rectangle (tx0 | tx1 << 16, ty0 | ty1 << 16), all ones when culled;
+  // the covered tiles are rect_tile_count(trect[slot])
+  uint2* trect;
   // 3 float4 per slot:
   //   (u_hi, u_lo, v_hi, v_lo)  image-plane centre as float hi + lo parts
   //   (A', B', C', log2 aleph)  log2(alpha) = log2 aleph + A' dx^2 + B' dx dy + C' dy^2
@@ -85,6 +85,12 @@ struct DeferCheck {
   DeferredStatus* status_host;   // pinned copy of it after the update, or null
   Counters* counters_host;       // pinned copy of the counters, or null
 };
+
+// The tiles a slot's rectangle covers (0 for a culled slot).
+__device__ __forceinline__ uint32_t rect_tile_count(uint2 r) {
+  if (r.x == 0xFFFFFFFFu) return 0u;
+  return ((r.x >> 16) - (r.x & 0xFFFFu) + 1u) * ((r.y >> 16) - (r.y & 0xFFFFu) + 1u);
+}
 
 // The instance count a kernel after the emission works on: 0 for a failed
 // deferred render.
@@ -141,26 +147,26 @@ int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
 // passes 1..3 only, which is right only if the plan leaves pass 0 inactive
 // (the caller checks plan[0] once it has read the counters, and sorts again
 // with first_pass = 0 otherwise).  The result is in (k1, v1); returns 1.
-// The last pass also writes, in sorted order, each value's tile count and
-// rectangle from `tinfo` (indexed by value) into nt_out / rect_out.
+// The last pass also writes, in sorted order, each value's tile rectangle
+// from `trect` (indexed by value) and its tile count into rect_out / nt_out.
 int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
                        uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
                        const uint32_t* plan, int first_pass, uint32_t* counts,
-                       const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s);
+                       const uint2* trect, uint32_t* nt_out, uint2* rect_out, hipStream_t s);
 
 // Exclusive scan of ntiles in sorted-slot order and emission of instances.
 size_t scan_blocks_size(int64_t n);
 // Exclusive scan of the depth-sorted tile counts (nt_sorted), or with
-// nt_sorted null of the counts in the tile records in slot order, per block
+// nt_sorted null of the tile counts of the rectangles in slot order, per block
 // of 512 slots (block totals in block_sums; scanned across blocks here
 // only when there are more blocks than the emission sums itself).
-void launch_emit_scan(const uint32_t* nt_sorted, const uint4* tinfo, int64_t n_slots,
+void launch_emit_scan(const uint32_t* nt_sorted, const uint2* trect, int64_t n_slots,
                       uint32_t* scan_local, uint32_t* block_sums, hipStream_t s);
 // Writes the instances of the depth-sorted slots (rectangles in
 // rect_sorted), or with sorted_slots null of the slots in their own order
-// (rectangles in tinfo); instances at positions >= capacity are not written.
+// (rectangles in trect); instances at positions >= capacity are not written.
 void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted,
-                       const uint4* tinfo, int64_t n_slots, int32_t n_gauss,
+                       const uint2* trect, int64_t n_slots, int32_t n_gauss,
                        const ViewDev* views, const uint32_t* scan_local,
                        const uint32_t* block_sums, uint32_t capacity, uint32_t* inst_tile,
                        uint32_t* inst_val, hipStream_t s);

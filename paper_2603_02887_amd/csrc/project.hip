@@ -378,11 +378,11 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     uint2 rect = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
     uint32_t nt = 0;
     if (kg.visible) {
-      nt = (uint32_t)((kg.tx1 - kg.tx0 + 1) * (kg.ty1 - kg.ty0 + 1));
       dmin = min(dmin, kg.depth_bits);
       dmax = max(dmax, kg.depth_bits);
       rect = make_uint2((uint32_t)kg.tx0 | ((uint32_t)kg.tx1 << 16),
                         (uint32_t)kg.ty0 | ((uint32_t)kg.ty1 << 16));
+      nt = rect_tile_count(rect);
       // ---- composite footprint ----------------------------------------------
       // Sigma2D = A A^T + 0.3 I from the recipe's A (float32).  Its determinant
       // by Cauchy-Binet, |A0 x A1|^2 + 0.3 (|A0|^2 + |A1|^2) + 0.09, is a sum
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
       rec[2] = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(hx | (hy << 16)));
     }
     out.depth_key[slot] = kg.depth_bits;
-    out.tinfo[slot] = make_uint4(rect.x, rect.y, nt, 0u);
+    out.trect[slot] = rect;
     nt_sum += nt;
   }
   // block reductions: instance total and visible depth-bit range

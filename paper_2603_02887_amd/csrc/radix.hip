@@ -214,7 +214,8 @@ __global__ __launch_bounds__(kRThreads) void rx_scan(uint32_t* __restrict__ coun
 }
 
 // vals_in == nullptr: the values are the input positions.  The last pass
-// also writes the payload from `tinfo` when it is given.
+// also writes each value's tile rectangle (from `trect`) and tile count when
+// trect is given.
 template <int ITEMS>
 __global__ __launch_bounds__(kRThreads) void rx_scatter(
     const uint32_t* keys_in, const uint32_t* vals_in, const uint32_t* keys_first,
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     uint32_t* __restrict__ vals_out, int64_t n, int shift, int width,
     const uint32_t* __restrict__ plan, int pass, uint32_t nchunks, uint32_t per,
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
-    const uint4* __restrict__ tinfo, uint32_t* __restrict__ nt_out,
+    const uint2* __restrict__ trect, uint32_t* __restrict__ nt_out,
     uint2* __restrict__ rect_out, const Counters* __restrict__ dn) {
   // Per-wave digit counts (at most 64 * ITEMS) and each digit's local start
   // in the chunk (at most 256 * ITEMS) are kept in 16 bits: at 4,096 keys
@@ -326,10 +327,10 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
       const uint32_t g = s_delta[d] + (uint32_t)i;
       keys_out[g] = k;
       vals_out[g] = s_val[i];
-      if (tinfo) {   // the slot's tile record, now in sorted order
-        const uint4 ti = tinfo[s_val[i]];
-        nt_out[g] = ti.z;
-        rect_out[g] = make_uint2(ti.x, ti.y);
+      if (trect) {   // the slot's tile rectangle, now in sorted order
+        const uint2 r = trect[s_val[i]];
+        nt_out[g] = rect_tile_count(r);
+        rect_out[g] = r;
       }
     }
     __syncthreads();   // the LDS tables are rebuilt for the next chunk
@@ -709,7 +710,7 @@ namespace {
 int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, uint32_t* v0,
                uint32_t* k1, uint32_t* v1, int64_t n, int first, int passes,
                const int* shifts, const int* widths, const uint32_t* plan, uint32_t* counts,
-               const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s,
+               const uint2* trect, uint32_t* nt_out, uint2* rect_out, hipStream_t s,
                const Counters* dn, int64_t n_plan) {
   // n bounds the keys (the counts layout); the grid is planned for n_plan
   // keys (with dn, the count expected on the device) and loops beyond it
@@ -736,7 +737,7 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
                          nchunks, totals, width, plan, p, n, dn);
       hipLaunchKernelGGL(rx_scatter<kRItemsLarge>, dim3(grid), dim3(kRThreads), 0, s, kin, vin,
                          keys_in, vals_in, kout, vout, n, shift, width, plan, p, nchunks, per,
-                         counts, totals, last ? tinfo : nullptr, nt_out, rect_out, dn);
+                         counts, totals, last ? trect : nullptr, nt_out, rect_out, dn);
     } else {
       hipLaunchKernelGGL(rx_count<kRItemsSmall>, dim3(grid), dim3(kRThreads), 0, s, kin,
                          keys_in, n, shift, width, plan, p, nchunks, per, counts, dn);
@@ -744,7 +745,7 @@ int run_passes(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
                          nchunks, totals, width, plan, p, n, dn);
       hipLaunchKernelGGL(rx_scatter<kRItemsSmall>, dim3(grid), dim3(kRThreads), 0, s, kin, vin,
                          keys_in, vals_in, kout, vout, n, shift, width, plan, p, nchunks, per,
-                         counts, totals, last ? tinfo : nullptr, nt_out, rect_out, dn);
+                         counts, totals, last ? trect : nullptr, nt_out, rect_out, dn);
     }
     kin = kout;
     vin = vout;
@@ -774,10 +775,10 @@ int radix_sort(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0, u
 int radix_sort_planned(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* k0,
                        uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
                        const uint32_t* plan, int first_pass, uint32_t* counts,
-                       const uint4* tinfo, uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
+                       const uint2* trect, uint32_t* nt_out, uint2* rect_out, hipStream_t s) {
   if (n <= 0) return 1;
   return run_passes(keys_in, vals_in, k0, v0, k1, v1, n, first_pass, kPlanPasses, nullptr,
-                    nullptr, plan, counts, tinfo, nt_out, rect_out, s, nullptr, n);
+                    nullptr, plan, counts, trect, nt_out, rect_out, s, nullptr, n);
 }
 
 void launch_tile_depth_sort(const uint2* ranges, int64_t n_tiles, const uint32_t* depth_key,

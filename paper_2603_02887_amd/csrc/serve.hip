@@ -85,7 +85,7 @@ double workspace_estimate(const Scene& sc, const std::vector<const Request*>& ba
   }
   const double slots = (double)sc.g.n * (double)batch.size();
   const double inst = sc.inst_per_px * pixels;
-  return 88.0 * slots + 20.0 * inst + 12.0 * tiles + (1 << 20);
+  return 92.0 * slots + 20.0 * inst + 12.0 * tiles + (1 << 20);
 }
 
 double pixels_of(const std::vector<const Request*>& batch) {

@@ -53,9 +53,9 @@ constexpr int kScanChunk = kScanBlock * kScanItems;
 
 // Block-local exclusive scan of the slots' tile counts: nt_sorted in
 // depth-sorted order, or (nt_sorted null) the counts in the projection's
-// tile records, in slot order.
+// rectangles, in slot order.
 __global__ __launch_bounds__(kScanBlock) void scan_local_kernel(
-    const uint32_t* __restrict__ nt_sorted, const uint4* __restrict__ tinfo, int64_t n,
+    const uint32_t* __restrict__ nt_sorted, const uint2* __restrict__ trect, int64_t n,
     uint32_t* __restrict__ local, uint32_t* __restrict__ block_sums) {
   __shared__ uint32_t s_tmp[kScanBlock / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_local_kernel(
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     int64_t i = base + k;
-    v[k] = i < n ? (nt_sorted ? nt_sorted[i] : tinfo[i].z) : 0u;
+    v[k] = i < n ? (nt_sorted ? nt_sorted[i] : rect_tile_count(trect[i])) : 0u;
     sum += v[k];
   }
   uint32_t tot;
@@ -123,10 +123,10 @@ constexpr int kInlineBlocks = 2048;
 constexpr uint32_t kEmitWindow = 8192;   // positions per owner map (16 KB)
 constexpr uint32_t kEmitShort = 32;      // longer runs are marked by a whole wave
 
-// sorted_slots null: the slots in their own order, rectangles from tinfo.
+// sorted_slots null: the slots in their own order, rectangles from trect.
 __global__ __launch_bounds__(kScanBlock) void emit_kernel(
     const uint32_t* __restrict__ sorted_slots, const uint2* __restrict__ rect_sorted,
-    const uint4* __restrict__ tinfo, int64_t n,
+    const uint2* __restrict__ trect, int64_t n,
     int32_t n_gauss, int n_views, const ViewDev* __restrict__ views,
     const uint32_t* __restrict__ local, const uint32_t* __restrict__ block_sums, int nblocks,
     uint32_t capacity, uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_val) {
@@ -178,8 +178,7 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
     } else if (sorted_slots) {
       rect_r[q] = rect_sorted[b0 + k];
     } else {
-      const uint4 ti = tinfo[b0 + k];
-      rect_r[q] = make_uint2(ti.x, ti.y);
+      rect_r[q] = trect[b0 + k];
     }
   }
   if (!inline_sum) block_offset();
@@ -302,11 +301,11 @@ size_t scan_blocks_size(int64_t n) {
   return 2 * (size_t)((n + kScanChunk - 1) / kScanChunk) + 1;
 }
 
-void launch_emit_scan(const uint32_t* nt_sorted, const uint4* tinfo, int64_t n_slots,
+void launch_emit_scan(const uint32_t* nt_sorted, const uint2* trect, int64_t n_slots,
                       uint32_t* scan_local, uint32_t* block_sums, hipStream_t s) {
   if (n_slots <= 0) return;
   const int nblocks = (int)((n_slots + kScanChunk - 1) / kScanChunk);
-  hipLaunchKernelGGL(scan_local_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, nt_sorted, tinfo,
+  hipLaunchKernelGGL(scan_local_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, nt_sorted, trect,
                      n_slots, scan_local, block_sums);
   if (nblocks > kInlineBlocks)
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(kSumThreads), 0, s, block_sums,
@@ -314,7 +313,7 @@ void launch_emit_scan(const uint32_t* nt_sorted, const uint4* tinfo, int64_t n_s
 }
 
 void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted,
-                       const uint4* tinfo, int64_t n_slots, int32_t n_gauss,
+                       const uint2* trect, int64_t n_slots, int32_t n_gauss,
                        const ViewDev* views, const uint32_t* scan_local,
                        const uint32_t* block_sums, uint32_t capacity, uint32_t* inst_tile,
                        uint32_t* inst_val, hipStream_t s) {
@@ -322,7 +321,7 @@ void launch_emit_write(const uint32_t* sorted_slots, const uint2* rect_sorted,
   const int nblocks = (int)((n_slots + kScanChunk - 1) / kScanChunk);
   const int n_views = (int)(n_slots / n_gauss);
   hipLaunchKernelGGL(emit_kernel, dim3(nblocks), dim3(kScanBlock), 0, s, sorted_slots,
-                     rect_sorted, tinfo, n_slots, n_gauss, n_views, views, scan_local,
+                     rect_sorted, trect, n_slots, n_gauss, n_views, views, scan_local,
                      block_sums, nblocks, capacity, inst_tile, inst_val);
 }
 

@@ -70,11 +70,11 @@ HBM_PEAK_GBS = 8000.0
 # size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
 # kernel sources with this digest and are reported as null once those change.
 TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_stage.h", "nxs_internal.h")
-TRAFFIC = {"digest": "366497bff0df9da7a2f6bbb7176565a5406797d0df448e4379b12777e3f7fd1f",
+TRAFFIC = {"digest": "a98d3f8f71799fca3ea0cda04c95ffdc5ebf8608e8c6abb24ba1ce9b1b9b9db1",
            "tile": "16x16",
            "bytes": {
-               "queue": {0: 502216918, 1: 254830257, 2: 288599259, 3: 242061326},
-               "tiles": {0: 225049701, 1: 131736034, 2: 145836523, 3: 127258251}}}
+               "queue": {0: 501264207, 1: 253544478, 2: 285084033, 3: 239762078},
+               "tiles": {0: 225114184, 1: 131596968, 2: 145841819, 3: 127135629}}}
 
 
 def measured_traffic(model, tile, schedule):

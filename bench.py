@@ -88,6 +88,61 @@ def measured_traffic(model, tile, schedule):
     return TRAFFIC["bytes"].get(schedule, {}).get(model)
 
 
+def depth_sort_passes(scene, cam):
+    """Digit passes of the depth sort for this frame: three 9-bit digits when
+    the float32 depth bits of the Gaussians in front of the camera vary in at
+    most 27 bits, else four (the device plans from the visible ones; a few
+    culled off-screen ones could only narrow the range)."""
+    z = (scene.means.astype(np.float32) @ np.asarray(cam.R, np.float32)[2]
+         + np.float32(cam.t[2])).astype(np.float32)
+    bits = z[z > cam.znear].view(np.uint32)
+    if bits.size == 0:
+        return 3
+    nbits = int(bits.min() ^ bits.max()).bit_length()
+    return 3 if nbits <= 27 else 4
+
+
+def stage_roofline(m, scene, cam, conf, counts, od, stage_ms, thr_ms):
+    """T_roof = sum over stages of max(algorithmic bytes / 8 TB/s, lane-ops /
+    39.3 T lane-ops/s), per stage and overall, against the stages measured
+    alone and against one render's share of the throughput mode.  Algorithmic
+    bytes are those this pipeline must move: S slots (one view), M tile
+    instances, T tiles, P pixels; the composite's lane-ops are 24 per
+    composited pair."""
+    M, T = counts
+    S = scene.n
+    P = cam.width * cam.height
+    K = (scene.sh_degree + 1) ** 2
+    dpass = depth_sort_passes(scene, cam)
+    tpass = -(-max(1, int(T - 1).bit_length()) // 9)
+    b = {"project": (56 + 12 * K) * scene.n + 60 * S,      # inputs; record, depth, rectangle
+         "depth_sort": 16 * S * dpass + 20 * S,           # passes; rectangles laid out in order
+         "emit": 24 * S + 8 * M,                          # scan and slot records; instances
+         "tile_sort": 16 * M * tpass,
+         "ranges": 4 * M + 8 * T,
+         "composite": 52 * M + 20 * P}                    # slot index + record per entry; image
+    if conf["sort_order"] == "tile_first":                # per-tile depth sort in "ranges"
+        b["ranges"] += (16 * dpass + 4) * M
+        b["depth_sort"] = 0
+    ops = {"composite": od * SLOTS_PER_PAIR}
+    stages = {}
+    roof_total = 0.0
+    for k, ms in stage_ms.items():
+        t_bytes = b.get(k, 0) / (HBM_PEAK_GBS * 1e9)
+        t_ops = ops.get(k, 0) / (VALU_SLOT_PEAK_T * 1e12)
+        t_roof = max(t_bytes, t_ops) * 1e3
+        roof_total += t_roof
+        stages[k] = {"bytes": b.get(k, 0), "lane_ops": ops.get(k, 0),
+                     "bound": "alu" if t_ops > t_bytes else "hbm",
+                     "roof_ms": t_roof, "measured_ms": ms,
+                     "frac": t_roof / ms if ms > 0 else None}
+    meas = sum(stage_ms.values())
+    return {"stages": stages, "roof_ms": roof_total, "measured_ms": meas,
+            "frac": roof_total / meas, "throughput_ms_per_render": thr_ms * 1e3,
+            "frac_throughput": roof_total / (thr_ms * 1e3),
+            "depth_sort_passes": dpass, "tile_sort_passes": tpass}
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -561,6 +616,7 @@ def main():
     R.set_timing(True)
     lat = {m: [] for m in range(4)}
     stages = {m: [] for m in range(4)}
+    counts = {}
     for _ in range(args.steps):
         for m in range(4):
             t0 = time.perf_counter()
@@ -568,6 +624,7 @@ def main():
             torch.cuda.synchronize()
             lat[m].append(time.perf_counter() - t0)
             stages[m].append(R.stage_times())
+            counts[m] = R.counts()   # (instances, tiles) of this model's configuration
     R.set_timing(False)
 
     per_model = {}
@@ -616,6 +673,9 @@ def main():
 
     renders = 4 * args.steps
     value = W * H * renders / total / 1e6
+    stage_roof = {MODELS[m]: stage_roofline(m, scene, cam, cfg[m], counts[m], od_sum[m],
+                                            stage_mean[m], total / renders)
+                  for m in range(4)}
     exp_ms = per_model["exponential"]["ms_per_render"]
     for name in MODELS[1:]:
         per_model[name]["speedup_vs_exponential"] = exp_ms / per_model[name]["ms_per_render"]
@@ -655,6 +715,7 @@ def main():
         "throughput_modes_mpix_per_s": {k: W * H * renders / v / 1e6 for k, v in modes.items()},
         "per_model": per_model,
         "roofline": roofline,
+        "stage_roofline": stage_roof,
         "measured_peaks": {"fp32_fma_tflops": peaks["fp32_fma_tflops"],
                            "copy_gbs": peaks["copy_gbs"],
                            "datasheet": {"fp32_tflops": FP32_VALU_PEAK_TFLOPS,

@@ -542,6 +542,13 @@ def main():
                 for m, c in cfg.items()}
     if no_order != cfg:
         cfg_sets["tuned_tile_schedule"] = no_order
+    # the tile schedule with the library's default tiles and lists for every
+    # model: with renders in flight, the tuner's per-render choices (timed one
+    # render at a time) need not be the fastest mix
+    plain_tiles = {m: {"tile": (16, 16), "schedule": "tiles", "lds_batch": 64,
+                       "sort_order": "depth_first"} for m in range(4)}
+    if plain_tiles not in cfg_sets.values():
+        cfg_sets["tile_schedule_16x16"] = plain_tiles
     for conf in cfg_sets.values():
         for m in range(4):
             for c, o in zip(ctxs, ctx_outs):

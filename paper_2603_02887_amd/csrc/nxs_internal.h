@@ -86,6 +86,24 @@ struct DeferCheck {
   Counters* counters_host;       // pinned copy of the counters, or null
 };
 
+// Inclusive sum over the lanes of a wave (every lane active): within each
+// 16-lane row by four DPP row shifts (a lane whose source lies before its
+// row adds 0), then the three lower rows' totals, read by readlane.  Integer
+// sums: the same result as any other order.
+__device__ __forceinline__ uint32_t wave_inclusive_scan_u32(uint32_t x) {
+  int v = (int)x;
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+  const int r0 = __builtin_amdgcn_readlane(v, 15);
+  const int r1 = __builtin_amdgcn_readlane(v, 31);
+  const int r2 = __builtin_amdgcn_readlane(v, 47);
+  const int row = (int)(threadIdx.x & 63) >> 4;
+  v += (row >= 1 ? r0 : 0) + (row >= 2 ? r1 : 0) + (row >= 3 ? r2 : 0);
+  return (uint32_t)v;
+}
+
 // The tiles a slot's rectangle covers (0 for a culled slot).
 __device__ __forceinline__ uint32_t rect_tile_count(uint2 r) {
   if (r.x == 0xFFFFFFFFu) return 0u;

@@ -189,11 +189,22 @@ __device__ void fold_partials(const uint4* partials, int nblocks, Counters* c,
   __shared__ uint32_t s_mn[NT / 64], s_mx[NT / 64];
   unsigned long long tot = 0;
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-  for (int b = threadIdx.x; b < nblocks; b += NT) {
-    const uint4 p = partials[b];
-    tot += p.x;
-    mn = min(mn, p.y);
-    mx = max(mx, p.z);
+  // rounds of kFoldLoads partials per thread, each round's loads issued
+  // before the first is used
+  constexpr int kFoldLoads = 4;
+  for (int b0 = 0; b0 < nblocks; b0 += NT * kFoldLoads) {
+    uint4 p[kFoldLoads];
+#pragma unroll
+    for (int q = 0; q < kFoldLoads; ++q) {
+      const int b = b0 + q * NT + (int)threadIdx.x;
+      p[q] = b < nblocks ? partials[b] : make_uint4(0u, 0xFFFFFFFFu, 0u, 0u);
+    }
+#pragma unroll
+    for (int q = 0; q < kFoldLoads; ++q) {
+      tot += p[q].x;
+      mn = min(mn, p[q].y);
+      mx = max(mx, p[q].z);
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {

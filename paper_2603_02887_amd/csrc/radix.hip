@@ -156,12 +156,7 @@ __global__ __launch_bounds__(kRThreads) void rx_count(const uint32_t* keys,
 
 __device__ __forceinline__ uint32_t rx_block_scan(uint32_t x, uint32_t* s_tmp, uint32_t* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t incl = x;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
+  const uint32_t incl = wave_inclusive_scan_u32(x);
   if (lane == 63) s_tmp[wid] = incl;
   __syncthreads();
   uint32_t off = 0, tot = 0;
@@ -592,13 +587,7 @@ __device__ void seg_sort_wave(uint32_t* list, int m, const uint32_t* __restrict_
       uint32_t local = 0;
       for (int i = 0; i < per; ++i)
         if (d0 + i < nd) local += L.cnt[d0 + i];
-      uint32_t incl = local;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-      }
-      uint32_t run = incl - local;
+      uint32_t run = wave_inclusive_scan_u32(local) - local;
       wave_lds_fence();
       for (int i = 0; i < per; ++i)
         if (d0 + i < nd) {

@@ -25,12 +25,7 @@ template <int NW = 4>   // waves in the work-group
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s_tmp,
                                                          uint32_t* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t incl = x;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
+  const uint32_t incl = wave_inclusive_scan_u32(x);
   if (lane == 63) s_tmp[wid] = incl;
   __syncthreads();
   uint32_t wave_off = 0, tot = 0;
@@ -147,9 +142,19 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
   uint32_t out0 = 0, out1 = 0;
   auto block_offset = [&]() {
     if (inline_sum) {
-      // the sum of the totals of the blocks before this one
+      // the sum of the totals of the blocks before this one (all of a
+      // thread's loads issued before the first is added)
+      constexpr int kInlinePerT = kInlineBlocks / kScanBlock;
+      static_assert(kInlineBlocks % kScanBlock == 0, "whole rounds of block totals");
+      uint32_t v[kInlinePerT];
+#pragma unroll
+      for (int q = 0; q < kInlinePerT; ++q) {
+        const int b = q * kScanBlock + threadIdx.x;
+        v[q] = b < (int)blockIdx.x ? block_sums[b] : 0u;
+      }
       uint32_t part = 0;
-      for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBlock) part += block_sums[b];
+#pragma unroll
+      for (int q = 0; q < kInlinePerT; ++q) part += v[q];
       uint32_t all;
       (void)block_exclusive_scan(part, s_tmp, &all);
       out0 = all;

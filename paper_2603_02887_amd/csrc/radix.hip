@@ -220,14 +220,13 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals,
     const uint2* __restrict__ trect, uint32_t* __restrict__ nt_out,
     uint2* __restrict__ rect_out, const Counters* __restrict__ dn) {
-  // Per-wave digit counts (at most 64 * ITEMS) and each digit's local start
-  // in the chunk (at most 256 * ITEMS) are kept in 16 bits: at 4,096 keys
-  // the tables then leave room for four work-groups per CU instead of three.
+  // Per-wave digit counts (at most 64 * ITEMS), then each wave's first
+  // position per digit in the chunk (below 256 * ITEMS), are kept in 16 bits:
+  // at 4,096 keys the tables then leave room for four work-groups per CU.
   static_assert(kRThreads * ITEMS <= 0xFFFF, "local positions must fit 16 bits");
   __shared__ uint32_t s_key[(kRThreads * ITEMS)];
   __shared__ uint32_t s_val[(kRThreads * ITEMS)];
   __shared__ uint16_t s_wave[kRWaves][kRBins];
-  __shared__ uint16_t s_lbase[kRBins];
   __shared__ uint32_t s_delta[kRBins];   // global minus local start of each digit's run
   __shared__ uint32_t s_tmp[kRWaves];
 
@@ -289,17 +288,25 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
       }
     }
     __syncthreads();
-    // local start of each digit's run in the chunk
+    // local start of each digit's run in the chunk; each wave's count of a
+    // digit then becomes the wave's first position for that digit (the run's
+    // start plus the digit's keys in the waves before it)
     {
-      uint32_t cnt0 = 0, cnt1 = 0;
+      uint32_t cnt0 = 0, cnt1 = 0, before0[kRWaves], before1[kRWaves];
+#pragma unroll
       for (int w = 0; w < kRWaves; ++w) {
+        before0[w] = cnt0;
+        before1[w] = cnt1;
         cnt0 += s_wave[w][d0];
         cnt1 += s_wave[w][d1];
       }
       uint32_t all;
       const uint32_t ex = rx_block_scan(cnt0 + cnt1, s_tmp, &all);
-      s_lbase[d0] = (uint16_t)ex;
-      s_lbase[d1] = (uint16_t)(ex + cnt0);
+#pragma unroll
+      for (int w = 0; w < kRWaves; ++w) {
+        s_wave[w][d0] = (uint16_t)(ex + before0[w]);
+        s_wave[w][d1] = (uint16_t)(ex + cnt0 + before1[w]);
+      }
       s_delta[d0] = gbase0 - ex;
       s_delta[d1] = gbase1 - (ex + cnt0);
     }
@@ -308,9 +315,7 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
     for (int r = 0; r < ITEMS; ++r) {
       const int li = wid * (64 * ITEMS) + r * 64 + lane;
       if (li < chunk_n) {
-        const uint32_t d = dig[r];
-        uint32_t off = s_lbase[d] + rank[r];
-        for (int w = 0; w < wid; ++w) off += s_wave[w][d];
+        const uint32_t off = s_wave[wid][dig[r]] + rank[r];
         s_key[off] = k_reg[r];
         s_val[off] = v_reg[r];
       }

@@ -238,9 +238,9 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
   const int lane = t & 63, wid = t >> 6;
   const uint32_t mask = (1u << width) - 1u;
   const int nd = 1 << width;
+  static_assert(sizeof(s_wave) == 16 * kRThreads, "one 16-byte store per thread clears s_wave");
   for (uint32_t c = walk.first; c < walk.end; c += walk.step) {   // (uniform per group)
-    for (int w = 0; w < kRWaves; ++w)
-      for (int d = t; d < kRBins; d += kRThreads) s_wave[w][d] = 0;
+    reinterpret_cast<uint4*>(&s_wave[0][0])[t] = make_uint4(0u, 0u, 0u, 0u);
     const int64_t base = (int64_t)c * (kRThreads * ITEMS);
     const int chunk_n = (int)min((int64_t)(kRThreads * ITEMS), n - base);
 
@@ -321,16 +321,22 @@ __global__ __launch_bounds__(kRThreads) void rx_scatter(
       }
     }
     __syncthreads();
-    for (int i = t; i < chunk_n; i += kRThreads) {
-      const uint32_t k = s_key[i];
-      const uint32_t d = (k >> shift) & mask;
-      const uint32_t g = s_delta[d] + (uint32_t)i;
-      keys_out[g] = k;
-      vals_out[g] = s_val[i];
-      if (trect) {   // the slot's tile rectangle, now in sorted order
-        const uint2 r = trect[s_val[i]];
-        nt_out[g] = rect_tile_count(r);
-        rect_out[g] = r;
+    // (unrolled by four: each group's LDS reads are issued together, and the
+    // 4,096-key chunks keep the registers of four work-groups per CU)
+#pragma unroll 4
+    for (int r = 0; r < ITEMS; ++r) {
+      const int i = r * kRThreads + t;
+      if (i < chunk_n) {
+        const uint32_t k = s_key[i];
+        const uint32_t g = s_delta[(k >> shift) & mask] + (uint32_t)i;
+        const uint32_t v = s_val[i];
+        keys_out[g] = k;
+        vals_out[g] = v;
+        if (trect) {   // the slot's tile rectangle, now in sorted order
+          const uint2 rc = trect[v];
+          nt_out[g] = rect_tile_count(rc);
+          rect_out[g] = rc;
+        }
       }
     }
     __syncthreads();   // the LDS tables are rebuilt for the next chunk

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kSumThreads) void scan_blocks_kernel(uint32_t* __re
 // the blocks before them (no separate scan launch); beyond it the totals are
 // scanned by scan_blocks_kernel first.
 constexpr int kInlineBlocks = 2048;
-constexpr uint32_t kEmitWindow = 8192;   // positions per owner map (16 KB)
+constexpr uint32_t kEmitWindow = 4096;   // positions per owner map (8 KB)
 constexpr uint32_t kEmitShort = 32;      // longer runs are marked by a whole wave
 
 // sorted_slots null: the slots in their own order, rectangles from trect.

@@ -70,11 +70,11 @@ HBM_PEAK_GBS = 8000.0
 # size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
 # kernel sources with this digest and are reported as null once those change.
 TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_stage.h", "nxs_internal.h")
-TRAFFIC = {"digest": "a98d3f8f71799fca3ea0cda04c95ffdc5ebf8608e8c6abb24ba1ce9b1b9b9db1",
+TRAFFIC = {"digest": "811972389476b60cf8497713fc34d9ec27c40b1b303bb8b4a3726a1d0b974c09",
            "tile": "16x16",
            "bytes": {
-               "queue": {0: 501264207, 1: 253544478, 2: 285084033, 3: 239762078},
-               "tiles": {0: 225114184, 1: 131596968, 2: 145841819, 3: 127135629}}}
+               "queue": {0: 483835904, 1: 252552391, 2: 283843232, 3: 238860959},
+               "tiles": {0: 224983339, 1: 131538891, 2: 145888652, 3: 127188017}}}
 
 
 def measured_traffic(model, tile, schedule):

@@ -409,6 +409,52 @@ int32_t nxs_server_in_flight(const nxs_server* server);
 nxs_status nxs_server_workspace_bytes(const nxs_server* server, size_t* bytes);
 const char* nxs_server_last_error(const nxs_server* server);
 
+/* ---------------------------------------------------------------------------
+ * Pipelined renders (for callers that enqueue many independent renders back
+ * to back and want them to overlap on the device, from one object and one
+ * stream).  A pipeline holds `lanes` contexts, each with a stream of its own,
+ * and deals consecutive renders to them in turn: one render's latency-bound
+ * sort kernels then run beside another's projection or composite.  Images
+ * are those nxs_render_forward renders (Sec. 4), bitwise.
+ *
+ *   nxs_pipeline_create: lanes in 1..8; alloc / free / user as for nxs_create
+ *     (every lane's workspace comes from them; both NULL: each lane's own
+ *     stream-ordered pool).  The streams are created at the default priority.
+ *   nxs_pipeline_render: as nxs_render_forward without backward state.  The
+ *     render waits for the work already enqueued on `stream` (an event) and
+ *     runs on the next lane's stream; `stream` itself does not wait for it.
+ *     The outputs are complete, and the inputs may be changed or freed, only
+ *     after nxs_pipeline_join has made a stream wait for the lanes (and that
+ *     stream has reached the join).  Renders in flight at the same time must
+ *     write distinct outputs.  With NXS_FLAG_DEFERRED no call waits on the
+ *     host; nxs_pipeline_status then reports renders that outgrew their lane.
+ *     Errors as nxs_render_forward (message: nxs_pipeline_last_error); a lane
+ *     that fails is used again by the next call.
+ *   nxs_pipeline_join: makes `stream` wait for every render enqueued so far
+ *     (nothing waits on the host).
+ *   nxs_pipeline_status: nxs_forward_status of every lane (waits for them on
+ *     the host): NXS_OK, or NXS_ECAPACITY if a deferred render outgrew its
+ *     lane's workspace; every lane has then grown to the largest count
+ *     needed (within its workspace limit), so rendering it again succeeds on
+ *     any lane.  (A render that needed a four-pass depth sort where three
+ *     were launched is reported the same way; each lane then launches four
+ *     once one of its own renders has needed them.)  needed (may be NULL):
+ *     the largest instance count needed.
+ *   nxs_pipeline_destroy: waits for the lanes, then frees them.
+ * ------------------------------------------------------------------------- */
+typedef struct nxs_pipeline nxs_pipeline;
+
+nxs_status nxs_pipeline_create(nxs_pipeline** pipeline, int device, int32_t lanes,
+                               nxs_alloc_fn alloc, nxs_free_fn free, void* user);
+nxs_status nxs_pipeline_destroy(nxs_pipeline* pipeline);
+nxs_status nxs_pipeline_render(nxs_pipeline* pipeline, const nxs_gaussians* g,
+                               const nxs_camera* cams, int32_t n_views,
+                               const nxs_render_opts* opts, const nxs_image* out,
+                               void* stream);
+nxs_status nxs_pipeline_join(nxs_pipeline* pipeline, void* stream);
+nxs_status nxs_pipeline_status(nxs_pipeline* pipeline, int64_t* needed);
+const char* nxs_pipeline_last_error(const nxs_pipeline* pipeline);
+
 /* Message for the last non-OK status returned on this context ("" if none).
  * The pointer stays valid until the next call on the context. */
 const char* nxs_last_error(const nxs_context* ctx);

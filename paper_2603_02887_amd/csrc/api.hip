@@ -266,6 +266,19 @@ nxs_status grow_instances(nxs_context* ctx, uint64_t m, int64_t S, hipStream_t s
   return NXS_OK;
 }
 
+}  // namespace
+
+// After the context's work: instance buffers for `need` instances (a pipeline
+// grows every lane to what one of them needed).
+nxs_status nxs::grow_instance_capacity(nxs_context* ctx, uint64_t need) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (ctx->has_done) HIP_TRY(hipEventSynchronize(ctx->done));
+  if (need == 0 || need >= 0xFFFFFFFFull || need <= instance_capacity(ctx)) return NXS_OK;
+  return grow_instances(ctx, need, ctx->last_slots, nullptr);
+}
+
+namespace {
+
 // Records ctx->done on `s` when it goes out of scope once work has been
 // enqueued (so that the next call on any stream orders after a failed one).
 struct DoneGuard {

@@ -285,4 +285,8 @@ size_t peak_fma_out_floats(int groups);
 void launch_peak_fma(float* out, int groups, int iters, hipStream_t s);
 void launch_peak_copy(const float4* src, float4* dst, int64_t n4, hipStream_t s);
 
+// Waits for the context's work, then grows its instance buffers to `need`
+// instances (api.hip; a pipeline grows every lane to what one of them needed).
+nxs_status grow_instance_capacity(nxs_context* ctx, uint64_t need);
+
 }  // namespace nxs

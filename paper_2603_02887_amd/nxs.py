@@ -30,12 +30,15 @@ SYMBOLS = ["nxs_create", "nxs_destroy", "nxs_render_forward", "nxs_render_backwa
            "nxs_server_submit", "nxs_server_step", "nxs_server_pending",
            "nxs_server_in_flight", "nxs_server_workspace_bytes", "nxs_server_last_error",
            "nxs_last_error",
+           "nxs_pipeline_create", "nxs_pipeline_destroy", "nxs_pipeline_render",
+           "nxs_pipeline_join", "nxs_pipeline_status", "nxs_pipeline_last_error",
            "nxs_measure_peaks",
            "nxs_set_timing", "nxs_inspect_stage_times", "nxs_inspect_counts",
            "nxs_inspect_instances", "nxs_inspect_ranges", "nxs_inspect_projection",
            "nxs_inspect_slot_grads"]
 # entry points that do not return an nxs_status
 _NOT_STATUS = {"nxs_last_error": ctypes.c_char_p, "nxs_server_last_error": ctypes.c_char_p,
+               "nxs_pipeline_last_error": ctypes.c_char_p,
                "nxs_server_pending": c_int32, "nxs_server_in_flight": c_int32}
 
 
@@ -132,6 +135,14 @@ def lib():
                                       POINTER(c_int32)]
         L.nxs_server_pending.argtypes = [c_void_p]
         L.nxs_server_last_error.argtypes = [c_void_p]
+        L.nxs_pipeline_create.argtypes = [POINTER(c_void_p), ctypes.c_int, c_int32, ALLOC_FN,
+                                          FREE_FN, c_void_p]
+        L.nxs_pipeline_destroy.argtypes = [c_void_p]
+        L.nxs_pipeline_render.argtypes = [c_void_p, POINTER(Gaussians), POINTER(Camera),
+                                          c_int32, POINTER(RenderOpts), POINTER(Image), c_void_p]
+        L.nxs_pipeline_join.argtypes = [c_void_p, c_void_p]
+        L.nxs_pipeline_status.argtypes = [c_void_p, POINTER(c_int64)]
+        L.nxs_pipeline_last_error.argtypes = [c_void_p]
         L.nxs_last_error.argtypes = [c_void_p]
         L.nxs_last_error.restype = ctypes.c_char_p
         L.nxs_set_timing.argtypes = [c_void_p, c_int32]
@@ -577,6 +588,71 @@ class Renderer:
         self._check(self._L.nxs_inspect_projection(self._ctx, int(view), d.ctypes.data,
                                                    r.ctypes.data, max(n, 1)))
         return d[:n], r[:4 * n].reshape(n, 4)
+
+
+class Pipeline:
+    """Renders dealt in turn to `lanes` contexts on streams of their own
+    (nxs_pipeline_*): consecutive renders overlap on the device.  render()
+    returns its outputs, complete once join() has made a stream wait for the
+    lanes and that stream has reached the join; renders in flight at the same
+    time need distinct outputs."""
+
+    def __init__(self, device=0, lanes=3, allocator="torch"):
+        self._L = lib()
+        self._p = c_void_p()
+        self.device = torch.device("cuda", int(device))
+        self._alloc = TorchAllocator(self.device) if allocator == "torch" else None
+        a = (self._alloc.alloc_cb, self._alloc.free_cb) if self._alloc else (ALLOC_FN(), FREE_FN())
+        st = self._L.nxs_pipeline_create(byref(self._p), int(device), int(lanes), a[0], a[1], None)
+        if st != 0:
+            raise NxsError(st, "nxs_pipeline_create failed")
+
+    def close(self):
+        if self._p:
+            self._L.nxs_pipeline_destroy(self._p)
+            self._p = c_void_p()
+            if self._alloc is not None:
+                self._alloc.drain()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            msg = self._L.nxs_pipeline_last_error(self._p)
+            raise NxsError(st, msg.decode() if msg else "")
+
+    def render(self, g, cams, model=0, outputs=None, stream=None, background=(0.0, 0.0, 0.0),
+               alpha_min=0.0, t_eps=0.0, tile=(16, 16), lds_batch=0, overdraw=True, param=0.0,
+               schedule=0, deferred=True, sort_order=0, instance_hint=0.0):
+        gs = _make_gaussians(g)
+        V = len(cams)
+        carr = (Camera * V)(*[make_camera(c) for c in cams])
+        outputs = _make_outputs(self.device, cams, outputs, overdraw)
+        imgs = (Image * V)(*[_make_image(o) for o in outputs])
+        opts = _make_opts(model, background, alpha_min, t_eps, tile, lds_batch, param,
+                          schedule, deferred, instance_hint, sort_order)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._check(self._L.nxs_pipeline_render(self._p, byref(gs), carr, V, byref(opts), imgs,
+                                                c_void_p(stream.cuda_stream)))
+        return outputs
+
+    def join(self, stream=None):
+        """Make `stream` (default: the current one) wait for every render so far."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._check(self._L.nxs_pipeline_join(self._p, c_void_p(stream.cuda_stream)))
+
+    def status(self):
+        """nxs_pipeline_status: raises NxsError(NXS_ECAPACITY) if a deferred
+        render outgrew its lane (render it again); returns the largest count."""
+        need = c_int64()
+        self._check(self._L.nxs_pipeline_status(self._p, byref(need)))
+        return need.value
 
 
 class Server:

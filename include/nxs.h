@@ -441,6 +441,7 @@ const char* nxs_server_last_error(const nxs_server* server);
  *     once one of its own renders has needed them.)  needed (may be NULL):
  *     the largest instance count needed.
  *   nxs_pipeline_destroy: waits for the lanes, then frees them.
+ * A pipeline is used by one host thread at a time.
  * ------------------------------------------------------------------------- */
 typedef struct nxs_pipeline nxs_pipeline;
 

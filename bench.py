@@ -70,11 +70,11 @@ HBM_PEAK_GBS = 8000.0
 # size (profiles/forward_hbm_traffic_scene1m_1080p.md).  They describe the
 # kernel sources with this digest and are reported as null once those change.
 TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_stage.h", "nxs_internal.h")
-TRAFFIC = {"digest": "811972389476b60cf8497713fc34d9ec27c40b1b303bb8b4a3726a1d0b974c09",
+TRAFFIC = {"digest": "4dbd297174eaaed7865081fbd6d73b76f50b9775b3666197a56c27f04d2d49aa",
            "tile": "16x16",
            "bytes": {
-               "queue": {0: 483835904, 1: 252552391, 2: 283843232, 3: 238860959},
-               "tiles": {0: 224983339, 1: 131538891, 2: 145888652, 3: 127188017}}}
+               "queue": {0: 487081423, 1: 254261412, 2: 288009129, 3: 241029830},
+               "tiles": {0: 225159099, 1: 131651750, 2: 145883997, 3: 127228212}}}
 
 
 def measured_traffic(model, tile, schedule):

@@ -162,20 +162,32 @@ __device__ __forceinline__ void sh_colour(const float* sh, float dx, float dy, f
   rgb[2] = b > 0.0f ? b : 0.0f;
 }
 
+// A wave's reduction under an associative, commutative op (every lane active):
+// within each 16-lane row by four DPP row shifts (a lane whose source lies
+// before its row combines the identity), then the four rows' last lanes,
+// read by readlane; the result is the same on every lane.
+template <typename Op>
+__device__ __forceinline__ uint32_t wave_reduce_u32(uint32_t x, uint32_t identity, Op op) {
+  const int id = (int)identity;
+  uint32_t v = x;
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x111, 0xF, 0xF, false));
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x112, 0xF, 0xF, false));
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x114, 0xF, 0xF, false));
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x118, 0xF, 0xF, false));
+  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+  const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+  return op(op(r0, r1), op(r2, r3));
+}
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  return wave_reduce_u32(x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
 }
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, 64));
-  return x;
+  return wave_reduce_u32(x, 0xFFFFFFFFu, [](uint32_t a, uint32_t b) { return min(a, b); });
 }
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o, 64));
-  return x;
+  return wave_reduce_u32(x, 0u, [](uint32_t a, uint32_t b) { return max(a, b); });
 }
 
 // One work-group of NT threads folds the per-block partials into the counters

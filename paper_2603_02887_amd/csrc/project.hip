@@ -218,12 +218,16 @@ __device__ void fold_partials(const uint4* partials, int nblocks, Counters* c,
       mx = max(mx, p[q].z);
     }
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    tot += __shfl_xor(tot, o, 64);
-    mn = min(mn, (uint32_t)__shfl_xor(mn, o, 64));
-    mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+  // (the 64-bit total as three 32-bit wave sums that cannot overflow: its
+  // high word and the two 16-bit halves of its low word)
+  {
+    const uint32_t lo = (uint32_t)tot;
+    const uint32_t hi = wave_sum_u32((uint32_t)(tot >> 32));
+    const uint32_t l1 = wave_sum_u32(lo >> 16), l0 = wave_sum_u32(lo & 0xFFFFu);
+    tot = ((unsigned long long)hi << 32) + ((unsigned long long)l1 << 16) + l0;
   }
+  mn = wave_min_u32(mn);
+  mx = wave_max_u32(mx);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
     s_tot[wid] = tot;

@@ -231,7 +231,9 @@ __global__ __launch_bounds__(kScanBlock) void emit_kernel(
       while (runs) {
         const int b = __builtin_ctzll(runs);
         runs &= runs - 1;
-        const uint32_t ba = __shfl(a, b, 64), be = __shfl(e, b, 64);
+        // (b is the same on every lane: the bounds come by readlane)
+        const uint32_t ba = (uint32_t)__builtin_amdgcn_readlane((int)a, b);
+        const uint32_t be = (uint32_t)__builtin_amdgcn_readlane((int)e, b);
         const uint16_t bk = (uint16_t)(k - lane + b);
         for (uint32_t j = max(ba, w0) + lane; j < min(be, w1); j += 64) s_owner[j - w0] = bk;
       }

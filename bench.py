@@ -73,8 +73,8 @@ TRAFFIC_SOURCES = ("composite.hip", "nxs_ops.h", "nxs_stage.h", "nxs_internal.h"
 TRAFFIC = {"digest": "4dbd297174eaaed7865081fbd6d73b76f50b9775b3666197a56c27f04d2d49aa",
            "tile": "16x16",
            "bytes": {
-               "queue": {0: 487081423, 1: 254261412, 2: 288009129, 3: 241029830},
-               "tiles": {0: 225159099, 1: 131651750, 2: 145883997, 3: 127228212}}}
+               "queue": {0: 485824065, 1: 253662114, 2: 287820851, 3: 240616214},
+               "tiles": {0: 225022077, 1: 131614891, 2: 145831234, 3: 127215006}}}
 
 
 def measured_traffic(model, tile, schedule):

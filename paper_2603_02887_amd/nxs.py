@@ -595,7 +595,10 @@ class Pipeline:
     (nxs_pipeline_*): consecutive renders overlap on the device.  render()
     returns its outputs, complete once join() has made a stream wait for the
     lanes and that stream has reached the join; renders in flight at the same
-    time need distinct outputs."""
+    time need distinct outputs.  A lane has no instance buffers before its
+    first render: a waiting render (deferred=False) sizes it, else status()
+    reports the deferred render that outgrew it (every lane then grows, and
+    the render succeeds when repeated)."""
 
     def __init__(self, device=0, lanes=3, allocator="torch"):
         self._L = lib()

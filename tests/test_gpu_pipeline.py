@@ -104,3 +104,30 @@ def test_pipeline_outgrown_render_is_reported_and_rendered_again():
     finally:
         P.close()
         R.close()
+
+
+@pytest.mark.timeout(300)
+def test_pipeline_of_one_and_of_eight_lanes():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2603_02887_amd import nxs
+    sc, cams = synth.tiny_scene(seed=2, n=2048)
+    g = nxs.scene_to_device(sc)
+    R = nxs.Renderer(0)
+    try:
+        ref = R.render(g, cams, model=3)
+        torch.cuda.synchronize()
+        for lanes in (1, 8):
+            print("case: %d lane(s)" % lanes, flush=True)
+            P = nxs.Pipeline(0, lanes=lanes)
+            try:
+                outs = [P.render(g, cams, model=3, deferred=False) for _ in range(lanes + 2)]
+                P.join()
+                torch.cuda.synchronize()
+                assert P.status() == 0
+                for o in outs:
+                    _same(o[0], ref[0])
+            finally:
+                P.close()
+    finally:
+        R.close()

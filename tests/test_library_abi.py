@@ -66,3 +66,27 @@ def test_state_and_status_entry_points_reject_null_context(lib):
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_void_p] * nargs
         assert f(*([None] * nargs)) == -1, name
+
+
+def test_pipeline_entry_points_check_arguments_without_gpu(lib):
+    create = lib.nxs_pipeline_create
+    create.restype = ctypes.c_int
+    create.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int32, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_void_p]
+    out = ctypes.c_void_p()
+    assert create(None, 0, 3, None, None, None) == -1
+    for lanes in (0, -1, 9):                 # lanes in 1..8
+        assert create(ctypes.byref(out), 0, lanes, None, None, None) == -1
+        assert not out.value
+    # an allocator needs both callbacks
+    assert create(ctypes.byref(out), 0, 2, ctypes.c_void_p(1), None, None) == -1
+    assert not out.value
+    for name, nargs in (("nxs_pipeline_destroy", 1), ("nxs_pipeline_render", 7),
+                        ("nxs_pipeline_join", 2), ("nxs_pipeline_status", 2)):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p] * nargs
+        assert f(*([None] * nargs)) == -1, name
+    lib.nxs_pipeline_last_error.restype = ctypes.c_char_p
+    lib.nxs_pipeline_last_error.argtypes = [ctypes.c_void_p]
+    assert lib.nxs_pipeline_last_error(None) == b"null pipeline"
